@@ -1,0 +1,177 @@
+// Device-side building blocks shared by the gfx950 kernels: complex
+// arithmetic, the exponential-of-semicircle (ES) kernel, and an LDS-resident
+// mixed radix-2/4/8 decimation-in-time FFT used by every transform pass.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfb {
+
+constexpr int kThreads = 256;   // every kernel runs 4 wave64 per workgroup
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cplx {
+    R re, im;
+};
+
+template <typename R> __device__ __forceinline__ cplx<R> mk(R a, R b) { return cplx<R>{a, b}; }
+template <typename R> __device__ __forceinline__ cplx<R> operator+(cplx<R> a, cplx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __device__ __forceinline__ cplx<R> operator-(cplx<R> a, cplx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> __device__ __forceinline__ cplx<R> operator*(cplx<R> a, cplx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ cplx<R> operator*(cplx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <typename R> __device__ __forceinline__ cplx<R> conj(cplx<R> a) { return {a.re, -a.im}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename R, bool INV> __device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) {
+    return INV ? cplx<R>{-a.im, a.re} : cplx<R>{a.im, -a.re};
+}
+
+__device__ __forceinline__ float  dev_exp(float x)  { return expf(x); }
+__device__ __forceinline__ double dev_exp(double x) { return exp(x); }
+__device__ __forceinline__ float  dev_sqrt(float x)  { return sqrtf(x); }
+__device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float  dev_floor(float x)  { return floorf(x); }
+__device__ __forceinline__ double dev_floor(double x) { return floor(x); }
+__device__ __forceinline__ void dev_sincospi(float x, float *s, float *c) { sincospif(x, s, c); }
+__device__ __forceinline__ void dev_sincospi(double x, double *s, double *c) { sincospi(x, s, c); }
+
+// exp(2 pi i t) for t in cycles (t already small in magnitude)
+template <typename R> __device__ __forceinline__ cplx<R> cis_cycles(R t) {
+    R s, c;
+    dev_sincospi(R(2) * t, &s, &c);
+    return {c, s};
+}
+
+// ES kernel phi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1)) on |z| < W/2, zero outside
+// (Barnett, Magland & af Klinteberg 2019).  inv_hw = 2/W.
+template <typename R> __device__ __forceinline__ R es_kernel(R z, R beta, R inv_hw) {
+    R t = z * inv_hw;
+    R a = R(1) - t * t;
+    return a > R(0) ? dev_exp(beta * (dev_sqrt(a) - R(1))) : R(0);
+}
+
+// ---------------------------------------------------------------------------
+// LDS FFT
+// ---------------------------------------------------------------------------
+// Padding of LDS indices to spread power-of-two strides over banks.
+template <typename R> struct LdsPad { static constexpr int SH = sizeof(R) == 4 ? 3 : 4; };
+template <typename R> __device__ __forceinline__ int lpad(int p) { return p + (p >> LdsPad<R>::SH); }
+template <typename R> __host__ __device__ constexpr int lds_len(int L) { return L + (L >> LdsPad<R>::SH); }
+
+// Radix plan for L = 2^LOG2L: first stage of radix 2^(LOG2L % 3) (if non-zero), then radix 8.
+template <int LOG2L> struct FftPlan {
+    static constexpr int L = 1 << LOG2L;
+    static constexpr int REM = LOG2L % 3;
+    static constexpr int NSTAGE = LOG2L / 3 + (REM ? 1 : 0);
+    static __host__ __device__ constexpr int radix(int st) { return (REM && st == 0) ? (1 << REM) : 8; }
+};
+
+// Position in LDS of input element n for the in-place DIT sequence (mixed-radix digit reversal).
+template <int LOG2L> __device__ __forceinline__ int dit_pos(int n) {
+    using P = FftPlan<LOG2L>;
+    int pos = 0, M = P::L, x = n;
+#pragma unroll
+    for (int st = P::NSTAGE - 1; st >= 0; --st) {
+        const int R = P::radix(st);
+        M /= R;
+        pos += (x % R) * M;
+        x /= R;
+    }
+    return pos;
+}
+
+template <typename R, bool INV> __device__ __forceinline__ void dft2(cplx<R> *v) {
+    cplx<R> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+}
+template <typename R, bool INV> __device__ __forceinline__ void dft4(cplx<R> *v) {
+    cplx<R> s02 = v[0] + v[2], d02 = v[0] - v[2];
+    cplx<R> s13 = v[1] + v[3], d13 = mul_mi<R, INV>(v[1] - v[3]);
+    v[0] = s02 + s13;
+    v[2] = s02 - s13;
+    v[1] = d02 + d13;
+    v[3] = d02 - d13;
+}
+template <typename R, bool INV> __device__ __forceinline__ void dft8(cplx<R> *v) {
+    const R h = R(0.70710678118654752440084436210485);
+    cplx<R> e[4] = {v[0], v[2], v[4], v[6]};
+    cplx<R> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<R, INV>(e);
+    dft4<R, INV>(o);
+    // w8^k for k = 1,2,3 (forward: exp(-2 pi i k / 8))
+    cplx<R> o1 = INV ? cplx<R>{h * (o[1].re - o[1].im), h * (o[1].re + o[1].im)}
+                     : cplx<R>{h * (o[1].re + o[1].im), h * (o[1].im - o[1].re)};
+    cplx<R> o2 = mul_mi<R, INV>(o[2]);
+    cplx<R> o3 = INV ? cplx<R>{-h * (o[3].re + o[3].im), h * (o[3].re - o[3].im)}
+                     : cplx<R>{h * (o[3].im - o[3].re), -h * (o[3].re + o[3].im)};
+    v[0] = e[0] + o[0];
+    v[4] = e[0] - o[0];
+    v[1] = e[1] + o1;
+    v[5] = e[1] - o1;
+    v[2] = e[2] + o2;
+    v[6] = e[2] - o2;
+    v[3] = e[3] + o3;
+    v[7] = e[3] - o3;
+}
+template <typename R, bool INV, int RAD> __device__ __forceinline__ void dft_small(cplx<R> *v) {
+    if constexpr (RAD == 2) dft2<R, INV>(v);
+    else if constexpr (RAD == 4) dft4<R, INV>(v);
+    else dft8<R, INV>(v);
+}
+
+// twiddle exp(-+2 pi i e / Lmax) from the forward table of length Lmax
+template <typename R, bool INV> __device__ __forceinline__ cplx<R> twiddle(const cplx<R> *tw, int e) {
+    cplx<R> w = tw[e];
+    return INV ? conj(w) : w;
+}
+
+// One DIT stage of radix RAD at span m over C vectors stored at buf + c*ld.
+template <typename R, bool INV, int RAD, int LOG2L>
+__device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, const cplx<R> *tw, int tw_shift) {
+    constexpr int L = 1 << LOG2L;
+    constexpr int NB = L / RAD;               // butterflies per vector
+    const int total = NB * C;
+    // table index step for w_{RAD m}^{t j}: Lmax / (RAD m) = (Lmax / L) * (L / (RAD m))
+    const int estep = (L / (RAD * m)) << tw_shift;
+    for (int id = threadIdx.x; id < total; id += kThreads) {
+        const int c = id / NB;
+        const int bfly = id - c * NB;
+        const int j = bfly % m;
+        const int g = bfly / m;
+        const int base = g * RAD * m + j;
+        cplx<R> *vb = buf + c * ld;
+        cplx<R> v[RAD];
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) v[t] = vb[lpad<R>(base + t * m)];
+        if (m > 1) {
+#pragma unroll
+            for (int t = 1; t < RAD; ++t) v[t] = v[t] * twiddle<R, INV>(tw, t * j * estep);
+        }
+        dft_small<R, INV, RAD>(v);
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) vb[lpad<R>(base + t * m)] = v[t];
+    }
+}
+
+// Full in-place FFT of C vectors of length 2^LOG2L already loaded in DIT order.
+// Ends with a barrier; the result is in natural order at lpad(k).
+template <typename R, bool INV, int LOG2L>
+__device__ __forceinline__ void lds_fft(cplx<R> *buf, int C, int ld, const cplx<R> *tw, int tw_shift) {
+    using P = FftPlan<LOG2L>;
+    int m = 1;
+#pragma unroll
+    for (int st = 0; st < P::NSTAGE; ++st) {
+        constexpr int dummy = 0;
+        (void)dummy;
+        const int RAD = P::radix(st);
+        if (RAD == 2) dit_stage<R, INV, 2, LOG2L>(buf, C, ld, m, tw, tw_shift);
+        else if (RAD == 4) dit_stage<R, INV, 4, LOG2L>(buf, C, ld, m, tw, tw_shift);
+        else dit_stage<R, INV, 8, LOG2L>(buf, C, ld, m, tw, tw_shift);
+        m *= RAD;
+        __syncthreads();
+    }
+}
+
+}  // namespace pfb

@@ -1,0 +1,996 @@
+// Host side of the C ABI: plan creation (validation, w-range analysis,
+// bucket counting, work lists, correction and twiddle tables, workspace
+// layout) and the operator entry points, which only enqueue kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pfb.h"
+#include "pfb_kernels.h"
+
+using namespace pfb;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+pfb_status fail(pfb_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_OK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t _e = (expr);                                                          \
+        if (_e != hipSuccess)                                                            \
+            return fail(PFB_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e));       \
+    } while (0)
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+ColSplit make_split(int n) {
+    ColSplit c;
+    const int lg = ilog2(n);
+    if (lg <= 9) {
+        c.n1 = n;
+        c.n2 = 1;
+        c.log2n1 = lg;
+        c.log2n2 = 0;
+    } else {
+        c.log2n1 = (lg + 1) / 2;
+        c.log2n2 = lg / 2;
+        c.n1 = 1 << c.log2n1;
+        c.n2 = 1 << c.log2n2;
+    }
+    return c;
+}
+
+// ---- Fourier transform of the ES kernel --------------------------------------
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) {
+                x[i] = z;
+                w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+                break;
+            }
+            x[i] = z;
+            w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        }
+    }
+}
+
+// psi_hat(xi) = int phi(x) exp(2 pi i x xi) dx over |x| < W/2, with x = (W/2) sin(theta)
+// removing the square-root edge of the ES kernel so the quadrature converges fast.
+struct PsiHat {
+    int W;
+    double beta;
+    std::vector<double> th, wt;
+    PsiHat(int W_, double beta_) : W(W_), beta(beta_) {
+        std::vector<double> x, w;
+        gauss_legendre(160, x, w);
+        th.resize(x.size());
+        wt.resize(x.size());
+        for (size_t k = 0; k < x.size(); ++k) {
+            th[k] = 0.25 * M_PI * (x[k] + 1.0);
+            wt[k] = 0.25 * M_PI * w[k];
+        }
+    }
+    double operator()(double xi) const {
+        double s = 0.0;
+        for (size_t k = 0; k < th.size(); ++k)
+            s += wt[k] * std::exp(beta * (std::cos(th[k]) - 1.0)) * std::cos(M_PI * W * xi * std::sin(th[k])) *
+                 std::cos(th[k]);
+        return W * s;
+    }
+};
+
+// Chebyshev coefficients of psi_hat in y = 2 (xi / xi_max)^2 - 1.
+std::vector<double> psihat_chebyshev(const PsiHat &f, double xi_max, int K, double *max_rel_err) {
+    std::vector<double> fk(K), c(K);
+    for (int k = 0; k < K; ++k) {
+        const double y = std::cos(M_PI * (k + 0.5) / K);
+        fk[k] = f(xi_max * std::sqrt(0.5 * (y + 1.0)));
+    }
+    for (int j = 0; j < K; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) s += fk[k] * std::cos(M_PI * j * (k + 0.5) / K);
+        c[j] = 2.0 * s / K;
+    }
+    c[0] *= 0.5;
+    double err = 0.0;
+    for (int t = 0; t <= 200; ++t) {
+        const double xi = xi_max * t / 200.0;
+        const double y = 2.0 * (xi / xi_max) * (xi / xi_max) - 1.0;
+        double b1 = 0, b2 = 0;
+        for (int k = K - 1; k >= 1; --k) {
+            const double b0 = c[k] + 2.0 * y * b1 - b2;
+            b2 = b1;
+            b1 = b0;
+        }
+        const double v = c[0] + y * b1 - b2;
+        const double ref = f(xi);
+        err = std::max(err, std::fabs(v - ref) / std::fabs(ref));
+    }
+    *max_rel_err = err;
+    return c;
+}
+
+// ---- workspace layout --------------------------------------------------------
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+}  // namespace
+
+// One NUFFT configuration (main w-stacked operator or the flat PSF gridder).
+struct GridderHost {
+    GeomDev g{};
+    ColSplit cs{};
+    std::vector<BandDev> bands;
+    std::vector<int64_t> offsets;        // n_band * ntiles * nj0max + 1
+    std::vector<GridWork> gwork;
+    std::vector<InterpWork> iwork;
+    std::vector<int> gband_start, iband_start;  // per band first work item (n_band + 1)
+    int64_t n_entries = 0;
+    // workspace offsets
+    size_t o_bands = 0, o_offsets = 0, o_cursor = 0, o_gwork = 0, o_iwork = 0, o_recs = 0, o_omega = 0;
+    size_t o_corr2d = 0, o_corrx = 0, o_corry = 0;
+    bool corr2d = true;
+    // device pointers (valid after set_workspace)
+    BandDev *d_bands = nullptr;
+    int64_t *d_offsets = nullptr;
+    unsigned long long *d_cursor = nullptr;
+    GridWork *d_gwork = nullptr;
+    InterpWork *d_iwork = nullptr;
+    void *d_recs = nullptr, *d_omega = nullptr, *d_corr2d = nullptr, *d_corrx = nullptr, *d_corry = nullptr;
+    int64_t keys() const { return (int64_t)g.n_band * g.ntx * g.nty * g.nj0max; }
+};
+
+struct pfb_plan {
+    pfb_problem prob{};
+    pfb_options opt{};
+    bool dbl = false;
+    size_t rsz = 4;
+    std::vector<int32_t> chan_band;
+    std::vector<double> freq;
+    GridderHost main, psf;
+    int64_t n_active = 0, n_flagged = 0;
+    double s_min = 0.0;
+    int band_batch = 1;
+    ColSplit ccs{};
+    int ldh = 0;
+    int log2_lmax = 0;
+    std::vector<double> cheb;
+    double xi_max = 0.25;
+    std::vector<double> tw_host;   // interleaved (re, im) float64
+    std::vector<float> tw_f32;     // staging copies that outlive asynchronous uploads
+    std::vector<int> cb_host;
+    int max_partials = 0;
+    // workspace
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+    bool ws_ready = false, psf_ready = false;
+    size_t o_freq = 0, o_cb = 0, o_cheb = 0, o_tw = 0, o_flagged = 0, o_flagcur = 0;
+    size_t o_planes = 0, o_t1 = 0, o_t2 = 0, o_vals = 0, o_psfimg = 0;
+    size_t o_t1c = 0, o_t2c = 0, o_psfhat = 0, o_vec = 0, o_partials = 0, o_scal = 0;
+    size_t planes_bytes = 0, t_bytes = 0, vec_bytes = 0;
+    void *p(size_t off) const { return ws + off; }
+};
+
+namespace {
+
+GeomDev base_geom(const pfb_plan &P, int nx, int ny, bool flat) {
+    GeomDev g{};
+    g.nx = nx;
+    g.ny = ny;
+    g.gx = 2 * nx;
+    g.gy = 2 * ny;
+    g.T = P.opt.tile;
+    g.ntx = g.gx / g.T;
+    g.nty = g.gy / g.T;
+    g.W = P.opt.support;
+    g.n_band = P.prob.n_band;
+    g.flat = flat ? 1 : 0;
+    g.cellx = P.prob.cellx;
+    g.celly = P.prob.celly;
+    g.beta = 2.30 * g.W;
+    return g;
+}
+
+// Work lists from the per-(band, tile, base plane) counts.
+void build_work(GridderHost &G, const std::vector<unsigned> &counts, int chunk) {
+    const GeomDev &g = G.g;
+    const int ntiles = g.ntx * g.nty;
+    const int W = g.flat ? 1 : g.W;
+    G.gwork.clear();
+    G.iwork.clear();
+    G.gband_start.assign(g.n_band + 1, 0);
+    G.iband_start.assign(g.n_band + 1, 0);
+    std::vector<std::pair<int64_t, GridWork>> gw;
+    std::vector<std::pair<int64_t, InterpWork>> iw;
+    for (int b = 0; b < g.n_band; ++b) {
+        const BandDev &bd = G.bands[b];
+        gw.clear();
+        iw.clear();
+        for (int t = 0; t < ntiles; ++t) {
+            const int64_t kb = ((int64_t)b * ntiles + t) * g.nj0max;
+            const unsigned *c = counts.data() + kb;
+            int64_t tot = 0;
+            for (int q = 0; q < bd.nj0; ++q) tot += c[q];
+            // spread items: split the plane range so each item sees <= chunk entries
+            const int nw = bd.nw;
+            int p0 = 0;
+            while (p0 < nw) {
+                int p1 = p0 + 1;
+                auto cost = [&](int a0, int a1) {
+                    int64_t s = 0;
+                    for (int q = std::max(0, a0 - W + 1); q < std::min(a1, bd.nj0); ++q) s += c[q];
+                    return s;
+                };
+                while (p1 < nw && cost(p0, p1 + 1) <= chunk) ++p1;
+                gw.push_back({cost(p0, p1) * (int64_t)W + 1, GridWork{b, t, p0, p1}});
+                p0 = p1;
+            }
+            // interpolation items: runs of <= chunk entries
+            int64_t e = G.offsets[kb];
+            const int64_t eend = e + tot;
+            int q = 0;
+            int64_t qend = G.offsets[kb] + c[0];
+            while (e < eend) {
+                while (e >= qend) qend += c[++q];
+                const int64_t e1 = std::min(eend, e + chunk);
+                int q1 = q;
+                int64_t qe = qend;
+                while (e1 > qe) qe += c[++q1];
+                iw.push_back({e1 - e, InterpWork{b, t, (int)e, (int)e1, q, q1}});
+                e = e1;
+            }
+        }
+        std::stable_sort(gw.begin(), gw.end(), [](auto &a, auto &b) { return a.first > b.first; });
+        std::stable_sort(iw.begin(), iw.end(), [](auto &a, auto &b) { return a.first > b.first; });
+        for (auto &x : gw) G.gwork.push_back(x.second);
+        for (auto &x : iw) G.iwork.push_back(x.second);
+        G.gband_start[b + 1] = (int)G.gwork.size();
+        G.iband_start[b + 1] = (int)G.iwork.size();
+    }
+}
+
+pfb_status check_ready(const pfb_plan *P) {
+    if (!P) return fail(PFB_EINVAL, "plan is NULL");
+    if (!P->ws_ready) return fail(PFB_ESTATE, "pfb_plan_set_workspace has not been called");
+    return PFB_OK;
+}
+
+XformArgs xform_args(const pfb_plan *P, const GridderHost &G, int b0, int nbb) {
+    XformArgs a{};
+    a.g = G.g;
+    a.bands = G.d_bands;
+    a.band0 = b0;
+    a.n_bb = nbb;
+    a.cs = G.cs;
+    a.tw = P->p(P->o_tw);
+    a.log2_lmax = P->log2_lmax;
+    a.planes = P->p(P->o_planes);
+    a.t1 = P->p(P->o_t1);
+    a.t2 = P->p(P->o_t2);
+    a.corr2d = G.corr2d ? G.d_corr2d : nullptr;
+    a.corr_x = G.d_corrx;
+    a.corr_y = G.d_corry;
+    return a;
+}
+
+ConvArgs conv_args(const pfb_plan *P) {
+    ConvArgs a{};
+    a.n_band = P->prob.n_band;
+    a.nx = P->prob.nx;
+    a.ny = P->prob.ny;
+    a.ldh = P->ldh;
+    a.cs = P->ccs;
+    a.tw = P->p(P->o_tw);
+    a.log2_lmax = P->log2_lmax;
+    a.t1c = P->p(P->o_t1c);
+    a.t2c = P->p(P->o_t2c);
+    a.psfhat = P->p(P->o_psfhat);
+    a.partials = reinterpret_cast<double *>(P->p(P->o_partials));
+    a.max_partials = P->max_partials;
+    a.scal = reinterpret_cast<double *>(P->p(P->o_scal));
+    return a;
+}
+
+SpreadLaunch spread_args(const GridderHost &G, int b0, int nbb, int vmode, const void *vis, void *planes) {
+    SpreadLaunch s{};
+    s.g = G.g;
+    s.bands = G.d_bands;
+    s.work = G.d_gwork + G.gband_start[b0];
+    s.n_work = G.gband_start[b0 + nbb] - G.gband_start[b0];
+    s.offsets = G.d_offsets;
+    s.recs = G.d_recs;
+    s.omega = G.d_omega;
+    s.vis = vis;
+    s.planes = planes;
+    s.band0 = b0;
+    s.vmode = vmode;
+    return s;
+}
+
+InterpLaunch interp_args(const GridderHost &G, int b0, int nbb, int omode, const void *planes, void *out) {
+    InterpLaunch s{};
+    s.g = G.g;
+    s.bands = G.d_bands;
+    s.work = G.d_iwork + G.iband_start[b0];
+    s.n_work = G.iband_start[b0 + nbb] - G.iband_start[b0];
+    s.offsets = G.d_offsets;
+    s.recs = G.d_recs;
+    s.omega = G.d_omega;
+    s.planes = planes;
+    s.out = out;
+    s.band0 = b0;
+    s.omode = omode;
+    return s;
+}
+
+#define LAUNCH_OK(expr)                                                                  \
+    do {                                                                                 \
+        hipError_t _e = (expr);                                                          \
+        if (_e != hipSuccess)                                                            \
+            return fail(PFB_EHIP, "%s: %s", #expr, hipGetErrorString(_e));              \
+    } while (0)
+
+pfb_status cg_solve(pfb_plan *P, const void *g, void *y, double sigma, int iters, hipStream_t s) {
+    const bool d = P->dbl;
+    ConvArgs ca = conv_args(P);
+    const int nb = P->prob.n_band;
+    const int64_t Pn = (int64_t)P->prob.nx * P->prob.ny;
+    char *v = reinterpret_cast<char *>(P->p(P->o_vec));
+    void *r = v, *p = v + P->vec_bytes, *ap = v + 2 * P->vec_bytes;
+    const int vparts = vec_partials_per_band(Pn);
+    const int cparts = conv_partials_per_band(d, ca);
+    LAUNCH_OK(launch_vec(d, VEC_CG_INIT, nb, Pn, ca.partials, ca.max_partials, ca.scal, const_cast<void *>(g), y, r,
+                         p, nullptr, 0, 0, s));
+    LAUNCH_OK(launch_reduce(RED_SET_RR, nb, ca.partials, vparts, ca.max_partials, ca.scal, s));
+    for (int it = 0; it < iters; ++it) {
+        LAUNCH_OK(launch_psf_conv(d, ca, r, p, ap, p, sigma, CONV_IN_CG_P, CONV_OUT_CG, s));
+        LAUNCH_OK(launch_reduce(RED_ALPHA, nb, ca.partials, cparts, ca.max_partials, ca.scal, s));
+        LAUNCH_OK(launch_vec(d, VEC_CG_UPDATE, nb, Pn, ca.partials, ca.max_partials, ca.scal, nullptr, y, r, p, ap,
+                             0, 0, s));
+        LAUNCH_OK(launch_reduce(RED_BETA, nb, ca.partials, vparts, ca.max_partials, ca.scal, s));
+    }
+    return PFB_OK;
+}
+
+pfb_status hessian_impl(pfb_plan *P, const void *x, void *y, hipStream_t s) {
+    const bool d = P->dbl;
+    GridderHost &G = P->main;
+    for (int b0 = 0; b0 < P->prob.n_band; b0 += P->band_batch) {
+        const int nbb = std::min(P->band_batch, P->prob.n_band - b0);
+        XformArgs xa = xform_args(P, G, b0, nbb);
+        xa.image_in = x;
+        xa.image_out = y;
+        LAUNCH_OK(launch_degrid_xform(d, xa, s));
+        LAUNCH_OK(launch_interp(d, interp_args(G, b0, nbb, 1, P->p(P->o_planes), P->p(P->o_vals)), s));
+        LAUNCH_OK(launch_spread(d, spread_args(G, b0, nbb, 2, P->p(P->o_vals), P->p(P->o_planes)), s));
+        LAUNCH_OK(launch_grid_xform(d, xa, s));
+    }
+    return PFB_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char *pfb_last_error(void) { return g_last_error.c_str(); }
+const char *pfb_version(void) { return "pfb-mi355x 0.1 (gfx950)"; }
+
+pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_options *opt_in, hipStream_t stream) {
+    if (!out) return fail(PFB_EINVAL, "plan output pointer is NULL");
+    *out = nullptr;
+    if (!prob) return fail(PFB_EINVAL, "problem is NULL");
+    pfb_options opt{};
+    if (opt_in) opt = *opt_in;
+    const pfb_problem &pr = *prob;
+    if (pr.n_row <= 0 || pr.n_chan <= 0 || pr.n_band <= 0)
+        return fail(PFB_EINVAL, "n_row, n_chan and n_band must be positive");
+    if (pr.n_band > pr.n_chan) return fail(PFB_EINVAL, "more bands than channels");
+    if (pr.n_row * pr.n_chan >= (int64_t(1) << 31))
+        return fail(PFB_EUNSUPPORTED, "n_row * n_chan must be below 2^31");
+    if (!pr.chan_band || !pr.freq || !pr.uvw || !pr.weight) return fail(PFB_EINVAL, "NULL array in problem");
+    if (!is_pow2(pr.nx) || !is_pow2(pr.ny) || pr.nx < 16 || pr.ny < 16)
+        return fail(PFB_EINVAL, "nx and ny must be powers of two >= 16 (got %d x %d)", pr.nx, pr.ny);
+    if (!(pr.cellx > 0) || !(pr.celly > 0) || !std::isfinite(pr.cellx) || !std::isfinite(pr.celly))
+        return fail(PFB_EINVAL, "cell sizes must be positive and finite");
+    if (opt.precision != PFB_FP32 && opt.precision != PFB_FP64) return fail(PFB_EINVAL, "unknown precision");
+    const bool dbl = opt.precision == PFB_FP64;
+    if (opt.support == 0) opt.support = dbl ? 13 : 7;
+    if (dbl ? (opt.support < 9 || opt.support > 16) : (opt.support < 4 || opt.support > 8))
+        return fail(PFB_EINVAL, "support %d outside the range compiled for this precision", opt.support);
+    if (opt.oversample == 0.0) opt.oversample = 2.0;
+    if (opt.oversample != 2.0) return fail(PFB_EUNSUPPORTED, "only oversampling 2.0 is implemented");
+    if (opt.tile == 0) opt.tile = dbl ? 8 : 32;
+    if (!is_pow2(opt.tile) || opt.tile < 8 || opt.tile > 64)
+        return fail(PFB_EINVAL, "tile must be a power of two in [8, 64]");
+    if (2 * std::min(pr.nx, pr.ny) < 2 * opt.tile) return fail(PFB_EINVAL, "tile larger than half the grid");
+    if (opt.flat != 0 && opt.flat != 1) return fail(PFB_EINVAL, "flat must be 0 or 1");
+    if (opt.chunk == 0) opt.chunk = 4096;
+    if (opt.chunk < 64) return fail(PFB_EINVAL, "chunk must be >= 64");
+    // FFT length limits (LDS-resident rows)
+    const int max_row = dbl ? 8192 : 16384;
+    if (4 * pr.nx > max_row || 4 * pr.ny > max_row)
+        return fail(PFB_EUNSUPPORTED, "image %d x %d needs FFT rows longer than %d for this precision", pr.nx, pr.ny,
+                    max_row);
+    const double lmax2 = std::pow(0.5 * pr.nx * pr.cellx, 2) + std::pow(0.5 * pr.ny * pr.celly, 2);
+    if (!opt.flat && lmax2 >= 1.0) return fail(PFB_EINVAL, "field of view reaches l^2 + m^2 >= 1");
+
+    pfb_plan *P = new pfb_plan();
+    P->prob = pr;
+    P->opt = opt;
+    P->dbl = dbl;
+    P->rsz = dbl ? 8 : 4;
+    P->chan_band.assign(pr.chan_band, pr.chan_band + pr.n_chan);
+    P->freq.assign(pr.freq, pr.freq + pr.n_chan);
+    auto bail = [&](pfb_status st) {
+        delete P;
+        return st;
+    };
+    for (int64_t c = 0; c < pr.n_chan; ++c) {
+        if (P->chan_band[c] < 0 || P->chan_band[c] >= pr.n_band) {
+            fail(PFB_EINVAL, "chan_band[%lld] = %d outside [0, %d)", (long long)c, P->chan_band[c], pr.n_band);
+            return bail(PFB_EINVAL);
+        }
+        if (!(P->freq[c] > 0) || !std::isfinite(P->freq[c])) {
+            fail(PFB_EINVAL, "freq[%lld] is not a positive finite number", (long long)c);
+            return bail(PFB_EINVAL);
+        }
+    }
+    // uvw analysis on the host
+    std::vector<double> uvw(3 * pr.n_row);
+    {
+        hipError_t e = hipMemcpy(uvw.data(), pr.uvw, uvw.size() * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            fail(PFB_EHIP, "copying uvw to the host failed: %s", hipGetErrorString(e));
+            return bail(PFB_EHIP);
+        }
+    }
+    double wlo = INFINITY, whi = -INFINITY;
+    for (int64_t r = 0; r < pr.n_row; ++r) {
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(uvw[3 * r + k])) {
+                fail(PFB_EINVAL, "uvw[%lld] is not finite", (long long)r);
+                return bail(PFB_EINVAL);
+            }
+        wlo = std::min(wlo, uvw[3 * r + 2]);
+        whi = std::max(whi, uvw[3 * r + 2]);
+    }
+    std::vector<double> fmin(pr.n_band, INFINITY), fmax(pr.n_band, 0.0);
+    for (int64_t c = 0; c < pr.n_chan; ++c) {
+        fmin[P->chan_band[c]] = std::min(fmin[P->chan_band[c]], P->freq[c]);
+        fmax[P->chan_band[c]] = std::max(fmax[P->chan_band[c]], P->freq[c]);
+    }
+
+    // geometry of the two gridders
+    GridderHost &M = P->main;
+    M.g = base_geom(*P, pr.nx, pr.ny, opt.flat != 0);
+    M.cs = make_split(M.g.gx);
+    {
+        const double r2 = lmax2;
+        P->s_min = opt.flat ? 0.0 : -r2 / (1.0 + std::sqrt(1.0 - r2));
+    }
+    M.bands.resize(pr.n_band);
+    M.g.nj0max = 1;
+    M.g.nwmax = 1;
+    for (int b = 0; b < pr.n_band; ++b) {
+        BandDev &bd = M.bands[b];
+        if (opt.flat || P->s_min == 0.0 || fmax[b] == 0.0) {
+            bd.w0 = 0.0;
+            bd.dw = 1.0;
+            bd.sc = 0.0;
+            bd.nw = 1;
+            bd.nj0 = 1;
+        } else {
+            const double s0 = fmin[b] / kC0, s1 = fmax[b] / kC0;
+            const double wmin = std::min({wlo * s0, wlo * s1, whi * s0, whi * s1});
+            const double wmax = std::max({wlo * s0, wlo * s1, whi * s0, whi * s1});
+            bd.dw = 1.0 / (2.0 * std::fabs(P->s_min));   // w oversampling 2
+            bd.sc = 0.5 * P->s_min;
+            const double D = (wmax - wmin) / bd.dw;
+            bd.nj0 = (int)std::floor(D) + 2;
+            bd.nw = bd.nj0 + opt.support - 1;
+            bd.w0 = wmin - (0.5 * opt.support - 0.5) * bd.dw;
+        }
+        M.g.nj0max = std::max(M.g.nj0max, bd.nj0);
+        M.g.nwmax = std::max(M.g.nwmax, bd.nw);
+    }
+    GridderHost &Q = P->psf;
+    Q.g = base_geom(*P, 2 * pr.nx, 2 * pr.ny, true);
+    Q.cs = make_split(Q.g.gx);
+    Q.bands.assign(pr.n_band, BandDev{0.0, 1.0, 0.0, 1, 1});
+    Q.g.nj0max = 1;
+    Q.g.nwmax = 1;
+    Q.corr2d = false;
+
+    // device count pass with a temporary buffer
+    const int64_t kM = M.keys(), kQ = Q.keys();
+    size_t tmp_bytes = 0;
+    Layout tl;
+    const size_t t_freq = tl.take(pr.n_chan * sizeof(double));
+    const size_t t_cb = tl.take(pr.n_chan * sizeof(int));
+    const size_t t_bm = tl.take(M.bands.size() * sizeof(BandDev));
+    const size_t t_bq = tl.take(Q.bands.size() * sizeof(BandDev));
+    const size_t t_cm = tl.take(kM * sizeof(unsigned));
+    const size_t t_cq = tl.take(kQ * sizeof(unsigned));
+    const size_t t_ctr = tl.take(8 * sizeof(unsigned long long));
+    tmp_bytes = tl.off;
+    char *tmp = nullptr;
+    {
+        hipError_t e = hipMalloc(&tmp, tmp_bytes);
+        if (e != hipSuccess) {
+            fail(PFB_ENOMEM, "temporary device buffer of %zu bytes: %s", tmp_bytes, hipGetErrorString(e));
+            return bail(PFB_ENOMEM);
+        }
+    }
+    std::vector<unsigned> cM(kM), cQ(kQ);
+    unsigned long long ctr[8] = {0};
+    pfb_status st = PFB_OK;
+    do {
+        hipError_t e = hipSuccess;
+        std::vector<int> cb(P->chan_band.begin(), P->chan_band.end());
+#define TMP_OK(x)                                                                    \
+    e = (x);                                                                         \
+    if (e != hipSuccess) {                                                           \
+        st = fail(PFB_EHIP, "%s: %s", #x, hipGetErrorString(e));                    \
+        break;                                                                       \
+    }
+        TMP_OK(hipMemcpyAsync(tmp + t_freq, P->freq.data(), pr.n_chan * sizeof(double), hipMemcpyHostToDevice, stream));
+        TMP_OK(hipMemcpyAsync(tmp + t_cb, cb.data(), pr.n_chan * sizeof(int), hipMemcpyHostToDevice, stream));
+        TMP_OK(hipMemcpyAsync(tmp + t_bm, M.bands.data(), M.bands.size() * sizeof(BandDev), hipMemcpyHostToDevice, stream));
+        TMP_OK(hipMemcpyAsync(tmp + t_bq, Q.bands.data(), Q.bands.size() * sizeof(BandDev), hipMemcpyHostToDevice, stream));
+        TMP_OK(hipMemsetAsync(tmp + t_cm, 0, kM * sizeof(unsigned), stream));
+        TMP_OK(hipMemsetAsync(tmp + t_cq, 0, kQ * sizeof(unsigned), stream));
+        TMP_OK(hipMemsetAsync(tmp + t_ctr, 0, 8 * sizeof(unsigned long long), stream));
+        BucketArgs ba{};
+        ba.uvw = pr.uvw;
+        ba.freq_dev = reinterpret_cast<const double *>(tmp + t_freq);
+        ba.chan_band_dev = reinterpret_cast<const int *>(tmp + t_cb);
+        ba.weight = pr.weight;
+        ba.flag = pr.flag;
+        ba.n_row = pr.n_row;
+        ba.n_chan = pr.n_chan;
+        unsigned long long *c = reinterpret_cast<unsigned long long *>(tmp + t_ctr);
+        ba.g = M.g;
+        ba.bands = reinterpret_cast<const BandDev *>(tmp + t_bm);
+        ba.counts = reinterpret_cast<unsigned *>(tmp + t_cm);
+        ba.n_active = c;
+        ba.n_flagged = c + 1;
+        ba.n_bad = c + 2;
+        TMP_OK(launch_count(dbl, ba, stream));
+        ba.g = Q.g;
+        ba.bands = reinterpret_cast<const BandDev *>(tmp + t_bq);
+        ba.counts = reinterpret_cast<unsigned *>(tmp + t_cq);
+        ba.n_active = c + 3;
+        ba.n_flagged = c + 4;
+        ba.n_bad = c + 5;
+        TMP_OK(launch_count(dbl, ba, stream));
+        TMP_OK(hipMemcpyAsync(cM.data(), tmp + t_cm, kM * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+        TMP_OK(hipMemcpyAsync(cQ.data(), tmp + t_cq, kQ * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+        TMP_OK(hipMemcpyAsync(ctr, c, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
+        TMP_OK(hipStreamSynchronize(stream));
+#undef TMP_OK
+    } while (0);
+    (void)hipFree(tmp);
+    if (st != PFB_OK) return bail(st);
+    if (ctr[2] || ctr[5]) {
+        fail(PFB_EINVAL, "%llu visibilities fell outside the planned w range", ctr[2] + ctr[5]);
+        return bail(PFB_EINVAL);
+    }
+    P->n_active = (int64_t)ctr[0];
+    P->n_flagged = (int64_t)ctr[1];
+
+    // bucket offsets and work lists
+    for (GridderHost *G : {&M, &Q}) {
+        const std::vector<unsigned> &cnt = (G == &M) ? cM : cQ;
+        G->offsets.resize(cnt.size() + 1);
+        int64_t acc = 0;
+        for (size_t k = 0; k < cnt.size(); ++k) {
+            G->offsets[k] = acc;
+            acc += cnt[k];
+        }
+        G->offsets[cnt.size()] = acc;
+        G->n_entries = acc;
+        if (acc >= (int64_t(1) << 31)) {
+            fail(PFB_EUNSUPPORTED, "%lld bucket entries exceed 2^31", (long long)acc);
+            return bail(PFB_EUNSUPPORTED);
+        }
+        build_work(*G, cnt, opt.chunk);
+    }
+
+    // grid correction: Chebyshev expansion of the ES kernel's Fourier transform
+    {
+        PsiHat ph(opt.support, M.g.beta);
+        double err = 0.0;
+        P->cheb = psihat_chebyshev(ph, P->xi_max, 40, &err);
+        if (err > 1e-13) {
+            fail(PFB_EHIP, "correction expansion error %.3g too large", err);
+            return bail(PFB_EHIP);
+        }
+    }
+    // twiddles
+    const int lmax = std::max({Q.g.gx, Q.g.gy, M.g.gx, M.g.gy});
+    P->log2_lmax = ilog2(lmax);
+    P->tw_host.resize(2 * (size_t)lmax);
+    for (int e2 = 0; e2 < lmax; ++e2) {
+        const double a = -2.0 * M_PI * (double)e2 / lmax;
+        P->tw_host[2 * e2] = std::cos(a);
+        P->tw_host[2 * e2 + 1] = std::sin(a);
+    }
+    P->ccs = make_split(2 * pr.nx);
+    P->ldh = ((pr.ny + 1 + 15) / 16) * 16;
+
+    // band batch
+    P->band_batch = opt.band_batch > 0 ? std::min(opt.band_batch, pr.n_band) : pr.n_band;
+    const size_t csz = 2 * P->rsz;
+    const size_t per_band_planes = std::max((size_t)M.g.nwmax * M.g.gx * M.g.gy, (size_t)Q.g.gx * Q.g.gy) * csz;
+    if (opt.band_batch == 0) {
+        const size_t budget = (size_t)96 << 30;   // planes + two intermediates
+        while (P->band_batch > 1 && P->band_batch * 2 * per_band_planes > budget) --P->band_batch;
+    }
+    P->opt.band_batch = P->band_batch;
+
+    // workspace layout
+    Layout L;
+    const int nb = pr.n_band;
+    const size_t Pimg = (size_t)pr.nx * pr.ny;
+    P->o_freq = L.take(pr.n_chan * sizeof(double));
+    P->o_cb = L.take(pr.n_chan * sizeof(int));
+    P->o_cheb = L.take(P->cheb.size() * sizeof(double));
+    P->o_tw = L.take((size_t)lmax * csz);
+    P->o_flagged = L.take(std::max<int64_t>(P->n_flagged, 1) * sizeof(uint32_t));
+    P->o_flagcur = L.take(sizeof(unsigned long long));
+    for (GridderHost *G : {&M, &Q}) {
+        G->o_bands = L.take(G->bands.size() * sizeof(BandDev));
+        G->o_offsets = L.take(G->offsets.size() * sizeof(int64_t));
+        G->o_cursor = L.take((G->offsets.size()) * sizeof(unsigned long long));
+        G->o_gwork = L.take(std::max<size_t>(G->gwork.size(), 1) * sizeof(GridWork));
+        G->o_iwork = L.take(std::max<size_t>(G->iwork.size(), 1) * sizeof(InterpWork));
+        G->o_recs = L.take(std::max<int64_t>(G->n_entries, 1) * (dbl ? sizeof(Rec<double>) : sizeof(Rec<float>)));
+        G->o_omega = L.take(std::max<int64_t>(G->n_entries, 1) * P->rsz);
+        if (G->corr2d) {
+            G->o_corr2d = L.take((size_t)nb * G->g.nx * G->g.ny * P->rsz);
+        } else {
+            G->o_corrx = L.take((size_t)G->g.nx * P->rsz);
+            G->o_corry = L.take((size_t)G->g.ny * P->rsz);
+        }
+    }
+    P->planes_bytes = (size_t)P->band_batch * per_band_planes;
+    P->t_bytes = (size_t)P->band_batch *
+                 std::max((size_t)M.g.nwmax * M.g.gx * M.g.ny, (size_t)Q.g.gx * Q.g.ny) * csz;
+    P->o_planes = L.take(P->planes_bytes);
+    P->o_t1 = L.take(P->t_bytes);
+    P->o_t2 = L.take(M.cs.n2 > 1 ? P->t_bytes : 256);
+    P->o_vals = L.take((size_t)pr.n_row * pr.n_chan * csz);
+    P->o_psfimg = L.take((size_t)nb * 4 * Pimg * P->rsz);
+    P->o_t1c = L.take((size_t)nb * 2 * pr.nx * P->ldh * csz);
+    P->o_t2c = L.take(P->ccs.n2 > 1 ? (size_t)nb * 2 * pr.nx * P->ldh * csz : 256);
+    P->o_psfhat = L.take((size_t)nb * 2 * pr.nx * P->ldh * P->rsz);
+    P->vec_bytes = ((Pimg * nb * P->rsz) + 255) & ~size_t(255);
+    P->o_vec = L.take(6 * P->vec_bytes);
+    {
+        ConvArgs ca{};
+        ca.nx = pr.nx;
+        ca.ny = pr.ny;
+        P->max_partials = std::max(vec_partials_per_band((int64_t)Pimg), conv_partials_per_band(dbl, ca));
+    }
+    P->o_partials = L.take((size_t)nb * P->max_partials * sizeof(double));
+    P->o_scal = L.take((size_t)nb * 8 * sizeof(double));
+    P->ws_bytes = L.off;
+    *out = P;
+    return PFB_OK;
+}
+
+pfb_status pfb_plan_workspace_size(const pfb_plan *P, size_t *bytes) {
+    if (!P || !bytes) return fail(PFB_EINVAL, "NULL argument");
+    *bytes = P->ws_bytes;
+    return PFB_OK;
+}
+
+pfb_status pfb_plan_get_info(const pfb_plan *P, pfb_plan_info *info) {
+    if (!P || !info) return fail(PFB_EINVAL, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->grid_x = P->main.g.gx;
+    info->grid_y = P->main.g.gy;
+    info->psf_grid_x = P->psf.g.gx;
+    info->psf_grid_y = P->psf.g.gy;
+    info->support = P->opt.support;
+    info->tile = P->opt.tile;
+    info->n_wplanes_max = P->main.g.nwmax;
+    info->band_batch = P->band_batch;
+    info->n_vis_active = P->n_active;
+    info->n_entries = P->main.n_entries;
+    info->n_psf_entries = P->psf.n_entries;
+    info->s_min = P->s_min;
+    info->es_beta = P->main.g.beta;
+    info->workspace_bytes = (int64_t)P->ws_bytes;
+    return PFB_OK;
+}
+
+pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStream_t s) {
+    if (!P) return fail(PFB_EINVAL, "plan is NULL");
+    if (!dev) return fail(PFB_ENOMEM, "workspace pointer is NULL");
+    if (bytes < P->ws_bytes) return fail(PFB_ENOMEM, "workspace of %zu bytes < required %zu", bytes, P->ws_bytes);
+    if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(PFB_EINVAL, "workspace must be 256-byte aligned");
+    P->ws = reinterpret_cast<char *>(dev);
+    P->ws_ready = false;
+    P->psf_ready = false;
+    const bool d = P->dbl;
+    const pfb_problem &pr = P->prob;
+    P->cb_host.assign(P->chan_band.begin(), P->chan_band.end());
+    HIP_OK(hipMemcpyAsync(P->p(P->o_freq), P->freq.data(), pr.n_chan * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(P->p(P->o_cb), P->cb_host.data(), pr.n_chan * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(P->p(P->o_cheb), P->cheb.data(), P->cheb.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    {
+        const size_t n = P->tw_host.size() / 2;
+        if (d) {
+            HIP_OK(hipMemcpyAsync(P->p(P->o_tw), P->tw_host.data(), n * 16, hipMemcpyHostToDevice, s));
+        } else {
+            P->tw_f32.assign(P->tw_host.begin(), P->tw_host.end());
+            HIP_OK(hipMemcpyAsync(P->p(P->o_tw), P->tw_f32.data(), n * 8, hipMemcpyHostToDevice, s));
+        }
+    }
+    HIP_OK(hipMemsetAsync(P->p(P->o_flagcur), 0, sizeof(unsigned long long), s));
+    for (GridderHost *G : {&P->main, &P->psf}) {
+        G->d_bands = reinterpret_cast<BandDev *>(P->p(G->o_bands));
+        G->d_offsets = reinterpret_cast<int64_t *>(P->p(G->o_offsets));
+        G->d_cursor = reinterpret_cast<unsigned long long *>(P->p(G->o_cursor));
+        G->d_gwork = reinterpret_cast<GridWork *>(P->p(G->o_gwork));
+        G->d_iwork = reinterpret_cast<InterpWork *>(P->p(G->o_iwork));
+        G->d_recs = P->p(G->o_recs);
+        G->d_omega = P->p(G->o_omega);
+        if (G->corr2d) {
+            G->d_corr2d = P->p(G->o_corr2d);
+        } else {
+            G->d_corrx = P->p(G->o_corrx);
+            G->d_corry = P->p(G->o_corry);
+        }
+        HIP_OK(hipMemcpyAsync(G->d_bands, G->bands.data(), G->bands.size() * sizeof(BandDev), hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(G->d_offsets, G->offsets.data(), G->offsets.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(G->d_cursor, G->d_offsets, G->offsets.size() * sizeof(int64_t),
+                              hipMemcpyDeviceToDevice, s));
+        if (!G->gwork.empty())
+            HIP_OK(hipMemcpyAsync(G->d_gwork, G->gwork.data(), G->gwork.size() * sizeof(GridWork),
+                                  hipMemcpyHostToDevice, s));
+        if (!G->iwork.empty())
+            HIP_OK(hipMemcpyAsync(G->d_iwork, G->iwork.data(), G->iwork.size() * sizeof(InterpWork),
+                                  hipMemcpyHostToDevice, s));
+        BucketArgs ba{};
+        ba.g = G->g;
+        ba.uvw = pr.uvw;
+        ba.freq_dev = reinterpret_cast<const double *>(P->p(P->o_freq));
+        ba.chan_band_dev = reinterpret_cast<const int *>(P->p(P->o_cb));
+        ba.weight = pr.weight;
+        ba.flag = pr.flag;
+        ba.bands = G->d_bands;
+        ba.n_row = pr.n_row;
+        ba.n_chan = pr.n_chan;
+        ba.cursor = G->d_cursor;
+        ba.recs = G->d_recs;
+        ba.omega = G->d_omega;
+        if (G == &P->main) {
+            ba.flagged = reinterpret_cast<uint32_t *>(P->p(P->o_flagged));
+            ba.flag_cursor = reinterpret_cast<unsigned long long *>(P->p(P->o_flagcur));
+        }
+        LAUNCH_OK(launch_scatter(d, ba, s));
+        const double *cheb = reinterpret_cast<const double *>(P->p(P->o_cheb));
+        const int nch = (int)P->cheb.size();
+        if (G->corr2d) {
+            LAUNCH_OK(launch_corr2d(d, G->g, G->d_bands, cheb, nch, P->xi_max, G->d_corr2d, s));
+        } else {
+            LAUNCH_OK(launch_corr1d(d, G->g.nx, G->g.gx, cheb, nch, P->xi_max, G->d_corrx, s));
+            LAUNCH_OK(launch_corr1d(d, G->g.ny, G->g.gy, cheb, nch, P->xi_max, G->d_corry, s));
+        }
+    }
+    HIP_OK(hipMemsetAsync(P->p(P->o_scal), 0, (size_t)pr.n_band * 8 * sizeof(double), s));
+    P->ws_ready = true;
+    return PFB_OK;
+}
+
+pfb_status pfb_plan_destroy(pfb_plan *P) {
+    delete P;
+    return PFB_OK;
+}
+
+pfb_status pfb_grid(pfb_plan *P, const void *vis, void *image, int mode, hipStream_t s) {
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    const bool d = P->dbl;
+    if (mode == PFB_GRID_DIRTY) {
+        if (!vis || !image) return fail(PFB_EINVAL, "vis and image must be non-NULL");
+        GridderHost &G = P->main;
+        for (int b0 = 0; b0 < P->prob.n_band; b0 += P->band_batch) {
+            const int nbb = std::min(P->band_batch, P->prob.n_band - b0);
+            LAUNCH_OK(launch_spread(d, spread_args(G, b0, nbb, 0, vis, P->p(P->o_planes)), s));
+            XformArgs xa = xform_args(P, G, b0, nbb);
+            xa.image_out = image;
+            LAUNCH_OK(launch_grid_xform(d, xa, s));
+        }
+        return PFB_OK;
+    }
+    if (mode == PFB_GRID_PSF) {
+        GridderHost &G = P->psf;
+        void *img = image ? image : P->p(P->o_psfimg);
+        for (int b0 = 0; b0 < P->prob.n_band; b0 += P->band_batch) {
+            const int nbb = std::min(P->band_batch, P->prob.n_band - b0);
+            LAUNCH_OK(launch_spread(d, spread_args(G, b0, nbb, 1, nullptr, P->p(P->o_planes)), s));
+            XformArgs xa = xform_args(P, G, b0, nbb);
+            xa.image_out = img;
+            xa.zero_edge = 1;
+            LAUNCH_OK(launch_grid_xform(d, xa, s));
+        }
+        LAUNCH_OK(launch_psfhat(d, conv_args(P), img, s));
+        P->psf_ready = true;
+        return PFB_OK;
+    }
+    return fail(PFB_EINVAL, "unknown grid mode %d", mode);
+}
+
+pfb_status pfb_degrid(pfb_plan *P, const void *image, void *vis, hipStream_t s) {
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!image || !vis) return fail(PFB_EINVAL, "image and vis must be non-NULL");
+    const bool d = P->dbl;
+    GridderHost &G = P->main;
+    LAUNCH_OK(launch_zero_flagged(d, reinterpret_cast<const uint32_t *>(P->p(P->o_flagged)), P->n_flagged, vis, s));
+    for (int b0 = 0; b0 < P->prob.n_band; b0 += P->band_batch) {
+        const int nbb = std::min(P->band_batch, P->prob.n_band - b0);
+        XformArgs xa = xform_args(P, G, b0, nbb);
+        xa.image_in = image;
+        LAUNCH_OK(launch_degrid_xform(d, xa, s));
+        LAUNCH_OK(launch_interp(d, interp_args(G, b0, nbb, 0, P->p(P->o_planes), vis), s));
+    }
+    return PFB_OK;
+}
+
+pfb_status pfb_hessian(pfb_plan *P, const void *x, void *y, hipStream_t s) {
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!x || !y) return fail(PFB_EINVAL, "x and y must be non-NULL");
+    if (x == y) return fail(PFB_EINVAL, "x and y must differ");
+    return hessian_impl(P, x, y, s);
+}
+
+pfb_status pfb_psf_conv(pfb_plan *P, const void *x, void *y, hipStream_t s) {
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!x || !y) return fail(PFB_EINVAL, "x and y must be non-NULL");
+    if (!P->psf_ready) return fail(PFB_ESTATE, "no PSF spectrum: call pfb_grid with PFB_GRID_PSF first");
+    LAUNCH_OK(launch_psf_conv(P->dbl, conv_args(P), x, nullptr, y, nullptr, 0.0, CONV_IN_X, CONV_OUT_Y, s));
+    return PFB_OK;
+}
+
+pfb_status pfb_precond_solve(pfb_plan *P, const void *g, void *y, double sigma, int iters, double *dev_resid,
+                             hipStream_t s) {
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!g || !y) return fail(PFB_EINVAL, "g and y must be non-NULL");
+    if (g == y) return fail(PFB_EINVAL, "g and y must differ");
+    if (!(sigma >= 0) || !std::isfinite(sigma)) return fail(PFB_EINVAL, "sigma must be finite and >= 0");
+    if (iters < 0) return fail(PFB_EINVAL, "iters must be >= 0");
+    if (!P->psf_ready) return fail(PFB_ESTATE, "no PSF spectrum: call pfb_grid with PFB_GRID_PSF first");
+    st = cg_solve(P, g, y, sigma, iters, s);
+    if (st) return st;
+    if (dev_resid) LAUNCH_OK(launch_copy_scalar(P->prob.n_band, reinterpret_cast<double *>(P->p(P->o_scal)), S_RR,
+                                                dev_resid, s));
+    return PFB_OK;
+}
+
+pfb_status pfb_power_iteration(pfb_plan *P, int op, const void *v0, int iters, double *dev_lambda, hipStream_t s) {
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!v0 || !dev_lambda) return fail(PFB_EINVAL, "v0 and dev_lambda must be non-NULL");
+    if (op != 0 && op != 1) return fail(PFB_EINVAL, "op must be 0 (PSF) or 1 (Hessian)");
+    if (iters < 0) return fail(PFB_EINVAL, "iters must be >= 0");
+    if (op == 0 && !P->psf_ready) return fail(PFB_ESTATE, "no PSF spectrum: call pfb_grid with PFB_GRID_PSF first");
+    const bool d = P->dbl;
+    ConvArgs ca = conv_args(P);
+    const int nb = P->prob.n_band;
+    const int64_t Pn = (int64_t)P->prob.nx * P->prob.ny;
+    char *v = reinterpret_cast<char *>(P->p(P->o_vec));
+    void *wa = v + 3 * P->vec_bytes, *wb = v + 4 * P->vec_bytes, *tmp = v + 5 * P->vec_bytes;
+    const int vparts = vec_partials_per_band(Pn);
+    const int cparts = conv_partials_per_band(d, ca);
+    const void *src = v0;
+    LAUNCH_OK(launch_vec(d, VEC_NORM, nb, Pn, ca.partials, ca.max_partials, ca.scal, const_cast<void *>(src), nullptr,
+                         nullptr, nullptr, nullptr, 0, 0, s));
+    LAUNCH_OK(launch_reduce(RED_INV_SQRT, nb, ca.partials, vparts, ca.max_partials, ca.scal, s));
+    for (int it = 0; it < iters; ++it) {
+        void *dst = (it % 2 == 0) ? wa : wb;
+        if (op == 0) {
+            LAUNCH_OK(launch_psf_conv(d, ca, src, nullptr, dst, nullptr, 0.0, CONV_IN_SCALED, CONV_OUT_NORM, s));
+            LAUNCH_OK(launch_reduce(RED_INV_SQRT, nb, ca.partials, cparts, ca.max_partials, ca.scal, s));
+        } else {
+            LAUNCH_OK(launch_vec(d, VEC_SCALE_COPY, nb, Pn, ca.partials, ca.max_partials, ca.scal,
+                                 const_cast<void *>(src), tmp, nullptr, nullptr, nullptr, 0, 0, s));
+            st = hessian_impl(P, tmp, dst, s);
+            if (st) return st;
+            LAUNCH_OK(launch_vec(d, VEC_NORM, nb, Pn, ca.partials, ca.max_partials, ca.scal, dst, nullptr, nullptr,
+                                 nullptr, nullptr, 0, 0, s));
+            LAUNCH_OK(launch_reduce(RED_INV_SQRT, nb, ca.partials, vparts, ca.max_partials, ca.scal, s));
+        }
+        src = dst;
+    }
+    // lambda = v^T A v with v = src * scale
+    void *dst = (iters % 2 == 0) ? wa : wb;
+    LAUNCH_OK(launch_vec(d, VEC_SCALE_COPY, nb, Pn, ca.partials, ca.max_partials, ca.scal, const_cast<void *>(src), tmp,
+                         nullptr, nullptr, nullptr, 0, 0, s));
+    if (op == 0) {
+        LAUNCH_OK(launch_psf_conv(d, ca, tmp, nullptr, dst, tmp, 0.0, CONV_IN_X, CONV_OUT_DOT, s));
+        LAUNCH_OK(launch_reduce(RED_LAMBDA, nb, ca.partials, cparts, ca.max_partials, ca.scal, s));
+    } else {
+        st = hessian_impl(P, tmp, dst, s);
+        if (st) return st;
+        LAUNCH_OK(launch_vec(d, VEC_DOT, nb, Pn, ca.partials, ca.max_partials, ca.scal, tmp, dst, nullptr, nullptr,
+                             nullptr, 0, 0, s));
+        LAUNCH_OK(launch_reduce(RED_LAMBDA, nb, ca.partials, vparts, ca.max_partials, ca.scal, s));
+    }
+    LAUNCH_OK(launch_copy_scalar(nb, ca.scal, S_LAMBDA, dev_lambda, s));
+    return PFB_OK;
+}
+
+pfb_status pfb_fb_step(pfb_plan *P, const void *dirty, void *x, double sigma, double gamma, double lambda,
+                       int cg_iters, hipStream_t s) {
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!dirty || !x) return fail(PFB_EINVAL, "dirty and x must be non-NULL");
+    if (!P->psf_ready) return fail(PFB_ESTATE, "no PSF spectrum: call pfb_grid with PFB_GRID_PSF first");
+    if (!(sigma >= 0) || !(gamma > 0) || !(lambda >= 0) || cg_iters < 0)
+        return fail(PFB_EINVAL, "need sigma >= 0, gamma > 0, lambda >= 0, cg_iters >= 0");
+    const bool d = P->dbl;
+    ConvArgs ca = conv_args(P);
+    char *v = reinterpret_cast<char *>(P->p(P->o_vec));
+    void *g = v + 3 * P->vec_bytes, *y = v + 4 * P->vec_bytes;
+    LAUNCH_OK(launch_psf_conv(d, ca, x, nullptr, g, dirty, 0.0, CONV_IN_X, CONV_OUT_SUB, s));
+    st = cg_solve(P, g, y, sigma, cg_iters, s);
+    if (st) return st;
+    const int64_t Pn = (int64_t)P->prob.nx * P->prob.ny;
+    LAUNCH_OK(launch_vec(d, VEC_FB_PROX, P->prob.n_band, Pn, ca.partials, ca.max_partials, ca.scal, x, y, nullptr,
+                         nullptr, nullptr, gamma, lambda, s));
+    return PFB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Host-callable launchers for the gfx950 kernels (implemented in pfb_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pfb_internal.h"
+
+namespace pfb {
+
+// All launchers return hipSuccess or the launch error; `dbl` selects float64.
+
+hipError_t launch_count(bool dbl, const BucketArgs &a, hipStream_t s);
+hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s);
+hipError_t launch_corr2d(bool dbl, const GeomDev &g, const BandDev *bands, const double *cheb,
+                         int ncheb, double xi_max, void *corr, hipStream_t s);
+hipError_t launch_corr1d(bool dbl, int n, int gsize, const double *cheb, int ncheb, double xi_max,
+                         void *corr, hipStream_t s);
+
+struct SpreadLaunch {
+    GeomDev g;
+    const BandDev *bands;
+    const GridWork *work;
+    int n_work;
+    const int64_t *offsets;
+    const void *recs, *omega;
+    const void *vis;      // VMODE 0: caller visibilities; VMODE 2: per-visibility values
+    void *planes;         // [band_batch][nwmax][gx][gy]
+    int band0;
+    int vmode;            // 0 data, 1 unit visibilities, 2 precomputed values
+};
+hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s);
+
+struct InterpLaunch {
+    GeomDev g;
+    const BandDev *bands;
+    const InterpWork *work;
+    int n_work;
+    const int64_t *offsets;
+    const void *recs, *omega;
+    const void *planes;
+    void *out;            // OMODE 0: visibilities; OMODE 1: per-visibility values
+    int band0;
+    int omode;
+};
+hipError_t launch_interp(bool dbl, const InterpLaunch &a, hipStream_t s);
+hipError_t launch_zero_flagged(bool dbl, const uint32_t *flagged, int64_t n, void *vis, hipStream_t s);
+
+// FFT passes of the operator transforms.  `tw` is the forward twiddle table of
+// length 2^log2_lmax.
+struct XformArgs {
+    GeomDev g;
+    const BandDev *bands;
+    int band0, n_bb;       // bands [band0, band0 + n_bb) of the batch
+    ColSplit cs;           // factorisation of gx
+    const void *tw;
+    int log2_lmax;
+    void *planes, *t1, *t2;
+    const void *corr2d;    // [n_band][nx][ny] or null
+    const void *corr_x, *corr_y;  // 1-D tables when corr2d is null
+    const void *image_in;  // degrid input [n_band][nx][ny]
+    void *image_out;       // grid output [n_band][nx][ny]
+    int zero_edge;         // PSF: zero row 0 and column 0 of the output
+};
+hipError_t launch_grid_xform(bool dbl, const XformArgs &a, hipStream_t s);    // planes -> image
+hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s);  // image -> planes
+
+// PSF convolution machinery.
+struct ConvArgs {
+    int n_band, nx, ny, ldh;   // image nx x ny; half-spectrum row stride ldh >= ny + 1
+    ColSplit cs;               // factorisation of 2 nx
+    const void *tw;
+    int log2_lmax;
+    void *t1c, *t2c;           // [n_band][2nx][ldh] complex
+    void *psfhat;              // [n_band][2nx][ldh] real (four-step order when split)
+    double *partials;          // [n_band][max_partials]
+    int max_partials;
+    double *scal;              // [n_band][8] device scalars
+};
+enum ConvIn { CONV_IN_X = 0, CONV_IN_CG_P = 1, CONV_IN_SCALED = 2 };
+enum ConvOut { CONV_OUT_Y = 0, CONV_OUT_SUB = 1, CONV_OUT_CG = 2, CONV_OUT_NORM = 3, CONV_OUT_DOT = 4 };
+// y = PSF * x with optional fused prologue / epilogue:
+//   in  CONV_IN_CG_P : p = r + beta p (x = r, aux_in = p, written back), transform p
+//       CONV_IN_SCALED: transform x * scal[S_SCALE]
+//   out CONV_OUT_SUB : y = conv - aux_out          (gradient, eq. 4)
+//       CONV_OUT_CG  : y = conv + sigma p, partial p . y  (CG, aux_out = p)
+//       CONV_OUT_NORM: partial y . y
+//       CONV_OUT_DOT : partial aux_out . y
+hipError_t launch_psf_conv(bool dbl, const ConvArgs &a, const void *x, void *aux_in, void *y,
+                           const void *aux_out, double sigma, int in_mode, int out_mode,
+                           hipStream_t s);
+// psfhat from a 2nx x 2ny PSF image (all bands)
+hipError_t launch_psfhat(bool dbl, const ConvArgs &a, const void *psf_img, hipStream_t s);
+int conv_partials_per_band(bool dbl, const ConvArgs &a);
+
+// Vector kernels for CG / power iteration / FB (all bands, P = nx*ny per band).
+enum VecOp {
+    VEC_CG_INIT = 0,     // y = 0, r = g, p = 0; partial r.r
+    VEC_CG_UPDATE = 1,   // y += alpha p; r -= alpha Ap; partial r.r
+    VEC_SCALE_COPY = 2,  // y = x * scal[SCALE]
+    VEC_DOT = 3,         // partial x.y
+    VEC_FB_PROX = 4,     // x = max(x - gamma y - gamma lambda, 0)
+    VEC_NORM = 5,        // partial x.x
+};
+hipError_t launch_vec(bool dbl, int op, int n_band, int64_t P, double *partials, int max_partials,
+                      const double *scal, void *x, void *y, void *r, void *p, const void *ap,
+                      double gamma, double lam, hipStream_t s);
+int vec_partials_per_band(int64_t P);
+
+// scalar slots in scal[b*8 + k]
+enum Slot { S_RR = 0, S_ALPHA = 1, S_BETA = 2, S_PAP = 3, S_SCALE = 4, S_LAMBDA = 5, S_TMP = 6 };
+enum ReduceOp {
+    RED_SET_RR = 0,       // rr = sum; beta = 0
+    RED_ALPHA = 1,        // pAp = sum; alpha = rr / pAp
+    RED_BETA = 2,         // beta = sum / rr; rr = sum
+    RED_INV_SQRT = 3,     // scale = 1 / sqrt(sum)
+    RED_LAMBDA = 4,       // lambda = sum
+    RED_STORE = 5,        // tmp = sum
+};
+hipError_t launch_reduce(int op, int n_band, const double *partials, int n_part, int max_partials,
+                         double *scal, hipStream_t s);
+hipError_t launch_copy_scalar(int n_band, const double *scal, int slot, double *dst, hipStream_t s);
+
+}  // namespace pfb

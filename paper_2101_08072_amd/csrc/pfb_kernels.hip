@@ -1,0 +1,1456 @@
+// gfx950 kernels of the pfb-clean hot path:
+//   * bucketing of visibilities into (band, uv tile, w base plane) buckets
+//   * ES-kernel gridding with owner-computes uv tiles (no global atomics)
+//   * ES-kernel degridding with a sliding window of w-planes in LDS
+//   * the 2-D FFT passes (LDS radix-8 DIT, four-step for long columns) with
+//     the w-phase, cropping, padding and grid correction fused into them
+//   * PSF convolution by zero-padded FFT and the CG / power-iteration kernels
+#include <type_traits>
+#include <utility>
+
+#include "pfb_kernels.h"
+
+namespace pfb {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+template <int LO, int HI, class F>
+static hipError_t dispatch_int(int v, F &&f) {
+    if constexpr (LO <= HI) {
+        if (v == LO) return f(std::integral_constant<int, LO>{});
+        return dispatch_int<LO + 1, HI>(v, std::forward<F>(f));
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <class K>
+static hipError_t set_lds(K kernel, size_t bytes) {
+    if (bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+#define PFB_LAUNCH(kernel, grid, lds, stream, ...)                                   \
+    do {                                                                             \
+        hipError_t _e = set_lds(kernel, (lds));                                      \
+        if (_e != hipSuccess) return _e;                                             \
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), (lds), stream,        \
+                           __VA_ARGS__);                                             \
+        _e = hipGetLastError();                                                      \
+        if (_e != hipSuccess) return _e;                                             \
+    } while (0)
+
+__device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
+
+__device__ __forceinline__ int wrapi(int a, int n) {
+    a %= n;
+    return a < 0 ? a + n : a;
+}
+
+// block-wide FP64 sum; result valid in thread 0
+__device__ double block_sum(double v, double *red) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wid = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    __syncthreads();
+    if (ln == 0) red[wid] = v;
+    __syncthreads();
+    double t = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kThreads / 64; ++k) t += red[k];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// bucketing
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct Keys {
+    R fu, fv, fw;
+    int tu, tv, j0, ou_lo, ou_hi, ov_lo, ov_hi;
+};
+
+// Grid coordinates of one visibility and the tiles its W x W footprint touches.
+// The local coordinates are rounded to R first so that the kernels, which
+// recompute the footprint from them, agree exactly with the bucket keys.
+template <typename R, bool FLAT>
+__device__ __forceinline__ bool vis_keys(const GeomDev &g, const BandDev &bd, double um, double vm,
+                                         double wm, double f, Keys<R> &k) {
+    const double s = f / kC0;
+    double tu = um * s * g.cellx * (double)g.gx;
+    double tv = vm * s * g.celly * (double)g.gy;
+    tu -= (double)g.gx * floor(tu / (double)g.gx);
+    tv -= (double)g.gy * floor(tv / (double)g.gy);
+    if (tu >= (double)g.gx) tu -= (double)g.gx;
+    if (tv >= (double)g.gy) tv -= (double)g.gy;
+    k.tu = min((int)(tu / g.T), g.ntx - 1);
+    k.tv = min((int)(tv / g.T), g.nty - 1);
+    k.fu = (R)(tu - (double)k.tu * g.T);
+    k.fv = (R)(tv - (double)k.tv * g.T);
+    const R hw = R(0.5) * (R)g.W;
+    const int i0 = (int)dev_floor(k.fu - hw) + 1;
+    const int j0 = (int)dev_floor(k.fv - hw) + 1;
+    // tiles (relative to the home tile) overlapped by cells [i0, i0 + W)
+    k.ou_lo = floordiv(i0, g.T);
+    k.ou_hi = floordiv(i0 + g.W - 1, g.T);
+    k.ov_lo = floordiv(j0, g.T);
+    k.ov_hi = floordiv(j0 + g.W - 1, g.T);
+    if (FLAT) {
+        k.fw = R(0);
+        k.j0 = 0;
+        return true;
+    }
+    const double tw = (wm * s - bd.w0) / bd.dw;
+    k.fw = (R)tw;
+    k.j0 = (int)dev_floor(k.fw - hw) + 1;
+    return k.j0 >= 0 && k.j0 < bd.nj0;
+}
+
+template <typename R, bool FLAT, bool SCATTER>
+__global__ __launch_bounds__(kThreads) void bucket_kernel(BucketArgs a) {
+    const int64_t total = a.n_row * a.n_chan;
+    const int ntiles = a.g.ntx * a.g.nty;
+    const R *wt = reinterpret_cast<const R *>(a.weight);
+    unsigned long long n_act = 0, n_flag = 0, n_bad = 0;
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < total; base += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = base + threadIdx.x;
+        bool valid = e < total;
+        bool flagged = false;
+        R w = R(0);
+        int64_t r = 0;
+        int c = 0;
+        if (valid) {
+            r = e / a.n_chan;
+            c = (int)(e - r * a.n_chan);
+            w = wt[e];
+            flagged = (a.flag && a.flag[e]) || !(w > R(0));
+        }
+        if (SCATTER && a.flagged) {
+            // wave-aggregated append of flagged indices
+            const unsigned long long m = __ballot(valid && flagged);
+            if (m) {
+                const int leader = __ffsll((long long)m) - 1;
+                unsigned long long b0 = 0;
+                if (lane == leader) b0 = atomicAdd(a.flag_cursor, (unsigned long long)__popcll(m));
+                b0 = __shfl(b0, leader, 64);
+                if (valid && flagged) {
+                    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                    a.flagged[b0 + rank] = (uint32_t)e;
+                }
+            }
+        }
+        if (!valid) continue;
+        if (flagged) {
+            ++n_flag;
+            continue;
+        }
+        const int b = a.chan_band_dev[c];
+        const BandDev bd = a.bands[b];
+        Keys<R> k;
+        const bool ok = vis_keys<R, FLAT>(a.g, bd, a.uvw[3 * r], a.uvw[3 * r + 1], a.uvw[3 * r + 2],
+                                          a.freq_dev[c], k);
+        if (!ok) {
+            ++n_bad;
+            continue;
+        }
+        ++n_act;
+        for (int ou = k.ou_lo; ou <= k.ou_hi; ++ou) {
+            for (int ov = k.ov_lo; ov <= k.ov_hi; ++ov) {
+                const int tile = wrapi(k.tu + ou, a.g.ntx) * a.g.nty + wrapi(k.tv + ov, a.g.nty);
+                const int64_t key = ((int64_t)b * ntiles + tile) * a.g.nj0max + k.j0;
+                if (!SCATTER) {
+                    atomicAdd(a.counts + key, 1u);
+                } else {
+                    const unsigned long long pos = atomicAdd(a.cursor + key, 1ull);
+                    Rec<R> rec;
+                    rec.fu = k.fu - (R)(ou * a.g.T);
+                    rec.fv = k.fv - (R)(ov * a.g.T);
+                    rec.fw = k.fw;
+                    rec.idx = (uint32_t)e | ((ou == 0 && ov == 0) ? kHomeBit : 0u);
+                    reinterpret_cast<Rec<R> *>(a.recs)[pos] = rec;
+                    reinterpret_cast<R *>(a.omega)[pos] = w;
+                }
+            }
+        }
+    }
+    if (!SCATTER) {
+        if (n_act) atomicAdd(a.n_active, n_act);
+        if (n_flag) atomicAdd(a.n_flagged, n_flag);
+        if (n_bad) atomicAdd(a.n_bad, n_bad);
+    }
+}
+
+template <bool SCATTER>
+static hipError_t launch_bucket(bool dbl, const BucketArgs &a, hipStream_t s) {
+    const int64_t total = a.n_row * a.n_chan;
+    int64_t nb = (total + kThreads - 1) / kThreads;
+    if (nb > 65536) nb = 65536;
+    if (nb < 1) nb = 1;
+    if (dbl) {
+        if (a.g.flat) PFB_LAUNCH((bucket_kernel<double, true, SCATTER>), nb, 0, s, a);
+        else PFB_LAUNCH((bucket_kernel<double, false, SCATTER>), nb, 0, s, a);
+    } else {
+        if (a.g.flat) PFB_LAUNCH((bucket_kernel<float, true, SCATTER>), nb, 0, s, a);
+        else PFB_LAUNCH((bucket_kernel<float, false, SCATTER>), nb, 0, s, a);
+    }
+    return hipSuccess;
+}
+hipError_t launch_count(bool dbl, const BucketArgs &a, hipStream_t s) { return launch_bucket<false>(dbl, a, s); }
+hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s) { return launch_bucket<true>(dbl, a, s); }
+
+// ---------------------------------------------------------------------------
+// grid correction
+// ---------------------------------------------------------------------------
+
+// Fourier transform of the ES kernel, psi_hat(xi) for |xi| <= xi_max, from its
+// Chebyshev expansion in y = 2 (xi / xi_max)^2 - 1 (the transform is even).
+__device__ double psihat_eval(const double *c, int n, double xi, double xi_max) {
+    const double t = xi / xi_max;
+    const double y = 2.0 * t * t - 1.0;
+    double b1 = 0, b2 = 0;
+    for (int k = n - 1; k >= 1; --k) {
+        const double b0 = c[k] + 2.0 * y * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+    }
+    return c[0] + y * b1 - b2;
+}
+
+// corr[b][i][j] = 1 / (psi_hat_u psi_hat_v [psi_hat_w(dw (s - sc)) n])
+template <typename R>
+__global__ __launch_bounds__(kThreads) void corr2d_kernel(GeomDev g, const BandDev *bands, const double *cheb,
+                                                          int ncheb, double xi_max, R *corr) {
+    const int64_t P = (int64_t)g.nx * g.ny;
+    const int64_t total = P * g.n_band;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total; e += (int64_t)gridDim.x * kThreads) {
+        const int b = (int)(e / P);
+        const int64_t p = e - (int64_t)b * P;
+        const int i = (int)(p / g.ny), j = (int)(p - (int64_t)i * g.ny);
+        const double qi = i - g.nx / 2, qj = j - g.ny / 2;
+        double c = psihat_eval(cheb, ncheb, qi / g.gx, xi_max) * psihat_eval(cheb, ncheb, qj / g.gy, xi_max);
+        if (!g.flat) {
+            const double l = qi * g.cellx, m = qj * g.celly;
+            const double r2 = l * l + m * m;
+            const double n = sqrt(1.0 - r2);
+            const double sm1 = -r2 / (1.0 + n);
+            const BandDev bd = bands[b];
+            c *= psihat_eval(cheb, ncheb, bd.dw * (sm1 - bd.sc), xi_max) * n;
+        }
+        corr[e] = (R)(1.0 / c);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void corr1d_kernel(int n, int gsize, const double *cheb, int ncheb,
+                                                          double xi_max, R *corr) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) corr[i] = (R)(1.0 / psihat_eval(cheb, ncheb, (double)(i - n / 2) / gsize, xi_max));
+}
+
+hipError_t launch_corr2d(bool dbl, const GeomDev &g, const BandDev *bands, const double *cheb, int ncheb,
+                         double xi_max, void *corr, hipStream_t s) {
+    int64_t nb = ((int64_t)g.nx * g.ny * g.n_band + kThreads - 1) / kThreads;
+    if (nb > 65536) nb = 65536;
+    if (dbl) PFB_LAUNCH(corr2d_kernel<double>, nb, 0, s, g, bands, cheb, ncheb, xi_max, (double *)corr);
+    else PFB_LAUNCH(corr2d_kernel<float>, nb, 0, s, g, bands, cheb, ncheb, xi_max, (float *)corr);
+    return hipSuccess;
+}
+hipError_t launch_corr1d(bool dbl, int n, int gsize, const double *cheb, int ncheb, double xi_max, void *corr,
+                         hipStream_t s) {
+    const int nb = (n + kThreads - 1) / kThreads;
+    if (dbl) PFB_LAUNCH(corr1d_kernel<double>, nb, 0, s, n, gsize, cheb, ncheb, xi_max, (double *)corr);
+    else PFB_LAUNCH(corr1d_kernel<float>, nb, 0, s, n, gsize, cheb, ncheb, xi_max, (float *)corr);
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// gridding: owner-computes uv tiles, sliding ring of W w-planes in LDS
+// ---------------------------------------------------------------------------
+// Each work item owns the T x T core cells of one uv tile for planes [p0, p1).
+// Its bucket lists every visibility whose footprint touches the core (copies
+// included), so every grid cell is accumulated by exactly one workgroup in FP32
+// LDS and written to HBM once, coalesced, with no global atomics and no
+// separate zero fill.  A group of LPV lanes handles one visibility: lane j owns
+// footprint column j and loops over the W rows and the W planes.
+template <typename R, int W, int LPV, bool FLAT, int VMODE>
+__global__ __launch_bounds__(kThreads) void spread_kernel(SpreadLaunch a) {
+    constexpr int WW = FLAT ? 1 : W;
+    constexpr int NGRP = kThreads / LPV;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int T = a.g.T, TT = T * T;
+    R *sre = reinterpret_cast<R *>(smem_raw);
+    R *sim = sre + WW * TT;
+    const GridWork wk = a.work[blockIdx.x];
+    const BandDev bd = a.bands[wk.band];
+    const int ntiles = a.g.ntx * a.g.nty;
+    const int tu = wk.tile / a.g.nty, tv = wk.tile - tu * a.g.nty;
+    const int bb = wk.band - a.band0;
+    const Rec<R> *recs = reinterpret_cast<const Rec<R> *>(a.recs);
+    const R *omega = reinterpret_cast<const R *>(a.omega);
+    const cplx<R> *vis = reinterpret_cast<const cplx<R> *>(a.vis);
+    cplx<R> *planes = reinterpret_cast<cplx<R> *>(a.planes);
+
+    for (int k = threadIdx.x; k < 2 * WW * TT; k += kThreads) sre[k] = R(0);
+    __syncthreads();
+
+    const int lane = threadIdx.x % LPV;
+    const int grp = threadIdx.x / LPV;
+    const R beta = (R)a.g.beta, inv_hw = R(2) / R(W), hw = R(0.5) * R(W);
+    const R w0 = (R)bd.w0, dw = (R)bd.dw, sc = (R)bd.sc;
+    const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
+    const int qstart = FLAT ? 0 : max(0, wk.p0 - W + 1);
+    const size_t plane_sz = (size_t)a.g.gx * a.g.gy;
+
+    for (int q = qstart; q < wk.p1; ++q) {
+        if (q < bd.nj0) {
+            const int64_t e_beg = a.offsets[keybase + q], e_end = a.offsets[keybase + q + 1];
+            for (int64_t e = e_beg + grp; e < e_end; e += NGRP) {
+                const Rec<R> rec = recs[e];
+                const uint32_t vid = rec.idx & ~kHomeBit;
+                cplx<R> z;
+                if (VMODE == 0) {
+                    const R om = omega[e];
+                    const cplx<R> v = vis[vid];
+                    z = v * cis_cycles<R>((w0 + rec.fw * dw) * sc) * om;
+                } else if (VMODE == 1) {
+                    z = cplx<R>{omega[e], R(0)};
+                } else {
+                    z = vis[vid];
+                }
+                const int i0 = (int)dev_floor(rec.fu - hw) + 1;
+                const int j0 = (int)dev_floor(rec.fv - hw) + 1;
+                R pu = R(0), pv = R(0), pw = R(1);
+                if (lane < W) {
+                    pu = es_kernel<R>(R(i0 + lane) - rec.fu, beta, inv_hw);
+                    pv = es_kernel<R>(R(j0 + lane) - rec.fv, beta, inv_hw);
+                    if (!FLAT) pw = es_kernel<R>(R(q + lane) - rec.fw, beta, inv_hw);
+                }
+                R wu[W];
+#pragma unroll
+                for (int i = 0; i < W; ++i) wu[i] = __shfl(pu, i, LPV);
+                R ww[WW];
+                if (FLAT) {
+                    ww[0] = R(1);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < WW; ++k) ww[k] = __shfl(pw, k, LPV);
+                }
+                const int c = j0 + lane;
+                const bool cok = (lane < W) && (c >= 0) && (c < T);
+                const cplx<R> zv = z * pv;
+#pragma unroll
+                for (int k = 0; k < WW; ++k) {
+                    const int p = q + k;
+                    if (!FLAT && (p < wk.p0 || p >= wk.p1)) continue;
+                    const int slot = FLAT ? 0 : p % W;
+                    R *re = sre + slot * TT + c;
+                    R *im = sim + slot * TT + c;
+                    const cplx<R> zk = zv * ww[k];
+#pragma unroll
+                    for (int i = 0; i < W; ++i) {
+                        const int row = i0 + i;
+                        if (cok && row >= 0 && row < T) {
+                            atomicAdd(re + row * T, zk.re * wu[i]);
+                            atomicAdd(im + row * T, zk.im * wu[i]);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const int slot = FLAT ? 0 : q % W;
+        if (FLAT || q >= wk.p0) {
+            cplx<R> *dst = planes + ((size_t)bb * a.g.nwmax + q) * plane_sz + (size_t)tu * T * a.g.gy + (size_t)tv * T;
+            for (int k = threadIdx.x; k < TT; k += kThreads) {
+                const int row = k / T, col = k - row * T;
+                dst[(size_t)row * a.g.gy + col] = cplx<R>{sre[slot * TT + k], sim[slot * TT + k]};
+            }
+        }
+        for (int k = threadIdx.x; k < TT; k += kThreads) {
+            sre[slot * TT + k] = R(0);
+            sim[slot * TT + k] = R(0);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R, int W, int LPV>
+static hipError_t spread_w(const SpreadLaunch &a, hipStream_t s) {
+    const bool flat = a.g.flat;
+    const size_t lds = 2 * (size_t)(flat ? 1 : W) * a.g.T * a.g.T * sizeof(R);
+#define SPREAD_CASE(FL, VM)                                                         \
+    if (flat == FL && a.vmode == VM) {                                              \
+        PFB_LAUNCH((spread_kernel<R, W, LPV, FL, VM>), a.n_work, lds, s, a);        \
+        return hipSuccess;                                                          \
+    }
+    SPREAD_CASE(false, 0)
+    SPREAD_CASE(false, 1)
+    SPREAD_CASE(false, 2)
+    SPREAD_CASE(true, 0)
+    SPREAD_CASE(true, 1)
+    SPREAD_CASE(true, 2)
+#undef SPREAD_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s) {
+    if (a.n_work <= 0) return hipSuccess;
+    if (dbl)
+        return dispatch_int<9, 16>(a.g.W, [&](auto Wc) { return spread_w<double, decltype(Wc)::value, 16>(a, s); });
+    return dispatch_int<4, 8>(a.g.W, [&](auto Wc) { return spread_w<float, decltype(Wc)::value, 8>(a, s); });
+}
+
+// ---------------------------------------------------------------------------
+// degridding: halo subgrid of W w-planes in an LDS ring
+// ---------------------------------------------------------------------------
+// A work item covers a run of entries of one tile sorted by base plane; it
+// keeps the (T+W) x (T+W) halo region of W consecutive w-planes in LDS and
+// slides one plane at a time.  Each visibility is computed once, from its home
+// tile; lanes of a group own footprint columns and the partial sums are
+// reduced across the group with lane shuffles.
+template <typename R, int W, int LPV, bool FLAT, int OMODE>
+__global__ __launch_bounds__(kThreads) void interp_kernel(InterpLaunch a) {
+    constexpr int WW = FLAT ? 1 : W;
+    constexpr int NGRP = kThreads / LPV;
+    constexpr int H = (W - 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *ring = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int T = a.g.T, S = T + W, SS = S * S;
+    const InterpWork wk = a.work[blockIdx.x];
+    const BandDev bd = a.bands[wk.band];
+    const int ntiles = a.g.ntx * a.g.nty;
+    const int tu = wk.tile / a.g.nty, tv = wk.tile - tu * a.g.nty;
+    const int bb = wk.band - a.band0;
+    const Rec<R> *recs = reinterpret_cast<const Rec<R> *>(a.recs);
+    const R *omega = reinterpret_cast<const R *>(a.omega);
+    const size_t plane_sz = (size_t)a.g.gx * a.g.gy;
+    const cplx<R> *pbase = reinterpret_cast<const cplx<R> *>(a.planes) + (size_t)bb * a.g.nwmax * plane_sz;
+    const int gx = a.g.gx, gy = a.g.gy;
+    const int ox = tu * T - H, oy = tv * T - H;
+
+    auto load_plane = [&](int p, int slot) {
+        const cplx<R> *P = pbase + (size_t)p * plane_sz;
+        cplx<R> *dst = ring + slot * SS;
+        for (int k = threadIdx.x; k < SS; k += kThreads) {
+            const int aa = k / S, cc = k - aa * S;
+            const int gi = wrapi(ox + aa, gx), gj = wrapi(oy + cc, gy);
+            dst[k] = P[(size_t)gi * gy + gj];
+        }
+    };
+
+    for (int k = 0; k < WW; ++k)
+        if (wk.q0 + k < (FLAT ? 1 : bd.nw)) load_plane(wk.q0 + k, (wk.q0 + k) % WW);
+    __syncthreads();
+
+    const int lane = threadIdx.x % LPV;
+    const int grp = threadIdx.x / LPV;
+    const R beta = (R)a.g.beta, inv_hw = R(2) / R(W), hw = R(0.5) * R(W);
+    const R w0 = (R)bd.w0, dw = (R)bd.dw, sc = (R)bd.sc;
+    const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
+
+    for (int q = wk.q0; q <= wk.q1; ++q) {
+        const int64_t lo = max((int64_t)wk.e0, a.offsets[keybase + q]);
+        const int64_t hi = min((int64_t)wk.e1, a.offsets[keybase + q + 1]);
+        for (int64_t e = lo + grp; e < hi; e += NGRP) {
+            const Rec<R> rec = recs[e];
+            if (!(rec.idx & kHomeBit)) continue;
+            const int i0 = (int)dev_floor(rec.fu - hw) + 1;
+            const int j0 = (int)dev_floor(rec.fv - hw) + 1;
+            R pu = R(0), pv = R(0), pw = R(1);
+            if (lane < W) {
+                pu = es_kernel<R>(R(i0 + lane) - rec.fu, beta, inv_hw);
+                pv = es_kernel<R>(R(j0 + lane) - rec.fv, beta, inv_hw);
+                if (!FLAT) pw = es_kernel<R>(R(q + lane) - rec.fw, beta, inv_hw);
+            }
+            R wu[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) wu[i] = __shfl(pu, i, LPV);
+            R ww[WW];
+            if (FLAT) {
+                ww[0] = R(1);
+            } else {
+#pragma unroll
+                for (int k = 0; k < WW; ++k) ww[k] = __shfl(pw, k, LPV);
+            }
+            cplx<R> acc{R(0), R(0)};
+            if (lane < W) {
+                const int col = j0 + lane + H;
+#pragma unroll
+                for (int k = 0; k < WW; ++k) {
+                    const cplx<R> *base = ring + ((q + k) % WW) * SS + col;
+                    cplx<R> ak{R(0), R(0)};
+#pragma unroll
+                    for (int i = 0; i < W; ++i) {
+                        const cplx<R> g = base[(i0 + i + H) * S];
+                        ak.re += wu[i] * g.re;
+                        ak.im += wu[i] * g.im;
+                    }
+                    acc.re += ww[k] * ak.re;
+                    acc.im += ww[k] * ak.im;
+                }
+                acc.re *= pv;
+                acc.im *= pv;
+            }
+#pragma unroll
+            for (int off = LPV / 2; off >= 1; off >>= 1) {
+                acc.re += __shfl_xor(acc.re, off, LPV);
+                acc.im += __shfl_xor(acc.im, off, LPV);
+            }
+            if (lane == 0) {
+                const uint32_t vid = rec.idx & ~kHomeBit;
+                if (OMODE == 0) {
+                    cplx<R> out = FLAT ? acc : acc * conj(cis_cycles<R>((w0 + rec.fw * dw) * sc));
+                    reinterpret_cast<cplx<R> *>(a.out)[vid] = out;
+                } else {
+                    reinterpret_cast<cplx<R> *>(a.out)[vid] = acc * omega[e];
+                }
+            }
+        }
+        __syncthreads();
+        if (!FLAT && q < wk.q1 && q + W < bd.nw) {
+            load_plane(q + W, q % W);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R, int W, int LPV>
+static hipError_t interp_w(const InterpLaunch &a, hipStream_t s) {
+    const bool flat = a.g.flat;
+    const int S = a.g.T + W;
+    const size_t lds = (size_t)(flat ? 1 : W) * S * S * sizeof(cplx<R>);
+#define INTERP_CASE(FL, OM)                                                         \
+    if (flat == FL && a.omode == OM) {                                              \
+        PFB_LAUNCH((interp_kernel<R, W, LPV, FL, OM>), a.n_work, lds, s, a);        \
+        return hipSuccess;                                                          \
+    }
+    INTERP_CASE(false, 0)
+    INTERP_CASE(false, 1)
+    INTERP_CASE(true, 0)
+    INTERP_CASE(true, 1)
+#undef INTERP_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_interp(bool dbl, const InterpLaunch &a, hipStream_t s) {
+    if (a.n_work <= 0) return hipSuccess;
+    if (dbl)
+        return dispatch_int<9, 16>(a.g.W, [&](auto Wc) { return interp_w<double, decltype(Wc)::value, 16>(a, s); });
+    return dispatch_int<4, 8>(a.g.W, [&](auto Wc) { return interp_w<float, decltype(Wc)::value, 8>(a, s); });
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void zero_flagged_kernel(const uint32_t *idx, int64_t n, cplx<R> *vis) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads)
+        vis[idx[e]] = cplx<R>{R(0), R(0)};
+}
+hipError_t launch_zero_flagged(bool dbl, const uint32_t *flagged, int64_t n, void *vis, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + kThreads - 1) / kThreads;
+    if (nb > 16384) nb = 16384;
+    if (dbl) PFB_LAUNCH(zero_flagged_kernel<double>, nb, 0, s, flagged, n, (cplx<double> *)vis);
+    else PFB_LAUNCH(zero_flagged_kernel<float>, nb, 0, s, flagged, n, (cplx<float> *)vis);
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// operator transforms (planes <-> image)
+// ---------------------------------------------------------------------------
+// Grid index q of image pixel i (period g): q = (i - n/2) mod g; inverse
+// i = (q + n/2) mod g, valid when < n.
+
+template <typename R>
+__device__ __forceinline__ R pixel_sm1(int i, int j, int nx, int ny, R cellx, R celly) {
+    const R l = R(i - nx / 2) * cellx, m = R(j - ny / 2) * celly;
+    const R r2 = l * l + m * m;
+    return -r2 / (R(1) + dev_sqrt(R(1) - r2));
+}
+
+constexpr int kRowLds = 32768;   // target LDS bytes per row-transform workgroup
+
+// rows per workgroup: the largest power of two whose LDS tiles fit kRowLds
+template <typename R, int LOG2L>
+__host__ __device__ constexpr int rows_per_block() {
+    constexpr int L = 1 << LOG2L;
+    constexpr int per = lds_len<R>(L) * (int)sizeof(cplx<R>);
+    int c = 1;
+    while (2 * c * per <= kRowLds) c *= 2;
+    return c;
+}
+
+// G1: inverse row DFT of every plane row, keeping the ny cropped outputs.
+template <typename R, int LOG2L>
+__global__ __launch_bounds__(kThreads) void g1_rows_kernel(XformArgs a, int C) {
+    constexpr int L = 1 << LOG2L;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int ld = lds_len<R>(L);
+    const int gx = a.g.gx, ny = a.g.ny;
+    const int ngrp = gx / C;
+    int blk = blockIdx.x;
+    const int ug = blk % ngrp;
+    blk /= ngrp;
+    const int j = blk % a.g.nwmax;
+    const int bb = blk / a.g.nwmax;
+    const int nw = a.g.flat ? 1 : a.bands[a.band0 + bb].nw;
+    if (j >= nw) return;
+    const size_t plane = (size_t)bb * a.g.nwmax + j;
+    const cplx<R> *src = reinterpret_cast<const cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
+    cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.t1) + (plane * gx + (size_t)ug * C) * ny;
+    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+        const int c = id / L, r = id - c * L;
+        buf[c * ld + lpad<R>(dit_pos<LOG2L>(r))] = src[(size_t)c * L + r];
+    }
+    __syncthreads();
+    lds_fft<R, true, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
+    for (int id = threadIdx.x; id < C * ny; id += kThreads) {
+        const int c = id / ny, iy = id - c * ny;
+        const int k = wrapi(iy - ny / 2, L);
+        dst[(size_t)c * ny + iy] = buf[c * ld + lpad<R>(k)];
+    }
+}
+
+// Column group width for column passes (contiguous complex values per row).
+template <typename R> __host__ __device__ constexpr int col_group() { return sizeof(R) == 4 ? 16 : 8; }
+
+// G2 / D1 / D2 helpers: step A of the four-step column transform.
+// Step A: for fixed r2, length-n1 DFT over rows r1*n2 + r2, times w_n^(-+r2 k1),
+// result stored at rows k1*n2 + r2.  INV selects the sign.
+// MODE 0 (grid, G2): in place on t1.  MODE 1 (degrid, D1): input computed from
+// the image with grid correction and the w-plane phase, output to t1.
+template <typename R, int LOG2N1, bool INV, int MODE>
+__global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
+    constexpr int N1 = 1 << LOG2N1;
+    constexpr int C = col_group<R>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int ld = lds_len<R>(N1);
+    const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny;
+    const int n2 = a.cs.n2;
+    const int ncg = (ny + C - 1) / C;
+    int blk = blockIdx.x;
+    const int cg = blk % ncg;
+    blk /= ncg;
+    const int r2 = blk % n2;
+    blk /= n2;
+    const int j = blk % a.g.nwmax;
+    const int bb = blk / a.g.nwmax;
+    const int b = a.band0 + bb;
+    const BandDev bd = a.bands[b];
+    const int nw = a.g.flat ? 1 : bd.nw;
+    if (j >= nw) return;
+    const size_t plane = (size_t)bb * a.g.nwmax + j;
+    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1) + plane * gx * ny;
+    const int col0 = cg * C;
+    const R wj = (R)(bd.w0 + j * bd.dw), sc = (R)bd.sc;
+    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
+        const int c = id % C, r1 = id / C;
+        const int col = col0 + c;
+        const int r = r1 * n2 + r2;
+        cplx<R> v{R(0), R(0)};
+        if (col < ny) {
+            if (MODE == 0) {
+                v = t1[(size_t)r * ny + col];
+            } else {
+                const int i = wrapi(r + nx / 2, gx);
+                if (i < nx) {
+                    const size_t pix = ((size_t)b * nx + i) * ny + col;
+                    const R x = reinterpret_cast<const R *>(a.image_in)[pix];
+                    const R cr = a.corr2d ? reinterpret_cast<const R *>(a.corr2d)[pix]
+                                          : reinterpret_cast<const R *>(a.corr_x)[i] * reinterpret_cast<const R *>(a.corr_y)[col];
+                    v = cplx<R>{x * cr, R(0)};
+                    if (!a.g.flat) {
+                        const R s = pixel_sm1<R>(i, col, nx, ny, (R)a.g.cellx, (R)a.g.celly) - sc;
+                        v = v * conj(cis_cycles<R>(wj * s));
+                    }
+                }
+            }
+        }
+        buf[c * ld + lpad<R>(dit_pos<LOG2N1>(r1))] = v;
+    }
+    __syncthreads();
+    const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
+    lds_fft<R, INV, LOG2N1>(buf, C, ld, tw, a.log2_lmax - LOG2N1);
+    const int shift_n = a.log2_lmax - (a.cs.log2n1 + a.cs.log2n2);
+    const int nmask = gx - 1;
+    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
+        const int c = id % C, k1 = id / C;
+        const int col = col0 + c;
+        if (col >= ny) continue;
+        cplx<R> v = buf[c * ld + lpad<R>(k1)];
+        if (n2 > 1) v = v * twiddle<R, INV>(tw, ((r2 * k1) & nmask) << shift_n);
+        t1[(size_t)(k1 * n2 + r2) * ny + col] = v;
+    }
+}
+
+// G3: step B of the inverse column transform (or the whole column when n1 = 1)
+// with the w-plane loop: accumulates Re(F_j e^{+2 pi i w_j (n - 1 - sc)}) over
+// planes in LDS, then applies the grid correction and writes the image.
+template <typename R, int LOG2N2>
+__global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
+    constexpr int N2 = 1 << LOG2N2;
+    constexpr int C = col_group<R>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int ld = lds_len<R>(N2);
+    R *acc = reinterpret_cast<R *>(buf + C * ld);     // [C][N2]
+    R *sv = acc + C * N2;                              // [C][N2] (n - 1 - sc)
+    const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny;
+    const int n1 = a.cs.n1;
+    const int ncg = (ny + C - 1) / C;
+    int blk = blockIdx.x;
+    const int cg = blk % ncg;
+    blk /= ncg;
+    const int k1 = blk % n1;
+    const int bb = blk / n1;
+    const int b = a.band0 + bb;
+    const BandDev bd = a.bands[b];
+    const int nw = a.g.flat ? 1 : bd.nw;
+    const int col0 = cg * C;
+    const R sc = (R)bd.sc;
+    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
+        const int c = id % C, k2 = id / C;
+        acc[c * N2 + k2] = R(0);
+        const int i = wrapi(k1 + n1 * k2 + nx / 2, gx);
+        const int col = col0 + c;
+        sv[c * N2 + k2] = (!a.g.flat && i < nx && col < ny)
+                              ? pixel_sm1<R>(i, col, nx, ny, (R)a.g.cellx, (R)a.g.celly) - sc
+                              : R(0);
+    }
+    const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
+    for (int j = 0; j < nw; ++j) {
+        const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1) + ((size_t)bb * a.g.nwmax + j) * gx * ny;
+        for (int id = threadIdx.x; id < C * N2; id += kThreads) {
+            const int c = id % C, r2 = id / C;
+            const int col = col0 + c;
+            buf[c * ld + lpad<R>(dit_pos<LOG2N2>(r2))] =
+                col < ny ? t1[(size_t)(k1 * N2 + r2) * ny + col] : cplx<R>{R(0), R(0)};
+        }
+        __syncthreads();
+        lds_fft<R, true, LOG2N2>(buf, C, ld, tw, a.log2_lmax - LOG2N2);
+        const R wj = (R)(bd.w0 + j * bd.dw);
+        for (int id = threadIdx.x; id < C * N2; id += kThreads) {
+            const int c = id % C, k2 = id / C;
+            const cplx<R> v = buf[c * ld + lpad<R>(k2)];
+            if (a.g.flat) {
+                acc[c * N2 + k2] += v.re;
+            } else {
+                const cplx<R> ph = cis_cycles<R>(wj * sv[c * N2 + k2]);
+                acc[c * N2 + k2] += v.re * ph.re - v.im * ph.im;
+            }
+        }
+        __syncthreads();
+    }
+    R *img = reinterpret_cast<R *>(a.image_out) + (size_t)b * nx * ny;
+    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
+        const int c = id % C, k2 = id / C;
+        const int col = col0 + c;
+        const int i = wrapi(k1 + n1 * k2 + nx / 2, gx);
+        if (i >= nx || col >= ny) continue;
+        const size_t pix = (size_t)i * ny + col;
+        const R cr = a.corr2d ? reinterpret_cast<const R *>(a.corr2d)[(size_t)b * nx * ny + pix]
+                              : reinterpret_cast<const R *>(a.corr_x)[i] * reinterpret_cast<const R *>(a.corr_y)[col];
+        R v = acc[c * N2 + k2] * cr;
+        if (a.zero_edge && (i == 0 || col == 0)) v = R(0);
+        img[pix] = v;
+    }
+}
+
+// D2: step B of the forward column transform, t1 (rows k1*n2 + r2) -> t2 (row k1 + n1 k2).
+template <typename R, int LOG2N2>
+__global__ __launch_bounds__(kThreads) void d2_kernel(XformArgs a) {
+    constexpr int N2 = 1 << LOG2N2;
+    constexpr int C = col_group<R>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int ld = lds_len<R>(N2);
+    const int gx = a.g.gx, ny = a.g.ny;
+    const int n1 = a.cs.n1;
+    const int ncg = (ny + C - 1) / C;
+    int blk = blockIdx.x;
+    const int cg = blk % ncg;
+    blk /= ncg;
+    const int k1 = blk % n1;
+    blk /= n1;
+    const int j = blk % a.g.nwmax;
+    const int bb = blk / a.g.nwmax;
+    const int nw = a.g.flat ? 1 : a.bands[a.band0 + bb].nw;
+    if (j >= nw) return;
+    const size_t plane = (size_t)bb * a.g.nwmax + j;
+    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1) + plane * gx * ny;
+    cplx<R> *t2 = reinterpret_cast<cplx<R> *>(a.t2) + plane * gx * ny;
+    const int col0 = cg * C;
+    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
+        const int c = id % C, r2 = id / C;
+        const int col = col0 + c;
+        buf[c * ld + lpad<R>(dit_pos<LOG2N2>(r2))] =
+            col < ny ? t1[(size_t)(k1 * N2 + r2) * ny + col] : cplx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    lds_fft<R, false, LOG2N2>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2N2);
+    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
+        const int c = id % C, k2 = id / C;
+        const int col = col0 + c;
+        if (col < ny) t2[(size_t)(k1 + n1 * k2) * ny + col] = buf[c * ld + lpad<R>(k2)];
+    }
+}
+
+// D3: forward row DFT of the ny placed inputs of each row, full output to the plane.
+template <typename R, int LOG2L>
+__global__ __launch_bounds__(kThreads) void d3_rows_kernel(XformArgs a, int C, const void *src_v) {
+    constexpr int L = 1 << LOG2L;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int ld = lds_len<R>(L);
+    const int gx = a.g.gx, ny = a.g.ny;
+    const int ngrp = gx / C;
+    int blk = blockIdx.x;
+    const int ug = blk % ngrp;
+    blk /= ngrp;
+    const int j = blk % a.g.nwmax;
+    const int bb = blk / a.g.nwmax;
+    const int nw = a.g.flat ? 1 : a.bands[a.band0 + bb].nw;
+    if (j >= nw) return;
+    const size_t plane = (size_t)bb * a.g.nwmax + j;
+    const cplx<R> *src = reinterpret_cast<const cplx<R> *>(src_v) + (plane * gx + (size_t)ug * C) * ny;
+    cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
+    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+        const int c = id / L, r = id - c * L;
+        const int iy = wrapi(r + ny / 2, L);
+        buf[c * ld + lpad<R>(dit_pos<LOG2L>(r))] = iy < ny ? src[(size_t)c * ny + iy] : cplx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    lds_fft<R, false, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
+    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+        const int c = id / L, k = id - c * L;
+        dst[(size_t)c * L + k] = buf[c * ld + lpad<R>(k)];
+    }
+}
+
+template <typename R>
+static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
+    const int lgy = __builtin_ctz(a.g.gy);
+    hipError_t e = dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        const int C = std::min(rows_per_block<R, LG>(), a.g.gx);
+        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C);
+        PFB_LAUNCH((g1_rows_kernel<R, LG>), nb, lds, s, a, C);
+        return hipSuccess;
+    });
+    if (e != hipSuccess) return e;
+    constexpr int C = col_group<R>();
+    const int ncg = (a.g.ny + C - 1) / C;
+    if (a.cs.n2 > 1) {
+        e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
+            constexpr int LG = decltype(Lc)::value;
+            const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+            const int nb = a.n_bb * a.g.nwmax * a.cs.n2 * ncg;
+            PFB_LAUNCH((colA_kernel<R, LG, true, 0>), nb, lds, s, a);
+            return hipSuccess;
+        });
+        if (e != hipSuccess) return e;
+    }
+    const int lg3 = a.cs.n2 > 1 ? a.cs.log2n2 : a.cs.log2n1;
+    XformArgs b = a;
+    if (a.cs.n2 == 1) {  // single pass: G3 takes the whole column (n1 -> 1, n2 -> L)
+        b.cs.n1 = 1;
+        b.cs.n2 = a.cs.n1;
+        b.cs.log2n1 = 0;
+        b.cs.log2n2 = a.cs.log2n1;
+    }
+    return dispatch_int<3, 9>(lg3, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        constexpr int N2 = 1 << LG;
+        const size_t lds = (size_t)C * lds_len<R>(N2) * sizeof(cplx<R>) + 2 * (size_t)C * N2 * sizeof(R);
+        const int nb = b.n_bb * b.cs.n1 * ncg;
+        PFB_LAUNCH((g3_kernel<R, LG>), nb, lds, s, b);
+        return hipSuccess;
+    });
+}
+
+template <typename R>
+static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
+    constexpr int C = col_group<R>();
+    const int ncg = (a.g.ny + C - 1) / C;
+    hipError_t e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const int nb = a.n_bb * a.g.nwmax * a.cs.n2 * ncg;
+        PFB_LAUNCH((colA_kernel<R, LG, false, 1>), nb, lds, s, a);
+        return hipSuccess;
+    });
+    if (e != hipSuccess) return e;
+    const void *rows_src = a.t1;
+    if (a.cs.n2 > 1) {
+        e = dispatch_int<3, 9>(a.cs.log2n2, [&](auto Lc) -> hipError_t {
+            constexpr int LG = decltype(Lc)::value;
+            const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+            const int nb = a.n_bb * a.g.nwmax * a.cs.n1 * ncg;
+            PFB_LAUNCH((d2_kernel<R, LG>), nb, lds, s, a);
+            return hipSuccess;
+        });
+        if (e != hipSuccess) return e;
+        rows_src = a.t2;
+    }
+    const int lgy = __builtin_ctz(a.g.gy);
+    return dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        const int C2 = std::min(rows_per_block<R, LG>(), a.g.gx);
+        const size_t lds = (size_t)C2 * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C2);
+        PFB_LAUNCH((d3_rows_kernel<R, LG>), nb, lds, s, a, C2, rows_src);
+        return hipSuccess;
+    });
+}
+
+hipError_t launch_grid_xform(bool dbl, const XformArgs &a, hipStream_t s) {
+    return dbl ? grid_xform_t<double>(a, s) : grid_xform_t<float>(a, s);
+}
+hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s) {
+    return dbl ? degrid_xform_t<double>(a, s) : degrid_xform_t<float>(a, s);
+}
+
+// ---------------------------------------------------------------------------
+// PSF convolution on the 2nx x 2ny zero-padded grid
+// ---------------------------------------------------------------------------
+
+// S1: forward row DFT (length 2ny) of real rows, keeping the half spectrum k = 0..ny.
+//   in_mode CONV_IN_X      : row i of x (ny values, zero padded)
+//           CONV_IN_CG_P   : p = r + beta p, written back, then transformed
+//           CONV_IN_SCALED : x * scale
+//   psfhat mode (nrows = 2nx): row i of the PSF rolled by (nx, ny)
+template <typename R, int LOG2L, int IN>
+__global__ __launch_bounds__(kThreads) void s1_kernel(ConvArgs a, const R *x, R *auxp, int nrows, int C, int psf) {
+    constexpr int L = 1 << LOG2L;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int ld = lds_len<R>(L);
+    const int nx = a.nx, ny = a.ny;
+    const int ngrp = nrows / C;
+    const int ig = blockIdx.x % ngrp;
+    const int b = blockIdx.x / ngrp;
+    R bscale = R(1);
+    if (IN == CONV_IN_CG_P) bscale = (R)a.scal[b * 8 + S_BETA];
+    if (IN == CONV_IN_SCALED) bscale = (R)a.scal[b * 8 + S_SCALE];
+    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+        const int c = id / L, r = id - c * L;
+        const int i = ig * C + c;
+        R v = R(0);
+        if (psf) {
+            const int si = wrapi(i + nx, 2 * nx), sj = wrapi(r + ny, 2 * ny);
+            v = x[((size_t)b * 2 * nx + si) * 2 * ny + sj];
+        } else if (r < ny) {
+            const size_t pix = ((size_t)b * nx + i) * ny + r;
+            if (IN == CONV_IN_X) {
+                v = x[pix];
+            } else if (IN == CONV_IN_SCALED) {
+                v = x[pix] * bscale;
+            } else {
+                v = x[pix] + bscale * auxp[pix];
+                auxp[pix] = v;
+            }
+        }
+        buf[c * ld + lpad<R>(dit_pos<LOG2L>(r))] = cplx<R>{v, R(0)};
+    }
+    __syncthreads();
+    lds_fft<R, false, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
+    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * C) * a.ldh;
+    for (int id = threadIdx.x; id < C * (ny + 1); id += kThreads) {
+        const int c = id / (ny + 1), k = id - c * (ny + 1);
+        t1[(size_t)c * a.ldh + k] = buf[c * ld + lpad<R>(k)];
+    }
+}
+
+// In-LDS product with the PSF spectrum followed by a re-ordering into DIT input
+// order for the inverse transform.  Values pass through registers.
+template <typename R, int LOG2L>
+__device__ __forceinline__ void mul_reorder(cplx<R> *buf, int C, int ld, const R *h, size_t hstride,
+                                            int col0, int ncol) {
+    constexpr int L = 1 << LOG2L;
+    constexpr int PER = (L * col_group<R>() + kThreads - 1) / kThreads;
+    cplx<R> v[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int id = threadIdx.x + t * kThreads;
+        if (id < C * L) {
+            const int c = id % C, k = id / C;
+            const R hv = (col0 + c) < ncol ? h[(size_t)k * hstride + col0 + c] : R(0);
+            v[t] = buf[c * ld + lpad<R>(k)] * hv;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int id = threadIdx.x + t * kThreads;
+        if (id < C * L) {
+            const int c = id % C, k = id / C;
+            buf[c * ld + lpad<R>(dit_pos<LOG2L>(k))] = v[t];
+        }
+    }
+    __syncthreads();
+}
+
+// S2 single pass (2nx <= 512): column DFT, product with psfhat, inverse, crop.
+// psf mode: forward only, stores Re into psfhat.
+template <typename R, int LOG2L>
+__global__ __launch_bounds__(kThreads) void s2_single_kernel(ConvArgs a, int psf) {
+    constexpr int L = 1 << LOG2L;
+    constexpr int C = col_group<R>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int ld = lds_len<R>(L);
+    const int nx = a.nx, ncol = a.ny + 1;
+    const int ncg = (ncol + C - 1) / C;
+    const int cg = blockIdx.x % ncg, b = blockIdx.x / ncg;
+    const int col0 = cg * C;
+    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + (size_t)b * 2 * nx * a.ldh;
+    R *h = reinterpret_cast<R *>(a.psfhat) + (size_t)b * 2 * nx * a.ldh;
+    const int nin = psf ? 2 * nx : nx;
+    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+        const int c = id % C, r = id / C;
+        const int col = col0 + c;
+        buf[c * ld + lpad<R>(dit_pos<LOG2L>(r))] =
+            (r < nin && col < ncol) ? t1[(size_t)r * a.ldh + col] : cplx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
+    lds_fft<R, false, LOG2L>(buf, C, ld, tw, a.log2_lmax - LOG2L);
+    if (psf) {
+        for (int id = threadIdx.x; id < C * L; id += kThreads) {
+            const int c = id % C, k = id / C;
+            if (col0 + c < ncol) h[(size_t)k * a.ldh + col0 + c] = buf[c * ld + lpad<R>(k)].re;
+        }
+        return;
+    }
+    mul_reorder<R, LOG2L>(buf, C, ld, h, a.ldh, col0, ncol);
+    lds_fft<R, true, LOG2L>(buf, C, ld, tw, a.log2_lmax - LOG2L);
+    for (int id = threadIdx.x; id < C * nx; id += kThreads) {
+        const int c = id % C, r = id / C;
+        if (col0 + c < ncol) t1[(size_t)r * a.ldh + col0 + c] = buf[c * ld + lpad<R>(r)];
+    }
+}
+
+// S2A: four-step step A (forward) over r1 for fixed r2: t1c rows r1*n2+r2 -> t2c rows k1*n2+r2.
+template <typename R, int LOG2N1>
+__global__ __launch_bounds__(kThreads) void s2a_kernel(ConvArgs a, int psf) {
+    constexpr int N1 = 1 << LOG2N1;
+    constexpr int C = col_group<R>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int ld = lds_len<R>(N1);
+    const int nx = a.nx, ncol = a.ny + 1, n2 = a.cs.n2;
+    const int ncg = (ncol + C - 1) / C;
+    int blk = blockIdx.x;
+    const int cg = blk % ncg;
+    blk /= ncg;
+    const int r2 = blk % n2;
+    const int b = blk / n2;
+    const int col0 = cg * C;
+    const size_t boff = (size_t)b * 2 * nx * a.ldh;
+    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + boff;
+    cplx<R> *t2 = reinterpret_cast<cplx<R> *>(a.t2c) + boff;
+    const int nin = psf ? 2 * nx : nx;
+    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
+        const int c = id % C, r1 = id / C;
+        const int r = r1 * n2 + r2;
+        const int col = col0 + c;
+        buf[c * ld + lpad<R>(dit_pos<LOG2N1>(r1))] =
+            (r < nin && col < ncol) ? t1[(size_t)r * a.ldh + col] : cplx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
+    lds_fft<R, false, LOG2N1>(buf, C, ld, tw, a.log2_lmax - LOG2N1);
+    const int shift_n = a.log2_lmax - (a.cs.log2n1 + a.cs.log2n2);
+    const int nmask = 2 * nx - 1;
+    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
+        const int c = id % C, k1 = id / C;
+        if (col0 + c >= ncol) continue;
+        t2[(size_t)(k1 * n2 + r2) * a.ldh + col0 + c] =
+            buf[c * ld + lpad<R>(k1)] * twiddle<R, false>(tw, ((r2 * k1) & nmask) << shift_n);
+    }
+}
+
+// S2B: for fixed k1, forward DFT over r2, product with psfhat (stored in the
+// same [k1*n2 + k2] order), inverse DFT over k2, twiddle w^(+r2 k1); in place.
+// psf mode: forward only, Re stored to psfhat.
+template <typename R, int LOG2N2>
+__global__ __launch_bounds__(kThreads) void s2b_kernel(ConvArgs a, int psf) {
+    constexpr int N2 = 1 << LOG2N2;
+    constexpr int C = col_group<R>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int ld = lds_len<R>(N2);
+    const int nx = a.nx, ncol = a.ny + 1, n1 = a.cs.n1;
+    const int ncg = (ncol + C - 1) / C;
+    int blk = blockIdx.x;
+    const int cg = blk % ncg;
+    blk /= ncg;
+    const int k1 = blk % n1;
+    const int b = blk / n1;
+    const int col0 = cg * C;
+    const size_t boff = (size_t)b * 2 * nx * a.ldh;
+    cplx<R> *t2 = reinterpret_cast<cplx<R> *>(a.t2c) + boff + (size_t)k1 * N2 * a.ldh;
+    R *h = reinterpret_cast<R *>(a.psfhat) + boff + (size_t)k1 * N2 * a.ldh;
+    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
+        const int c = id % C, r2 = id / C;
+        const int col = col0 + c;
+        buf[c * ld + lpad<R>(dit_pos<LOG2N2>(r2))] = col < ncol ? t2[(size_t)r2 * a.ldh + col] : cplx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
+    lds_fft<R, false, LOG2N2>(buf, C, ld, tw, a.log2_lmax - LOG2N2);
+    if (psf) {
+        for (int id = threadIdx.x; id < C * N2; id += kThreads) {
+            const int c = id % C, k2 = id / C;
+            if (col0 + c < ncol) h[(size_t)k2 * a.ldh + col0 + c] = buf[c * ld + lpad<R>(k2)].re;
+        }
+        return;
+    }
+    mul_reorder<R, LOG2N2>(buf, C, ld, h, a.ldh, col0, ncol);
+    lds_fft<R, true, LOG2N2>(buf, C, ld, tw, a.log2_lmax - LOG2N2);
+    const int shift_n = a.log2_lmax - (a.cs.log2n1 + a.cs.log2n2);
+    const int nmask = 2 * nx - 1;
+    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
+        const int c = id % C, r2 = id / C;
+        if (col0 + c >= ncol) continue;
+        t2[(size_t)r2 * a.ldh + col0 + c] =
+            buf[c * ld + lpad<R>(r2)] * twiddle<R, true>(tw, ((r2 * k1) & nmask) << shift_n);
+    }
+}
+
+// S2C: inverse step A over k1 for fixed r2: t2c rows k1*n2 + r2 -> t1c row r2 + n2 r1 (< nx only).
+template <typename R, int LOG2N1>
+__global__ __launch_bounds__(kThreads) void s2c_kernel(ConvArgs a) {
+    constexpr int N1 = 1 << LOG2N1;
+    constexpr int C = col_group<R>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int ld = lds_len<R>(N1);
+    const int nx = a.nx, ncol = a.ny + 1, n2 = a.cs.n2;
+    const int ncg = (ncol + C - 1) / C;
+    int blk = blockIdx.x;
+    const int cg = blk % ncg;
+    blk /= ncg;
+    const int r2 = blk % n2;
+    const int b = blk / n2;
+    const int col0 = cg * C;
+    const size_t boff = (size_t)b * 2 * nx * a.ldh;
+    const cplx<R> *t2 = reinterpret_cast<const cplx<R> *>(a.t2c) + boff;
+    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + boff;
+    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
+        const int c = id % C, k1 = id / C;
+        const int col = col0 + c;
+        buf[c * ld + lpad<R>(dit_pos<LOG2N1>(k1))] =
+            col < ncol ? t2[(size_t)(k1 * n2 + r2) * a.ldh + col] : cplx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    lds_fft<R, true, LOG2N1>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2N1);
+    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
+        const int c = id % C, r1 = id / C;
+        const int r = r2 + n2 * r1;
+        if (r < nx && col0 + c < ncol) t1[(size_t)r * a.ldh + col0 + c] = buf[c * ld + lpad<R>(r1)];
+    }
+}
+
+// S3: inverse row DFT (length 2ny) of the Hermitian half spectrum, real part,
+// cropped to ny, scaled by 1 / (4 nx ny), with fused epilogues.
+template <typename R, int LOG2L, int OUT>
+__global__ __launch_bounds__(kThreads) void s3_kernel(ConvArgs a, R *y, const R *aux, R sigma, int C) {
+    constexpr int L = 1 << LOG2L;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    __shared__ double red[kThreads / 64];
+    const int ld = lds_len<R>(L);
+    const int nx = a.nx, ny = a.ny;
+    const int ngrp = nx / C;
+    const int ig = blockIdx.x % ngrp;
+    const int b = blockIdx.x / ngrp;
+    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * C) * a.ldh;
+    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+        const int c = id / L, k = id - c * L;
+        const cplx<R> v = k <= ny ? t1[(size_t)c * a.ldh + k] : conj(t1[(size_t)c * a.ldh + (L - k)]);
+        buf[c * ld + lpad<R>(dit_pos<LOG2L>(k))] = v;
+    }
+    __syncthreads();
+    lds_fft<R, true, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
+    const R scale = R(1) / (R(4) * R(nx) * R(ny));
+    double part = 0.0;
+    for (int id = threadIdx.x; id < C * ny; id += kThreads) {
+        const int c = id / ny, j = id - c * ny;
+        const size_t pix = ((size_t)b * nx + ig * C + c) * ny + j;
+        R v = buf[c * ld + lpad<R>(j)].re * scale;
+        if (OUT == CONV_OUT_SUB) v -= aux[pix];
+        if (OUT == CONV_OUT_CG) {
+            const R pv = aux[pix];
+            v += sigma * pv;
+            part += (double)pv * (double)v;
+        }
+        if (OUT == CONV_OUT_NORM) part += (double)v * (double)v;
+        if (OUT == CONV_OUT_DOT) part += (double)aux[pix] * (double)v;
+        y[pix] = v;
+    }
+    if (OUT == CONV_OUT_CG || OUT == CONV_OUT_NORM || OUT == CONV_OUT_DOT) {
+        const double t = block_sum(part, red);
+        if (threadIdx.x == 0) a.partials[(size_t)b * a.max_partials + ig] = t;
+    }
+}
+
+template <typename R>
+static hipError_t conv_columns(const ConvArgs &a, int psf, hipStream_t s) {
+    constexpr int C = col_group<R>();
+    const int ncg = (a.ny + 1 + C - 1) / C;
+    if (a.cs.n2 == 1) {
+        return dispatch_int<5, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
+            constexpr int LG = decltype(Lc)::value;
+            const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+            PFB_LAUNCH((s2_single_kernel<R, LG>), a.n_band * ncg, lds, s, a, psf);
+            return hipSuccess;
+        });
+    }
+    hipError_t e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        PFB_LAUNCH((s2a_kernel<R, LG>), a.n_band * a.cs.n2 * ncg, lds, s, a, psf);
+        return hipSuccess;
+    });
+    if (e != hipSuccess) return e;
+    e = dispatch_int<3, 9>(a.cs.log2n2, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        PFB_LAUNCH((s2b_kernel<R, LG>), a.n_band * a.cs.n1 * ncg, lds, s, a, psf);
+        return hipSuccess;
+    });
+    if (e != hipSuccess || psf) return e;
+    return dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        PFB_LAUNCH((s2c_kernel<R, LG>), a.n_band * a.cs.n2 * ncg, lds, s, a);
+        return hipSuccess;
+    });
+}
+
+template <typename R>
+static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, void *y, const void *aux_out,
+                             double sigma, int in_mode, int out_mode, hipStream_t s) {
+    const int lg = __builtin_ctz(2 * a.ny);
+    hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        const int C = std::min(rows_per_block<R, LG>(), a.nx);
+        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const int nb = a.n_band * (a.nx / C);
+        const R *xr = reinterpret_cast<const R *>(x);
+        R *ap = reinterpret_cast<R *>(aux_in);
+        if (in_mode == CONV_IN_X) PFB_LAUNCH((s1_kernel<R, LG, CONV_IN_X>), nb, lds, s, a, xr, ap, a.nx, C, 0);
+        else if (in_mode == CONV_IN_CG_P) PFB_LAUNCH((s1_kernel<R, LG, CONV_IN_CG_P>), nb, lds, s, a, xr, ap, a.nx, C, 0);
+        else PFB_LAUNCH((s1_kernel<R, LG, CONV_IN_SCALED>), nb, lds, s, a, xr, ap, a.nx, C, 0);
+        return hipSuccess;
+    });
+    if (e != hipSuccess) return e;
+    e = conv_columns<R>(a, 0, s);
+    if (e != hipSuccess) return e;
+    return dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        const int C = std::min(rows_per_block<R, LG>(), a.nx);
+        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const int nb = a.n_band * (a.nx / C);
+        R *yr = reinterpret_cast<R *>(y);
+        const R *ax = reinterpret_cast<const R *>(aux_out);
+        const R sg = (R)sigma;
+        switch (out_mode) {
+            case CONV_OUT_Y: PFB_LAUNCH((s3_kernel<R, LG, CONV_OUT_Y>), nb, lds, s, a, yr, ax, sg, C); break;
+            case CONV_OUT_SUB: PFB_LAUNCH((s3_kernel<R, LG, CONV_OUT_SUB>), nb, lds, s, a, yr, ax, sg, C); break;
+            case CONV_OUT_CG: PFB_LAUNCH((s3_kernel<R, LG, CONV_OUT_CG>), nb, lds, s, a, yr, ax, sg, C); break;
+            case CONV_OUT_NORM: PFB_LAUNCH((s3_kernel<R, LG, CONV_OUT_NORM>), nb, lds, s, a, yr, ax, sg, C); break;
+            default: PFB_LAUNCH((s3_kernel<R, LG, CONV_OUT_DOT>), nb, lds, s, a, yr, ax, sg, C); break;
+        }
+        return hipSuccess;
+    });
+}
+
+hipError_t launch_psf_conv(bool dbl, const ConvArgs &a, const void *x, void *aux_in, void *y, const void *aux_out,
+                           double sigma, int in_mode, int out_mode, hipStream_t s) {
+    return dbl ? psf_conv_t<double>(a, x, aux_in, y, aux_out, sigma, in_mode, out_mode, s)
+               : psf_conv_t<float>(a, x, aux_in, y, aux_out, sigma, in_mode, out_mode, s);
+}
+
+int conv_partials_per_band(bool dbl, const ConvArgs &a) {
+    // S3 writes one partial per row group; rows per group depend on the row length
+    const int lg = __builtin_ctz(2 * a.ny);
+    int C = 1;
+    (void)dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        C = dbl ? rows_per_block<double, LG>() : rows_per_block<float, LG>();
+        return hipSuccess;
+    });
+    return a.nx / std::min(C, a.nx);
+}
+
+template <typename R>
+static hipError_t psfhat_t(const ConvArgs &a, const void *psf_img, hipStream_t s) {
+    const int lg = __builtin_ctz(2 * a.ny);
+    hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        const int C = std::min(rows_per_block<R, LG>(), a.nx);
+        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const int nb = a.n_band * (2 * a.nx / C);
+        PFB_LAUNCH((s1_kernel<R, LG, CONV_IN_X>), nb, lds, s, a, reinterpret_cast<const R *>(psf_img),
+                   (R *)nullptr, 2 * a.nx, C, 1);
+        return hipSuccess;
+    });
+    if (e != hipSuccess) return e;
+    return conv_columns<R>(a, 1, s);
+}
+hipError_t launch_psfhat(bool dbl, const ConvArgs &a, const void *psf_img, hipStream_t s) {
+    return dbl ? psfhat_t<double>(a, psf_img, s) : psfhat_t<float>(a, psf_img, s);
+}
+
+// ---------------------------------------------------------------------------
+// vector kernels and device-side scalar reductions
+// ---------------------------------------------------------------------------
+constexpr int kVecPerThread = 8;
+
+int vec_partials_per_band(int64_t P) {
+    const int64_t per = (int64_t)kThreads * kVecPerThread;
+    int64_t n = (P + per - 1) / per;
+    return (int)std::min<int64_t>(n, 4096);
+}
+
+template <typename R, int OP>
+__global__ __launch_bounds__(kThreads) void vec_kernel(int64_t P, int nblk, double *partials, int max_partials,
+                                                       const double *scal, R *x, R *y, R *r, R *p, const R *ap,
+                                                       R gamma, R lam) {
+    __shared__ double red[kThreads / 64];
+    const int b = blockIdx.x / nblk;
+    const int kb = blockIdx.x - b * nblk;
+    const size_t off = (size_t)b * P;
+    const double *sc = scal + b * 8;
+    double part = 0.0;
+    const R alpha = (OP == VEC_CG_UPDATE) ? (R)sc[S_ALPHA] : R(0);
+    const R scale = (OP == VEC_SCALE_COPY) ? (R)sc[S_SCALE] : R(1);
+    for (int64_t k = (int64_t)kb * kThreads + threadIdx.x; k < P; k += (int64_t)nblk * kThreads) {
+        const size_t e = off + k;
+        if (OP == VEC_CG_INIT) {
+            const R g = x[e];
+            y[e] = R(0);
+            r[e] = g;
+            p[e] = R(0);
+            part += (double)g * (double)g;
+        } else if (OP == VEC_CG_UPDATE) {
+            y[e] += alpha * p[e];
+            const R rn = r[e] - alpha * ap[e];
+            r[e] = rn;
+            part += (double)rn * (double)rn;
+        } else if (OP == VEC_SCALE_COPY) {
+            y[e] = x[e] * scale;
+        } else if (OP == VEC_DOT) {
+            part += (double)x[e] * (double)y[e];
+        } else if (OP == VEC_FB_PROX) {
+            const R v = x[e] - gamma * y[e] - gamma * lam;
+            x[e] = v > R(0) ? v : R(0);
+        } else if (OP == VEC_NORM) {
+            part += (double)x[e] * (double)x[e];
+        }
+    }
+    if (OP == VEC_CG_INIT || OP == VEC_CG_UPDATE || OP == VEC_DOT || OP == VEC_NORM) {
+        const double t = block_sum(part, red);
+        if (threadIdx.x == 0) partials[(size_t)b * max_partials + kb] = t;
+    }
+}
+
+hipError_t launch_vec(bool dbl, int op, int n_band, int64_t P, double *partials, int max_partials,
+                      const double *scal, void *x, void *y, void *r, void *p, const void *ap, double gamma,
+                      double lam, hipStream_t s) {
+    const int nblk = vec_partials_per_band(P);
+    const int nb = n_band * nblk;
+#define VEC_CASE(T, OPV)                                                                                    \
+    case OPV:                                                                                               \
+        PFB_LAUNCH((vec_kernel<T, OPV>), nb, 0, s, P, nblk, partials, max_partials, scal, (T *)x, (T *)y, \
+                   (T *)r, (T *)p, (const T *)ap, (T)gamma, (T)lam);                                       \
+        break;
+    if (dbl) {
+        switch (op) {
+            VEC_CASE(double, VEC_CG_INIT)
+            VEC_CASE(double, VEC_CG_UPDATE)
+            VEC_CASE(double, VEC_SCALE_COPY)
+            VEC_CASE(double, VEC_DOT)
+            VEC_CASE(double, VEC_FB_PROX)
+            VEC_CASE(double, VEC_NORM)
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (op) {
+            VEC_CASE(float, VEC_CG_INIT)
+            VEC_CASE(float, VEC_CG_UPDATE)
+            VEC_CASE(float, VEC_SCALE_COPY)
+            VEC_CASE(float, VEC_DOT)
+            VEC_CASE(float, VEC_FB_PROX)
+            VEC_CASE(float, VEC_NORM)
+            default: return hipErrorInvalidValue;
+        }
+    }
+#undef VEC_CASE
+    return hipSuccess;
+}
+
+// One workgroup per band sums that band's partials (fixed order) and updates
+// the band's scalars.
+__global__ __launch_bounds__(kThreads) void reduce_kernel(int op, const double *partials, int n_part,
+                                                          int max_partials, double *scal) {
+    __shared__ double red[kThreads / 64];
+    const int b = blockIdx.x;
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n_part; k += kThreads) v += partials[(size_t)b * max_partials + k];
+    const double t = block_sum(v, red);
+    if (threadIdx.x != 0) return;
+    double *sc = scal + b * 8;
+    switch (op) {
+        case RED_SET_RR:
+            sc[S_RR] = t;
+            sc[S_BETA] = 0.0;
+            break;
+        case RED_ALPHA:
+            sc[S_PAP] = t;
+            sc[S_ALPHA] = (t > 0.0 && sc[S_RR] > 0.0) ? sc[S_RR] / t : 0.0;
+            break;
+        case RED_BETA:
+            sc[S_BETA] = sc[S_RR] > 0.0 ? t / sc[S_RR] : 0.0;
+            sc[S_RR] = t;
+            break;
+        case RED_INV_SQRT:
+            sc[S_SCALE] = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+            break;
+        case RED_LAMBDA:
+            sc[S_LAMBDA] = t;
+            break;
+        default:
+            sc[S_TMP] = t;
+            break;
+    }
+}
+
+hipError_t launch_reduce(int op, int n_band, const double *partials, int n_part, int max_partials, double *scal,
+                         hipStream_t s) {
+    PFB_LAUNCH(reduce_kernel, n_band, 0, s, op, partials, n_part, max_partials, scal);
+    return hipSuccess;
+}
+
+__global__ void copy_scalar_kernel(int n_band, const double *scal, int slot, double *dst) {
+    const int b = threadIdx.x;
+    if (b < n_band) dst[b] = scal[b * 8 + slot];
+}
+hipError_t launch_copy_scalar(int n_band, const double *scal, int slot, double *dst, hipStream_t s) {
+    for (int b0 = 0; b0 < n_band; b0 += kThreads) {
+        PFB_LAUNCH(copy_scalar_kernel, 1, 0, s, n_band - b0, scal + (size_t)b0 * 8, slot, dst + b0);
+    }
+    return hipSuccess;
+}
+
+}  // namespace pfb

@@ -1,0 +1,201 @@
+"""Python binding of the pfb C ABI: one ``Plan`` per imaging problem.
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of every operator runs in the library's own kernels.
+The names follow ``include/pfb.h`` (and through it the paper's Section 2).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+@dataclass
+class Options:
+    precision: str = "fp32"     # "fp32" or "fp64"
+    support: int = 0            # ES kernel support W (0 = default: 7 fp32, 13 fp64)
+    tile: int = 0               # uv tile side (0 = default: 32 fp32, 8 fp64)
+    flat: bool = False          # drop the w term and 1/n (w = 0, n = 1)
+    band_batch: int = 0         # bands whose w-planes are resident together (0 = all that fit)
+    chunk: int = 0              # visibilities per work item (0 = 4096)
+
+    def to_c(self) -> _lib.PfbOptions:
+        o = _lib.PfbOptions()
+        o.precision = _lib.PFB_FP64 if self.precision == "fp64" else _lib.PFB_FP32
+        o.support = int(self.support)
+        o.oversample = 2.0
+        o.tile = int(self.tile)
+        o.flat = int(bool(self.flat))
+        o.band_batch = int(self.band_batch)
+        o.chunk = int(self.chunk)
+        return o
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Plan:
+    """Holds one problem's plan and its device workspace (a torch uint8 tensor).
+
+    Inputs (device tensors): uvw float64 [n_row, 3] metres; weight float32/float64
+    [n_row, n_chan]; flag uint8 [n_row, n_chan] or None.  Host arrays: freq
+    float64 [n_chan] Hz, chan_band int32 [n_chan].  The plan keeps references to
+    the device tensors (the library borrows them)."""
+
+    def __init__(self, uvw, freq, weight, flag, chan_band, n_band, nx, ny, cellx, celly,
+                 options: Options | None = None):
+        self.lib = _lib.load()
+        self.opt = options or Options()
+        self.real = torch.float64 if self.opt.precision == "fp64" else torch.float32
+        self.cplx = torch.complex128 if self.opt.precision == "fp64" else torch.complex64
+        if not (uvw.is_cuda and weight.is_cuda and (flag is None or flag.is_cuda)):
+            raise ValueError("uvw, weight and flag must be device tensors")
+        self.uvw = uvw.contiguous()
+        self.weight = weight.contiguous()
+        if self.weight.dtype != self.real:
+            raise ValueError(f"weight must be {self.real} for precision {self.opt.precision}")
+        self.flag = None if flag is None else flag.contiguous()
+        self.freq = np.ascontiguousarray(freq, dtype=np.float64)
+        self.chan_band = np.ascontiguousarray(chan_band, dtype=np.int32)
+        self.n_row, self.n_chan = int(self.uvw.shape[0]), int(self.freq.size)
+        self.n_band, self.nx, self.ny = int(n_band), int(nx), int(ny)
+        if tuple(self.weight.shape) != (self.n_row, self.n_chan):
+            raise ValueError("weight shape must be [n_row, n_chan]")
+        prob = _lib.PfbProblem()
+        prob.n_row, prob.n_chan, prob.n_band = self.n_row, self.n_chan, self.n_band
+        prob.chan_band = self.chan_band.ctypes.data
+        prob.freq = self.freq.ctypes.data
+        prob.uvw = self.uvw.data_ptr()
+        prob.weight = self.weight.data_ptr()
+        prob.flag = 0 if self.flag is None else self.flag.data_ptr()
+        prob.nx, prob.ny = self.nx, self.ny
+        prob.cellx, prob.celly = float(cellx), float(celly)
+        self._prob = prob
+        copt = self.opt.to_c()
+        handle = ctypes.c_void_p()
+        _lib.check(self.lib.pfb_plan_create(ctypes.byref(handle), ctypes.byref(prob),
+                                            ctypes.byref(copt), _stream()))
+        self.handle = handle
+        nbytes = ctypes.c_size_t()
+        _lib.check(self.lib.pfb_plan_workspace_size(self.handle, ctypes.byref(nbytes)))
+        self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8,
+                                     device=self.uvw.device)
+        _lib.check(self.lib.pfb_plan_set_workspace(self.handle, _ptr(self.workspace),
+                                                   self.workspace.numel(), _stream()))
+
+    @classmethod
+    def from_problem(cls, prob, device="cuda", options: Options | None = None):
+        """Build from a ``synth.Problem`` (host numpy arrays)."""
+        options = options or Options()
+        real = torch.float64 if options.precision == "fp64" else torch.float32
+        uvw = torch.as_tensor(prob.uvw, dtype=torch.float64, device=device)
+        weight = torch.as_tensor(np.asarray(prob.weight), device=device).to(real)
+        flag = None if prob.flag is None else torch.as_tensor(prob.flag, dtype=torch.uint8, device=device)
+        return cls(uvw, prob.freq, weight, flag, prob.chan_band, prob.n_band, prob.nx, prob.ny,
+                   prob.cellx, prob.celly, options)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.pfb_plan_destroy(h)
+            self.handle = None
+
+    # -- description ------------------------------------------------------------------
+    def info(self) -> dict:
+        inf = _lib.PfbPlanInfo()
+        _lib.check(self.lib.pfb_plan_get_info(self.handle, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in inf._fields_}
+
+    # -- tensors ----------------------------------------------------------------------
+    def image(self, side_factor: int = 1) -> torch.Tensor:
+        return torch.empty((self.n_band, side_factor * self.nx, side_factor * self.ny),
+                           dtype=self.real, device=self.uvw.device)
+
+    def vis(self) -> torch.Tensor:
+        return torch.empty((self.n_row, self.n_chan), dtype=self.cplx, device=self.uvw.device)
+
+    def _chk(self, t: torch.Tensor, shape, dtype):
+        if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"expected contiguous device tensor {dtype} {tuple(shape)}, "
+                             f"got {t.dtype} {tuple(t.shape)}")
+
+    # -- operators (eqs. 1-8 of the paper, see include/pfb.h) ----------------------------
+    def grid(self, vis: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Dirty image I^d = R^dagger Sigma^-1 V."""
+        self._chk(vis, (self.n_row, self.n_chan), self.cplx)
+        out = self.image() if out is None else out
+        self._chk(out, (self.n_band, self.nx, self.ny), self.real)
+        _lib.check(self.lib.pfb_grid(self.handle, _ptr(vis), _ptr(out), _lib.PFB_GRID_DIRTY, _stream()))
+        return out
+
+    def make_psf(self, out: torch.Tensor | None = None, want_image: bool = True):
+        """PSF on the 2nx x 2ny grid; also makes the resident PSF spectrum."""
+        if want_image:
+            out = self.image(2) if out is None else out
+            self._chk(out, (self.n_band, 2 * self.nx, 2 * self.ny), self.real)
+        _lib.check(self.lib.pfb_grid(self.handle, None, _ptr(out if want_image else None),
+                                     _lib.PFB_GRID_PSF, _stream()))
+        return out
+
+    def degrid(self, image: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Model visibilities V = R x."""
+        self._chk(image, (self.n_band, self.nx, self.ny), self.real)
+        out = self.vis() if out is None else out
+        self._chk(out, (self.n_row, self.n_chan), self.cplx)
+        _lib.check(self.lib.pfb_degrid(self.handle, _ptr(image), _ptr(out), _stream()))
+        return out
+
+    def hessian(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """R^dagger Sigma^-1 R x (eq. 3)."""
+        self._chk(x, (self.n_band, self.nx, self.ny), self.real)
+        out = self.image() if out is None else out
+        self._chk(out, (self.n_band, self.nx, self.ny), self.real)
+        _lib.check(self.lib.pfb_hessian(self.handle, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def psf_conv(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """I^psf * x (eq. 4)."""
+        self._chk(x, (self.n_band, self.nx, self.ny), self.real)
+        out = self.image() if out is None else out
+        self._chk(out, (self.n_band, self.nx, self.ny), self.real)
+        _lib.check(self.lib.pfb_psf_conv(self.handle, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def precond_solve(self, g: torch.Tensor, sigma: float, iters: int,
+                      out: torch.Tensor | None = None, resid: torch.Tensor | None = None):
+        """(I^psf * + sigma Id) y = g by `iters` CG steps (eq. 8)."""
+        self._chk(g, (self.n_band, self.nx, self.ny), self.real)
+        out = self.image() if out is None else out
+        self._chk(out, (self.n_band, self.nx, self.ny), self.real)
+        if resid is not None:
+            self._chk(resid, (self.n_band,), torch.float64)
+        _lib.check(self.lib.pfb_precond_solve(self.handle, _ptr(g), _ptr(out), float(sigma), int(iters),
+                                              _ptr(resid), _stream()))
+        return out
+
+    def power_iteration(self, v0: torch.Tensor, iters: int, op: str = "psf") -> torch.Tensor:
+        """Largest eigenvalue per band of I^psf * (op='psf') or the Hessian (op='hessian')."""
+        self._chk(v0, (self.n_band, self.nx, self.ny), self.real)
+        lam = torch.empty(self.n_band, dtype=torch.float64, device=v0.device)
+        _lib.check(self.lib.pfb_power_iteration(self.handle, 0 if op == "psf" else 1, _ptr(v0), int(iters),
+                                                _ptr(lam), _stream()))
+        return lam
+
+    def fb_step(self, dirty: torch.Tensor, x: torch.Tensor, sigma: float, gamma: float, lam: float,
+                cg_iters: int) -> torch.Tensor:
+        """One preconditioned forward-backward step (eqs. 4, 6, 8; l1 + positivity prox); x in place."""
+        self._chk(dirty, (self.n_band, self.nx, self.ny), self.real)
+        self._chk(x, (self.n_band, self.nx, self.ny), self.real)
+        _lib.check(self.lib.pfb_fb_step(self.handle, _ptr(dirty), _ptr(x), float(sigma), float(gamma),
+                                        float(lam), int(cg_iters), _stream()))
+        return x

@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every symbol that include/pfb.h declares;
+argument validation that needs no GPU returns the documented status codes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfb.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:pfb_status|const char \*)\s*(pfb_\w+)\s*\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2101_08072_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_and_binding_agree():
+    from paper_2101_08072_amd import _lib
+    assert _declared() == sorted(_lib.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_last_error(lib):
+    assert b"gfx950" in lib.pfb_version()
+    assert isinstance(lib.pfb_last_error(), bytes)
+
+
+def test_null_arguments_rejected_without_gpu(lib):
+    from paper_2101_08072_amd import _lib
+    assert lib.pfb_plan_create(None, None, None, None) == -1
+    h = ctypes.c_void_p()
+    assert lib.pfb_plan_create(ctypes.byref(h), None, None, None) == -1
+    assert b"NULL" in lib.pfb_last_error()
+    assert lib.pfb_plan_workspace_size(None, None) == -1
+    assert lib.pfb_grid(None, None, None, 0, None) == -1
+    assert lib.pfb_psf_conv(None, None, None, None) == -1
+    assert lib.pfb_plan_destroy(None) == 0
+
+
+def test_shape_validation_without_gpu(lib):
+    """Checks that run before any device access: odd / non-power-of-two sides,
+    bad bands, bad options."""
+    import numpy as np
+    from paper_2101_08072_amd import _lib
+    freq = np.array([1e9, 1.1e9])
+    cb = np.array([0, 0], np.int32)
+    prob = _lib.PfbProblem()
+    prob.n_row, prob.n_chan, prob.n_band = 10, 2, 1
+    prob.chan_band, prob.freq = cb.ctypes.data, freq.ctypes.data
+    prob.uvw, prob.weight = 16, 16            # never dereferenced: validation fails first
+    prob.nx, prob.ny, prob.cellx, prob.celly = 24, 32, 1e-4, 1e-4
+    h = ctypes.c_void_p()
+    opt = _lib.PfbOptions()
+    assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
+    assert b"powers of two" in lib.pfb_last_error()
+    prob.nx = 32
+    opt.support = 3
+    assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
+    opt.support = 0
+    opt.oversample = 1.5
+    assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -4
+    opt.oversample = 0
+    cb[1] = 3
+    assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
+    assert b"chan_band" in lib.pfb_last_error()
