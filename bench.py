@@ -1,0 +1,338 @@
+#!/usr/bin/env python3
+"""Throughput of the pfb-clean hot path on one MI355X.
+
+One step = one pass of the whole hot path over the resident synthetic data of
+the workload (Bester et al. 2021, Section 2):
+    I^d   = R^dagger Sigma^-1 V        (dirty image: grid)
+    V_mod = R x                        (model visibilities: degrid)
+    H x   = R^dagger Sigma^-1 R x      (exact Hessian, eq. 3)
+    x    <- prox(x - gamma U^-1 (I^psf * x - I^d)),  U = I^psf * + sigma Id
+                                       (eqs. 4, 6, 8: PSF convolution + CG solve + prox)
+Each step therefore grids and degrids the active visibilities twice; the value
+is that visibility count per second (grid+degrid visibilities/s).
+
+Prints ONE JSON line.  Plan creation (bucketing), PSF formation and the
+Lipschitz estimate happen before the timed region and are reported apart.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid+degrid visibilities/s at rel-ℓ₂ 1e-5; batched vs plain Hessian apps/s"
+PEAK = {"hbm_GBps": 8000.0, "fp32_vector_TFLOPs": 157.3, "fp64_vector_TFLOPs": 78.6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="single-band-2048")
+    ap.add_argument("--cg-iters", type=int, default=20)
+    ap.add_argument("--support", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# algorithmic work per kernel launch (for the roofline fraction)
+# ---------------------------------------------------------------------------
+
+def kernel_models(info, prob, M, W, csz, rsz):
+    """Algorithmic bytes (HBM-bound passes) or flops (ALU-bound spread/interp)
+    per launch, from the method's data structures moved once each."""
+    nx, ny = prob.nx, prob.ny
+    gx, gy = info["grid_x"], info["grid_y"]
+    nw = info["n_wplanes_max"]
+    P = nx * ny
+    spread_flops = M * (4.0 * W ** 3 + 60.0 * W)
+    return {
+        # ES spread / interpolation: W^3 complex*real multiply-adds + 3W kernel values per visibility
+        "spread_kernel": ("alu", spread_flops),
+        "interp_kernel": ("alu", spread_flops),
+        # row inverse DFT of every w-plane: read plane, write the cropped rows
+        "g1_rows_kernel": ("hbm", nw * gx * (gy + ny) * csz),
+        # column step A (in place on the cropped rows)
+        "colA_kernel": ("hbm", nw * gx * ny * 2 * csz),
+        # column step B + w-phase + accumulation over planes + correction
+        "g3_kernel": ("hbm", nw * gx * ny * csz + 2 * P * rsz),
+        "d2_kernel": ("hbm", nw * gx * ny * 2 * csz),
+        "d3_rows_kernel": ("hbm", nw * gx * (ny + gy) * csz),
+    }
+
+
+def traffic_for(kernel, workload, path):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was taken
+    on the current kernel source."""
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_2101_08072_amd", "csrc", "pfb_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    entry = rec.get(workload, {}).get(kernel)
+    if not entry or entry.get("source_sha") != sha:
+        return None
+    return entry.get("bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on a bounded sample of the same workload
+# ---------------------------------------------------------------------------
+
+def cpu_baseline(prob, vis_host, x_host, M, target_s):
+    import oracle
+    oracle.build()
+    nth = oracle.threads()
+    P = prob.nx * prob.ny
+    rng = np.random.default_rng(7)
+    # grid: whole batches of `nth` pixels (one per thread) against all visibilities
+    t0 = time.perf_counter()
+    oracle.grid(prob, vis_host, pix=rng.integers(0, P, nth))
+    tp = time.perf_counter() - t0
+    npix = nth * max(1, min(16, int(0.5 * target_s / max(tp, 1e-3))))
+    pix = rng.integers(0, P, npix)
+    t0 = time.perf_counter()
+    oracle.grid(prob, vis_host, pix=pix)
+    tg = time.perf_counter() - t0
+    # degrid: visibilities (parallel over visibilities) against the image x
+    active = np.flatnonzero(prob.effective_weight().ravel())
+    t0 = time.perf_counter()
+    oracle.degrid(prob, x_host, sel=active[:4 * nth])
+    tp = time.perf_counter() - t0
+    nvis = 4 * nth * max(1, min(256, int(0.5 * target_s / max(tp, 1e-3))))
+    sel = rng.choice(active, nvis, replace=False)
+    t0 = time.perf_counter()
+    oracle.degrid(prob, x_host, sel=sel)
+    td = time.perf_counter() - t0
+    t_grid_full = tg / npix * P
+    t_degrid_full = td / nvis * M
+    t_step = 2.0 * (t_grid_full + t_degrid_full)   # grid+degrid twice per step (FB part neglected)
+    return {"value": 2.0 * M / t_step, "unit": "visibilities/s", "cores": nth, "kind": "oracle",
+            "sample": (f"FP64 direct sum: grid of {npix} random pixels x {M} visibilities "
+                       f"({tg:.1f} s) and degrid of {nvis} random visibilities x the "
+                       f"{int(np.count_nonzero(x_host))} non-zero pixels of x ({td:.1f} s), scaled to "
+                       f"the full step (2 grids + 2 degrids of all {M} visibilities; the FFT-based "
+                       f"FB/CG part is not counted)"),
+            "seconds": round(tg + td, 2)}
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has "
+              f"no multi-GPU path: bands would be sharded across GPUs with no exchange.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2101_08072_amd import Options, Plan
+
+    dev = "cuda"
+    log(f"workload {args.workload}: generating inputs")
+    prob = synth.workload(args.workload)
+    n_vis = prob.n_row * prob.n_chan
+    x_true = synth.extended_sky(synth.SEED_BASE, prob.n_band, prob.nx, prob.ny)
+
+    opts = Options(precision="fp32", support=args.support, tile=args.tile, chunk=args.chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = Plan.from_problem(prob, device=dev, options=opts)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+    M = int(info["n_vis_active"])
+    log(f"plan: {plan_s:.2f} s, info {info}")
+
+    xg = torch.as_tensor(x_true, device=dev).contiguous()
+    vis = plan.degrid(xg)                      # resident synthetic visibilities V = R x_true
+    t0 = time.perf_counter()
+    plan.make_psf(want_image=False)
+    torch.cuda.synchronize()
+    psf_s = time.perf_counter() - t0
+    v0 = torch.ones_like(xg)
+    lam_max = plan.power_iteration(v0, 20)
+    torch.cuda.synchronize()
+    lam_max = float(lam_max.max().item())
+    sigma, gamma, lam = 1e-3 * lam_max, 1.0, 1e-3
+
+    dirty = plan.image()
+    vmod = plan.vis()
+    hx = plan.image()
+    xk = torch.zeros_like(xg)
+
+    def step():
+        plan.grid(vis, out=dirty)
+        plan.degrid(xg, out=vmod)
+        plan.hessian(xg, out=hx)
+        plan.fb_step(dirty, xk, sigma, gamma, lam, args.cg_iters)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    prof = plan.profile_report()
+    plan.profile(False)
+    value = 2.0 * M / (ms_step * 1e-3)
+    log(f"step {ms_step:.3f} ms (wall {wall / args.steps * 1e3:.3f} ms); {value:.4g} vis/s")
+
+    # per-operator times (separate short loops, HIP events on the same stream)
+    def timed(fn, n=3):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    breakdown = {
+        "grid": timed(lambda: plan.grid(vis, out=dirty)),
+        "degrid": timed(lambda: plan.degrid(xg, out=vmod)),
+        "hessian": timed(lambda: plan.hessian(xg, out=hx)),
+        "psf_conv": timed(lambda: plan.psf_conv(xg, out=hx)),
+        "cg_solve": timed(lambda: plan.precond_solve(dirty, sigma, args.cg_iters, out=hx)),
+    }
+    breakdown["fb_step"] = ms_step - breakdown["grid"] - breakdown["degrid"] - breakdown["hessian"]
+    grid_degrid_vis_s = M / ((breakdown["grid"] + breakdown["degrid"]) * 1e-3)
+    hess_apps = 1e3 / breakdown["hessian"]
+
+    # dominant kernel and its roofline
+    W = info["support"]
+    models = kernel_models(info, prob, M, W, 8, 4)
+    name, (n_launch, tot_ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    avg_ms = tot_ms / n_launch
+    roof = None
+    if name in models:
+        bound, work = models[name]
+        if bound == "hbm":
+            ach = work / (avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
+                    "frac": round(ach / PEAK["hbm_GBps"], 4)}
+        else:
+            ach = work / (avg_ms * 1e-3) / 1e12
+            roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK["fp32_vector_TFLOPs"],
+                    "unit": "TFLOP/s", "frac": round(ach / PEAK["fp32_vector_TFLOPs"], 4)}
+        roof["kernel"] = name
+        roof["avg_ms"] = round(avg_ms, 4)
+        roof["launches_per_step"] = n_launch / args.steps
+        roof["traffic"] = traffic_for(name, args.workload, args.traffic_file)
+    kernels = {k: {"launches_per_step": n / args.steps, "ms_per_step": round(t / args.steps, 4)}
+               for k, (n, t) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    log("kernels:", json.dumps(kernels))
+
+    # plain per-band FP64 path on the same GPU (Hessian applications/s)
+    plain = None
+    if not args.no_fp64_baseline:
+        try:
+            del_list = [dirty, vmod]
+            p64 = Plan.from_problem(prob, device=dev, options=Options(precision="fp64", band_batch=1))
+            x64 = xg.double()
+            h64 = p64.image()
+            t64 = timed(lambda: p64.hessian(x64, out=h64), n=2)
+            plain = {"precision": "fp64", "support": p64.info()["support"], "tile": p64.info()["tile"],
+                     "hessian_ms": round(t64, 3), "hessian_apps_per_s": round(1e3 / t64, 3),
+                     "speedup_fp32_over_fp64": round(t64 / breakdown["hessian"], 2)}
+            h32 = hx
+            plan.hessian(xg, out=h32)
+            torch.cuda.synchronize()
+            a, b = h32.double().cpu().numpy(), h64.cpu().numpy()
+            plain["fp32_vs_fp64_hessian_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            del p64, x64, h64, del_list
+        except Exception as exc:  # report, do not hide
+            plain = {"error": str(exc)}
+        torch.cuda.empty_cache()
+
+    # sampled parity against the FP64 oracle at the full size
+    parity = None
+    vis_host = None
+    if not args.no_parity or not args.no_cpu_baseline:
+        vis_host = vis.cpu().numpy()
+    if not args.no_parity:
+        import oracle
+        rng = np.random.default_rng(3)
+        P = prob.nx * prob.ny
+        pix = rng.integers(0, P, 16)
+        plan.grid(vis, out=dirty)
+        d = dirty.cpu().numpy().ravel()[pix]
+        d_ref = oracle.grid(prob, vis_host, pix=pix)
+        active = np.flatnonzero(prob.effective_weight().ravel())
+        sel = rng.choice(active, 128, replace=False)
+        v_ref = oracle.degrid(prob, x_true.astype(np.float64), sel=sel)
+        xs = np.zeros_like(x_true)
+        idx = rng.integers(0, P, 40)
+        xs[0].ravel()[idx] = rng.uniform(0.1, 1.0, 40)
+        hs = plan.hessian(torch.as_tensor(xs, device=dev)).cpu().numpy().ravel()[pix]
+        hs_ref = oracle.hessian(prob, xs, pix=pix)
+        parity = {"dirty_image": oracle.rel_l2(d, d_ref), "degrid": oracle.rel_l2(vis_host.ravel()[sel], v_ref),
+                  "hessian": oracle.rel_l2(hs, hs_ref),
+                  "sample": "16 random pixels (dirty image, Hessian of a 40-source sparse sky), "
+                            "128 random visibilities (degrid)"}
+        log("parity", parity)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob, vis_host, x_true.astype(np.float64), M, args.cpu_seconds)
+        log("cpu", cpu)
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "visibilities/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded VLA-like earth-rotation uvw, 10% flags, 500 points + 20 blobs)",
+        "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "n_band": prob.n_band,
+                   "n_row": prob.n_row, "n_chan": prob.n_chan, "visibilities": n_vis,
+                   "active_visibilities": M, "cg_iters": args.cg_iters, "support": W,
+                   "tile": info["tile"], "w_planes": info["n_wplanes_max"], "oversample": 2.0},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "grid_degrid_vis_per_s": round(grid_degrid_vis_s, 1),
+        "hessian_apps_per_s": round(hess_apps, 3),
+        "plain_fp64": plain,
+        "breakdown_ms": {k: round(v, 4) for k, v in breakdown.items()},
+        "kernels": kernels,
+        "parity_rel_l2": parity,
+        "setup_s": {"plan": round(plan_s, 3), "psf": round(psf_s, 3)},
+        "lambda_max": lam_max,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,7 +109,8 @@ typedef struct {
     int32_t tile;         /* uv tile side T (power of two, 8..64); default 32 FP32, 8 FP64   */
     int32_t flat;         /* 1: drop the w term and the 1/n factor from R (w = 0, n = 1)     */
     int32_t band_batch;   /* bands whose w-planes are resident at once; default n_band       */
-    int32_t chunk;        /* visibilities per work item before a tile is split; default 4096 */
+    int32_t chunk;        /* bucket entries per work item before a tile is split (>= 64);
+                             default max(4096, entries / 1024)                              */
     int32_t reserved[7];
 } pfb_options;
 
@@ -186,6 +187,15 @@ pfb_status pfb_power_iteration(pfb_plan *plan, int op, const void *v0, int iters
  * dirty, x DEVICE real [n_band][nx][ny]; x is updated in place. */
 pfb_status pfb_fb_step(pfb_plan *plan, const void *dirty, void *x, double sigma, double gamma,
                        double lambda, int cg_iters, hipStream_t stream);
+
+/* Diagnostics: while enabled, every kernel that an operator call on this plan
+ * launches is bracketed by HIP events recorded on that call's stream.  on != 0
+ * discards earlier records and starts recording; on == 0 stops. */
+pfb_status pfb_profile_enable(pfb_plan *plan, int on);
+
+/* Synchronises on the recorded events and writes one line per kernel,
+ * "name launches total_ms\n", into buf (NUL-terminated, truncated to len). */
+pfb_status pfb_profile_report(pfb_plan *plan, char *buf, size_t len);
 
 /* Thread-local text of the last non-OK status (never NULL). */
 const char *pfb_last_error(void);

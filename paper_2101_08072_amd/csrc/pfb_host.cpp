@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -207,8 +208,10 @@ struct pfb_plan {
     bool ws_ready = false, psf_ready = false;
     size_t o_freq = 0, o_cb = 0, o_cheb = 0, o_tw = 0, o_flagged = 0, o_flagcur = 0;
     size_t o_planes = 0, o_t1 = 0, o_t2 = 0, o_vals = 0, o_psfimg = 0;
-    size_t o_t1c = 0, o_t2c = 0, o_psfhat = 0, o_vec = 0, o_partials = 0, o_scal = 0;
+    size_t o_t1c = 0, o_t2c = 0, o_psfhat = 0, o_vec = 0, o_partials = 0, o_scal = 0, o_absmax = 0;
     size_t planes_bytes = 0, t_bytes = 0, vec_bytes = 0;
+    Profiler prof;
+    bool prof_on = false;
     void *p(size_t off) const { return ws + off; }
 };
 
@@ -290,6 +293,14 @@ void build_work(GridderHost &G, const std::vector<unsigned> &counts, int chunk) 
     }
 }
 
+// Installs the plan's launch profiler for the duration of one operator call.
+struct ProfScope {
+    explicit ProfScope(pfb_plan *P) {
+        if (P && P->prof_on) set_thread_profiler(&P->prof);
+    }
+    ~ProfScope() { set_thread_profiler(nullptr); }
+};
+
 pfb_status check_ready(const pfb_plan *P) {
     if (!P) return fail(PFB_EINVAL, "plan is NULL");
     if (!P->ws_ready) return fail(PFB_ESTATE, "pfb_plan_set_workspace has not been called");
@@ -332,8 +343,20 @@ ConvArgs conv_args(const pfb_plan *P) {
     return a;
 }
 
-SpreadLaunch spread_args(const GridderHost &G, int b0, int nbb, int vmode, const void *vis, void *planes) {
+// FP32 path: max |z| of the values to be spread (scale of the fixed-point LDS accumulators)
+pfb_status spread_prepass(pfb_plan *P, int vmode, const void *vis, hipStream_t s) {
+    if (P->dbl) return PFB_OK;
+    float *buf = reinterpret_cast<float *>(P->p(P->o_absmax));
+    hipError_t e = launch_absmax(vmode, vis, P->prob.weight, P->prob.flag, P->prob.n_row * P->prob.n_chan,
+                                 buf + 64, buf, s);
+    if (e != hipSuccess) return fail(PFB_EHIP, "absmax pre-pass: %s", hipGetErrorString(e));
+    return PFB_OK;
+}
+
+SpreadLaunch spread_args(const pfb_plan *P, const GridderHost &G, int b0, int nbb, int vmode, const void *vis,
+                         void *planes) {
     SpreadLaunch s{};
+    s.absmax = reinterpret_cast<const float *>(P->p(P->o_absmax));
     s.g = G.g;
     s.bands = G.d_bands;
     s.work = G.d_gwork + G.gband_start[b0];
@@ -403,7 +426,9 @@ pfb_status hessian_impl(pfb_plan *P, const void *x, void *y, hipStream_t s) {
         xa.image_out = y;
         LAUNCH_OK(launch_degrid_xform(d, xa, s));
         LAUNCH_OK(launch_interp(d, interp_args(G, b0, nbb, 1, P->p(P->o_planes), P->p(P->o_vals)), s));
-        LAUNCH_OK(launch_spread(d, spread_args(G, b0, nbb, 2, P->p(P->o_vals), P->p(P->o_planes)), s));
+        pfb_status st = spread_prepass(P, 2, P->p(P->o_vals), s);
+        if (st) return st;
+        LAUNCH_OK(launch_spread(d, spread_args(P, G, b0, nbb, 2, P->p(P->o_vals), P->p(P->o_planes)), s));
         LAUNCH_OK(launch_grid_xform(d, xa, s));
     }
     return PFB_OK;
@@ -443,13 +468,12 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         return fail(PFB_EINVAL, "support %d outside the range compiled for this precision", opt.support);
     if (opt.oversample == 0.0) opt.oversample = 2.0;
     if (opt.oversample != 2.0) return fail(PFB_EUNSUPPORTED, "only oversampling 2.0 is implemented");
-    if (opt.tile == 0) opt.tile = dbl ? 8 : 32;
+    if (opt.tile == 0) opt.tile = std::max(8, std::min(dbl ? 8 : 32, std::min(pr.nx, pr.ny)));
     if (!is_pow2(opt.tile) || opt.tile < 8 || opt.tile > 64)
         return fail(PFB_EINVAL, "tile must be a power of two in [8, 64]");
     if (2 * std::min(pr.nx, pr.ny) < 2 * opt.tile) return fail(PFB_EINVAL, "tile larger than half the grid");
     if (opt.flat != 0 && opt.flat != 1) return fail(PFB_EINVAL, "flat must be 0 or 1");
-    if (opt.chunk == 0) opt.chunk = 4096;
-    if (opt.chunk < 64) return fail(PFB_EINVAL, "chunk must be >= 64");
+    if (opt.chunk != 0 && opt.chunk < 64) return fail(PFB_EINVAL, "chunk must be >= 64");
     // FFT length limits (LDS-resident rows)
     const int max_row = dbl ? 8192 : 16384;
     if (4 * pr.nx > max_row || 4 * pr.ny > max_row)
@@ -637,7 +661,10 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
             fail(PFB_EUNSUPPORTED, "%lld bucket entries exceed 2^31", (long long)acc);
             return bail(PFB_EUNSUPPORTED);
         }
-        build_work(*G, cnt, opt.chunk);
+        // work-item size: a given chunk, else about 1/1024 of all entries (>= 4096), so
+        // that only tiles far heavier than the average are split
+        const int chunk = opt.chunk ? opt.chunk : (int)std::min<int64_t>(std::max<int64_t>(4096, acc / 1024), 1 << 20);
+        build_work(*G, cnt, chunk);
     }
 
     // grid correction: Chebyshev expansion of the ES kernel's Fourier transform
@@ -718,6 +745,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     }
     P->o_partials = L.take((size_t)nb * P->max_partials * sizeof(double));
     P->o_scal = L.take((size_t)nb * 8 * sizeof(double));
+    P->o_absmax = L.take((kAbsmaxBlocks + 64) * sizeof(float));
     P->ws_bytes = L.off;
     *out = P;
     return PFB_OK;
@@ -826,6 +854,8 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
         }
     }
     HIP_OK(hipMemsetAsync(P->p(P->o_scal), 0, (size_t)pr.n_band * 8 * sizeof(double), s));
+    // per-visibility Hessian values: keep entries that no band batch writes finite
+    HIP_OK(hipMemsetAsync(P->p(P->o_vals), 0, (size_t)pr.n_row * pr.n_chan * 2 * P->rsz, s));
     P->ws_ready = true;
     return PFB_OK;
 }
@@ -835,16 +865,54 @@ pfb_status pfb_plan_destroy(pfb_plan *P) {
     return PFB_OK;
 }
 
+pfb_status pfb_profile_enable(pfb_plan *P, int on) {
+    if (!P) return fail(PFB_EINVAL, "plan is NULL");
+    if (on) P->prof.clear();
+    P->prof_on = on != 0;
+    return PFB_OK;
+}
+
+pfb_status pfb_profile_report(pfb_plan *P, char *buf, size_t len) {
+    if (!P || !buf || len == 0) return fail(PFB_EINVAL, "NULL argument");
+    struct Acc {
+        long long n = 0;
+        double ms = 0.0;
+    };
+    std::map<std::string, Acc> acc;
+    for (auto &r : P->prof.recs) {
+        HIP_OK(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+        std::string name(r.name);
+        size_t a = name.find_first_not_of("( ");
+        size_t b = name.find_first_of("<)", a);
+        name = name.substr(a, b == std::string::npos ? std::string::npos : b - a);
+        acc[name].n += 1;
+        acc[name].ms += ms;
+    }
+    std::string out;
+    for (auto &kv : acc) {
+        char line[256];
+        snprintf(line, sizeof(line), "%s %lld %.6f\n", kv.first.c_str(), kv.second.n, kv.second.ms);
+        out += line;
+    }
+    std::snprintf(buf, len, "%s", out.c_str());
+    return PFB_OK;
+}
+
 pfb_status pfb_grid(pfb_plan *P, const void *vis, void *image, int mode, hipStream_t s) {
+    ProfScope prof_scope(P);
     pfb_status st = check_ready(P);
     if (st) return st;
     const bool d = P->dbl;
     if (mode == PFB_GRID_DIRTY) {
         if (!vis || !image) return fail(PFB_EINVAL, "vis and image must be non-NULL");
         GridderHost &G = P->main;
+        st = spread_prepass(P, 0, vis, s);
+        if (st) return st;
         for (int b0 = 0; b0 < P->prob.n_band; b0 += P->band_batch) {
             const int nbb = std::min(P->band_batch, P->prob.n_band - b0);
-            LAUNCH_OK(launch_spread(d, spread_args(G, b0, nbb, 0, vis, P->p(P->o_planes)), s));
+            LAUNCH_OK(launch_spread(d, spread_args(P, G, b0, nbb, 0, vis, P->p(P->o_planes)), s));
             XformArgs xa = xform_args(P, G, b0, nbb);
             xa.image_out = image;
             LAUNCH_OK(launch_grid_xform(d, xa, s));
@@ -854,9 +922,11 @@ pfb_status pfb_grid(pfb_plan *P, const void *vis, void *image, int mode, hipStre
     if (mode == PFB_GRID_PSF) {
         GridderHost &G = P->psf;
         void *img = image ? image : P->p(P->o_psfimg);
+        st = spread_prepass(P, 1, nullptr, s);
+        if (st) return st;
         for (int b0 = 0; b0 < P->prob.n_band; b0 += P->band_batch) {
             const int nbb = std::min(P->band_batch, P->prob.n_band - b0);
-            LAUNCH_OK(launch_spread(d, spread_args(G, b0, nbb, 1, nullptr, P->p(P->o_planes)), s));
+            LAUNCH_OK(launch_spread(d, spread_args(P, G, b0, nbb, 1, nullptr, P->p(P->o_planes)), s));
             XformArgs xa = xform_args(P, G, b0, nbb);
             xa.image_out = img;
             xa.zero_edge = 1;
@@ -870,6 +940,7 @@ pfb_status pfb_grid(pfb_plan *P, const void *vis, void *image, int mode, hipStre
 }
 
 pfb_status pfb_degrid(pfb_plan *P, const void *image, void *vis, hipStream_t s) {
+    ProfScope prof_scope(P);
     pfb_status st = check_ready(P);
     if (st) return st;
     if (!image || !vis) return fail(PFB_EINVAL, "image and vis must be non-NULL");
@@ -887,6 +958,7 @@ pfb_status pfb_degrid(pfb_plan *P, const void *image, void *vis, hipStream_t s) 
 }
 
 pfb_status pfb_hessian(pfb_plan *P, const void *x, void *y, hipStream_t s) {
+    ProfScope prof_scope(P);
     pfb_status st = check_ready(P);
     if (st) return st;
     if (!x || !y) return fail(PFB_EINVAL, "x and y must be non-NULL");
@@ -895,6 +967,7 @@ pfb_status pfb_hessian(pfb_plan *P, const void *x, void *y, hipStream_t s) {
 }
 
 pfb_status pfb_psf_conv(pfb_plan *P, const void *x, void *y, hipStream_t s) {
+    ProfScope prof_scope(P);
     pfb_status st = check_ready(P);
     if (st) return st;
     if (!x || !y) return fail(PFB_EINVAL, "x and y must be non-NULL");
@@ -905,6 +978,7 @@ pfb_status pfb_psf_conv(pfb_plan *P, const void *x, void *y, hipStream_t s) {
 
 pfb_status pfb_precond_solve(pfb_plan *P, const void *g, void *y, double sigma, int iters, double *dev_resid,
                              hipStream_t s) {
+    ProfScope prof_scope(P);
     pfb_status st = check_ready(P);
     if (st) return st;
     if (!g || !y) return fail(PFB_EINVAL, "g and y must be non-NULL");
@@ -920,6 +994,7 @@ pfb_status pfb_precond_solve(pfb_plan *P, const void *g, void *y, double sigma, 
 }
 
 pfb_status pfb_power_iteration(pfb_plan *P, int op, const void *v0, int iters, double *dev_lambda, hipStream_t s) {
+    ProfScope prof_scope(P);
     pfb_status st = check_ready(P);
     if (st) return st;
     if (!v0 || !dev_lambda) return fail(PFB_EINVAL, "v0 and dev_lambda must be non-NULL");
@@ -974,6 +1049,7 @@ pfb_status pfb_power_iteration(pfb_plan *P, int op, const void *v0, int iters, d
 
 pfb_status pfb_fb_step(pfb_plan *P, const void *dirty, void *x, double sigma, double gamma, double lambda,
                        int cg_iters, hipStream_t s) {
+    ProfScope prof_scope(P);
     pfb_status st = check_ready(P);
     if (st) return st;
     if (!dirty || !x) return fail(PFB_EINVAL, "dirty and x must be non-NULL");

@@ -5,7 +5,23 @@
 
 #include "pfb_internal.h"
 
+#include <vector>
+
 namespace pfb {
+
+// Records HIP events around each kernel launch of the thread that installed it.
+struct Profiler {
+    struct Rec {
+        const char *name;   // launch expression text, e.g. "(spread_kernel<R, W, ...>)"
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get();
+    void clear();
+    ~Profiler();
+};
+void set_thread_profiler(Profiler *p);
 
 // All launchers return hipSuccess or the launch error; `dbl` selects float64.
 
@@ -27,8 +43,14 @@ struct SpreadLaunch {
     void *planes;         // [band_batch][nwmax][gx][gy]
     int band0;
     int vmode;            // 0 data, 1 unit visibilities, 2 precomputed values
+    const float *absmax;  // FP32 path: device scalar, max |z| over active visibilities
 };
 hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s);
+// FP32 path: absmax = max over unflagged, non-zero-weight entries of |w V| (vmode 0),
+// w (vmode 1) or |values| (vmode 2); partials holds >= kAbsmaxBlocks floats.
+constexpr int kAbsmaxBlocks = 1024;
+hipError_t launch_absmax(int vmode, const void *vis, const void *weight, const uint8_t *flag, int64_t n,
+                         float *partials, float *absmax, hipStream_t s);
 
 struct InterpLaunch {
     GeomDev g;

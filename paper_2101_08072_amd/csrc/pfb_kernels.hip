@@ -36,14 +36,53 @@ static hipError_t set_lds(K kernel, size_t bytes) {
     return hipSuccess;
 }
 
-#define PFB_LAUNCH(kernel, grid, lds, stream, ...)                                   \
+// Optional per-launch timing: HIP events recorded on the launch stream around
+// every kernel while a profiler is installed for the calling thread.
+thread_local Profiler *t_prof = nullptr;
+void set_thread_profiler(Profiler *p) { t_prof = p; }
+
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+void Profiler::clear() {
+    for (auto &r : recs) {
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    recs.clear();
+}
+Profiler::~Profiler() {
+    clear();
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+#define PFB_LAUNCH(kernel, grid, lds, stream, ...) PFB_LAUNCH_NT(kernel, grid, kThreads, lds, stream, __VA_ARGS__)
+
+#define PFB_LAUNCH_NT(kernel, grid, nthreads, lds, stream, ...)                      \
     do {                                                                             \
         hipError_t _e = set_lds(kernel, (lds));                                      \
         if (_e != hipSuccess) return _e;                                             \
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), (lds), stream,        \
+        hipEvent_t _ea = nullptr;                                                    \
+        if (t_prof) {                                                                \
+            _ea = t_prof->get();                                                     \
+            (void)hipEventRecord(_ea, stream);                                       \
+        }                                                                            \
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(nthreads), (lds), stream,        \
                            __VA_ARGS__);                                             \
         _e = hipGetLastError();                                                      \
         if (_e != hipSuccess) return _e;                                             \
+        if (t_prof) {                                                                \
+            hipEvent_t _eb = t_prof->get();                                          \
+            (void)hipEventRecord(_eb, stream);                                       \
+            t_prof->recs.push_back({#kernel, _ea, _eb});                             \
+        }                                                                            \
     } while (0)
 
 __device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
@@ -275,18 +314,32 @@ hipError_t launch_corr1d(bool dbl, int n, int gsize, const double *cheb, int nch
 // ---------------------------------------------------------------------------
 // Each work item owns the T x T core cells of one uv tile for planes [p0, p1).
 // Its bucket lists every visibility whose footprint touches the core (copies
-// included), so every grid cell is accumulated by exactly one workgroup in FP32
-// LDS and written to HBM once, coalesced, with no global atomics and no
-// separate zero fill.  A group of LPV lanes handles one visibility: lane j owns
-// footprint column j and loops over the W rows and the W planes.
+// included), so every grid cell is accumulated by exactly one workgroup and
+// written to HBM once, coalesced, with no global atomics and no separate zero
+// fill.  A group of LPV lanes handles one visibility: lane j owns footprint
+// column j and loops over the W rows and the W planes.
+//
+// FP32 path: gfx950 LDS float atomics run at a small fraction of the integer
+// rate, so the ring accumulates 64-bit fixed point.  With S = 2^30 / max|z|
+// every contribution z phi_u phi_v phi_w (phi <= 1) becomes an exact int32 and
+// the int64 sums are exact; the store converts back with 1/S.
+// FP64 path: the ring holds doubles updated with LDS float atomics.
+constexpr int kTileThreads = 1024;   // 16 waves share one tile's LDS ring
+
+template <typename R> struct SpreadAcc { using T = R; };
+template <> struct SpreadAcc<float> { using T = unsigned long long; };
+
 template <typename R, int W, int LPV, bool FLAT, int VMODE>
-__global__ __launch_bounds__(kThreads) void spread_kernel(SpreadLaunch a) {
+__global__ __launch_bounds__(kTileThreads) void spread_kernel(SpreadLaunch a) {
+    using A = typename SpreadAcc<R>::T;
+    constexpr bool FIX = std::is_same<R, float>::value;
     constexpr int WW = FLAT ? 1 : W;
-    constexpr int NGRP = kThreads / LPV;
+    constexpr int NT = kTileThreads;
+    constexpr int NGRP = NT / LPV;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int T = a.g.T, TT = T * T;
-    R *sre = reinterpret_cast<R *>(smem_raw);
-    R *sim = sre + WW * TT;
+    A *sre = reinterpret_cast<A *>(smem_raw);
+    A *sim = sre + WW * TT;
     const GridWork wk = a.work[blockIdx.x];
     const BandDev bd = a.bands[wk.band];
     const int ntiles = a.g.ntx * a.g.nty;
@@ -296,8 +349,17 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SpreadLaunch a) {
     const R *omega = reinterpret_cast<const R *>(a.omega);
     const cplx<R> *vis = reinterpret_cast<const cplx<R> *>(a.vis);
     cplx<R> *planes = reinterpret_cast<cplx<R> *>(a.planes);
+    // fixed-point scale (FP32 path)
+    R fscale = R(1), finv = R(1);
+    if (FIX) {
+        const float am = *a.absmax;
+        if (am > 0.f) {
+            fscale = 1073741824.0f / am;   // 2^30 / max|z|
+            finv = am / 1073741824.0f;
+        }
+    }
 
-    for (int k = threadIdx.x; k < 2 * WW * TT; k += kThreads) sre[k] = R(0);
+    for (int k = threadIdx.x; k < 2 * WW * TT; k += NT) sre[k] = A(0);
     __syncthreads();
 
     const int lane = threadIdx.x % LPV;
@@ -310,8 +372,12 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SpreadLaunch a) {
 
     for (int q = qstart; q < wk.p1; ++q) {
         if (q < bd.nj0) {
-            const int64_t e_beg = a.offsets[keybase + q], e_end = a.offsets[keybase + q + 1];
-            for (int64_t e = e_beg + grp; e < e_end; e += NGRP) {
+            // each lane group takes a contiguous run of the bucket, so the groups
+            // working at the same time sit far apart in it (different baselines)
+            const int64_t b0 = a.offsets[keybase + q], n = a.offsets[keybase + q + 1] - b0;
+            const int64_t per = (n + NGRP - 1) / NGRP;
+            const int64_t e_beg = b0 + min(n, grp * per), e_end = b0 + min(n, (grp + 1) * per);
+            for (int64_t e = e_beg; e < e_end; ++e) {
                 const Rec<R> rec = recs[e];
                 const uint32_t vid = rec.idx & ~kHomeBit;
                 cplx<R> z;
@@ -344,21 +410,28 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SpreadLaunch a) {
                 }
                 const int c = j0 + lane;
                 const bool cok = (lane < W) && (c >= 0) && (c < T);
-                const cplx<R> zv = z * pv;
+                const cplx<R> zv = z * (pv * fscale);
 #pragma unroll
                 for (int k = 0; k < WW; ++k) {
                     const int p = q + k;
                     if (!FLAT && (p < wk.p0 || p >= wk.p1)) continue;
                     const int slot = FLAT ? 0 : p % W;
-                    R *re = sre + slot * TT + c;
-                    R *im = sim + slot * TT + c;
+                    A *re = sre + slot * TT + c;
+                    A *im = sim + slot * TT + c;
                     const cplx<R> zk = zv * ww[k];
 #pragma unroll
                     for (int i = 0; i < W; ++i) {
                         const int row = i0 + i;
                         if (cok && row >= 0 && row < T) {
-                            atomicAdd(re + row * T, zk.re * wu[i]);
-                            atomicAdd(im + row * T, zk.im * wu[i]);
+                            if constexpr (FIX) {
+                                const long long qr = (long long)__float2int_rn(zk.re * wu[i]);
+                                const long long qi = (long long)__float2int_rn(zk.im * wu[i]);
+                                atomicAdd(re + row * T, (unsigned long long)qr);
+                                atomicAdd(im + row * T, (unsigned long long)qi);
+                            } else {
+                                atomicAdd(re + row * T, zk.re * wu[i]);
+                                atomicAdd(im + row * T, zk.im * wu[i]);
+                            }
                         }
                     }
                 }
@@ -368,26 +441,85 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SpreadLaunch a) {
         const int slot = FLAT ? 0 : q % W;
         if (FLAT || q >= wk.p0) {
             cplx<R> *dst = planes + ((size_t)bb * a.g.nwmax + q) * plane_sz + (size_t)tu * T * a.g.gy + (size_t)tv * T;
-            for (int k = threadIdx.x; k < TT; k += kThreads) {
+            for (int k = threadIdx.x; k < TT; k += NT) {
                 const int row = k / T, col = k - row * T;
-                dst[(size_t)row * a.g.gy + col] = cplx<R>{sre[slot * TT + k], sim[slot * TT + k]};
+                cplx<R> v;
+                if constexpr (FIX) {
+                    v = cplx<R>{(R)((double)(long long)sre[slot * TT + k] * (double)finv),
+                                (R)((double)(long long)sim[slot * TT + k] * (double)finv)};
+                } else {
+                    v = cplx<R>{sre[slot * TT + k], sim[slot * TT + k]};
+                }
+                dst[(size_t)row * a.g.gy + col] = v;
             }
         }
-        for (int k = threadIdx.x; k < TT; k += kThreads) {
-            sre[slot * TT + k] = R(0);
-            sim[slot * TT + k] = R(0);
+        for (int k = threadIdx.x; k < TT; k += NT) {
+            sre[slot * TT + k] = A(0);
+            sim[slot * TT + k] = A(0);
         }
         __syncthreads();
     }
 }
 
+// max |z| over active visibilities (FP32 path): per-block maxima, then one block
+__global__ __launch_bounds__(kThreads) void absmax_blocks_kernel(int vmode, const cplx<float> *vis,
+                                                                 const float *weight, const uint8_t *flag,
+                                                                 int64_t n, float *partials) {
+    __shared__ float red[kThreads / 64];
+    float m = 0.f;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
+        const float w = weight[e];
+        if (!(w > 0.f) || (flag && flag[e])) continue;
+        float v;
+        if (vmode == 1) {
+            v = w;
+        } else {
+            const cplx<float> z = vis[e];
+            v = sqrtf(z.re * z.re + z.im * z.im) * (vmode == 0 ? w : 1.f);
+        }
+        m = fmaxf(m, v);
+    }
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < kThreads / 64; ++k) t = fmaxf(t, red[k]);
+        partials[blockIdx.x] = t;
+    }
+}
+__global__ __launch_bounds__(kThreads) void absmax_final_kernel(const float *partials, int n, float *out) {
+    __shared__ float red[kThreads / 64];
+    float m = 0.f;
+    for (int k = threadIdx.x; k < n; k += kThreads) m = fmaxf(m, partials[k]);
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < kThreads / 64; ++k) t = fmaxf(t, red[k]);
+        // margin so that rounding in z * phi * S never exceeds 2^31 - 1
+        out[0] = t * 1.0001f;
+    }
+}
+hipError_t launch_absmax(int vmode, const void *vis, const void *weight, const uint8_t *flag, int64_t n,
+                         float *partials, float *absmax, hipStream_t s) {
+    int64_t nb = (n + kThreads - 1) / kThreads;
+    if (nb > kAbsmaxBlocks) nb = kAbsmaxBlocks;
+    if (nb < 1) nb = 1;
+    PFB_LAUNCH(absmax_blocks_kernel, nb, 0, s, vmode, (const cplx<float> *)vis, (const float *)weight, flag, n,
+               partials);
+    PFB_LAUNCH(absmax_final_kernel, 1, 0, s, partials, (int)nb, absmax);
+    return hipSuccess;
+}
+
 template <typename R, int W, int LPV>
 static hipError_t spread_w(const SpreadLaunch &a, hipStream_t s) {
     const bool flat = a.g.flat;
-    const size_t lds = 2 * (size_t)(flat ? 1 : W) * a.g.T * a.g.T * sizeof(R);
+    const size_t lds = 2 * (size_t)(flat ? 1 : W) * a.g.T * a.g.T * sizeof(typename SpreadAcc<R>::T);
 #define SPREAD_CASE(FL, VM)                                                         \
     if (flat == FL && a.vmode == VM) {                                              \
-        PFB_LAUNCH((spread_kernel<R, W, LPV, FL, VM>), a.n_work, lds, s, a);        \
+        PFB_LAUNCH_NT((spread_kernel<R, W, LPV, FL, VM>), a.n_work, kTileThreads, lds, s, a); \
         return hipSuccess;                                                          \
     }
     SPREAD_CASE(false, 0)
@@ -416,9 +548,10 @@ hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s) {
 // tile; lanes of a group own footprint columns and the partial sums are
 // reduced across the group with lane shuffles.
 template <typename R, int W, int LPV, bool FLAT, int OMODE>
-__global__ __launch_bounds__(kThreads) void interp_kernel(InterpLaunch a) {
+__global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
     constexpr int WW = FLAT ? 1 : W;
-    constexpr int NGRP = kThreads / LPV;
+    constexpr int NT = kTileThreads;
+    constexpr int NGRP = NT / LPV;
     constexpr int H = (W - 1) / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *ring = reinterpret_cast<cplx<R> *>(smem_raw);
@@ -438,7 +571,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(InterpLaunch a) {
     auto load_plane = [&](int p, int slot) {
         const cplx<R> *P = pbase + (size_t)p * plane_sz;
         cplx<R> *dst = ring + slot * SS;
-        for (int k = threadIdx.x; k < SS; k += kThreads) {
+        for (int k = threadIdx.x; k < SS; k += NT) {
             const int aa = k / S, cc = k - aa * S;
             const int gi = wrapi(ox + aa, gx), gj = wrapi(oy + cc, gy);
             dst[k] = P[(size_t)gi * gy + gj];
@@ -458,7 +591,9 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(InterpLaunch a) {
     for (int q = wk.q0; q <= wk.q1; ++q) {
         const int64_t lo = max((int64_t)wk.e0, a.offsets[keybase + q]);
         const int64_t hi = min((int64_t)wk.e1, a.offsets[keybase + q + 1]);
-        for (int64_t e = lo + grp; e < hi; e += NGRP) {
+        const int64_t n = max(hi - lo, (int64_t)0), per = (n + NGRP - 1) / NGRP;
+        const int64_t e_end = lo + min(n, (grp + 1) * per);
+        for (int64_t e = lo + min(n, grp * per); e < e_end; ++e) {
             const Rec<R> rec = recs[e];
             if (!(rec.idx & kHomeBit)) continue;
             const int i0 = (int)dev_floor(rec.fu - hw) + 1;
@@ -528,7 +663,7 @@ static hipError_t interp_w(const InterpLaunch &a, hipStream_t s) {
     const size_t lds = (size_t)(flat ? 1 : W) * S * S * sizeof(cplx<R>);
 #define INTERP_CASE(FL, OM)                                                         \
     if (flat == FL && a.omode == OM) {                                              \
-        PFB_LAUNCH((interp_kernel<R, W, LPV, FL, OM>), a.n_work, lds, s, a);        \
+        PFB_LAUNCH_NT((interp_kernel<R, W, LPV, FL, OM>), a.n_work, kTileThreads, lds, s, a); \
         return hipSuccess;                                                          \
     }
     INTERP_CASE(false, 0)

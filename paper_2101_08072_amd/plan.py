@@ -116,6 +116,21 @@ class Plan:
         _lib.check(self.lib.pfb_plan_get_info(self.handle, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in inf._fields_}
 
+    # -- diagnostics -------------------------------------------------------------------
+    def profile(self, on: bool):
+        """Record HIP events around every kernel launched by this plan's operator calls."""
+        _lib.check(self.lib.pfb_profile_enable(self.handle, int(bool(on))))
+
+    def profile_report(self) -> dict:
+        """{kernel name: (launches, total ms)} for the recorded launches (synchronises)."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        _lib.check(self.lib.pfb_profile_report(self.handle, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, n, ms = line.split()
+            out[name] = (int(n), float(ms))
+        return out
+
     # -- tensors ----------------------------------------------------------------------
     def image(self, side_factor: int = 1) -> torch.Tensor:
         return torch.empty((self.n_band, side_factor * self.nx, side_factor * self.ny),

@@ -256,3 +256,39 @@ def test_error_paths():
     wide = synth.Problem(**{**prob.__dict__, "cellx": 0.2, "celly": 0.2})
     with pytest.raises(PfbError, match="PFB_EINVAL"):
         make_plan(wide, "fp32")
+
+
+# --------------------------------------------------------------------------
+# four-step column transforms (grid side > 512) and four-step PSF convolution
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_four_step_sizes_sampled(prec):
+    """512 x 256 image: operator grid 1024 x 512 and PSF-convolution columns of
+    1024 use the two-pass column transforms; outputs checked on samples."""
+    R, C = _dtypes(prec)
+    prob = synth.tiny_problem(seed=95, nx=512, ny=256, n_row=1500, freqs=(1.0e9, 1.2e9),
+                              cell_arcsec=8.0, w_frac=0.3, flag_frac=0.05)
+    rng = np.random.default_rng(96)
+    vis = rng.normal(size=(prob.n_row, prob.n_chan)) + 1j * rng.normal(size=(prob.n_row, prob.n_chan))
+    x = np.zeros((1, 512, 256))
+    x[0, rng.integers(0, 512, 30), rng.integers(0, 256, 30)] = rng.uniform(0.1, 1, 30)
+    x[0, 200:260, 100:150] += rng.normal(size=(60, 50))
+    plan = make_plan(prob, prec)
+    say(f"four-step {prec}: info {plan.info()}")
+    pix = rng.integers(0, 512 * 256, 300)
+    d = host(plan.grid(to_dev(vis, C))).ravel()[pix]
+    assert rel(d, oracle.grid(prob, vis, pix=pix)) < TOL[prec]
+    active = np.flatnonzero(prob.effective_weight().ravel())
+    sel = rng.choice(active, 300, replace=False)
+    v = host(plan.degrid(to_dev(x, R))).ravel()[sel]
+    assert rel(v, oracle.degrid(prob, x, sel=sel)) < TOL[prec]
+    h = host(plan.hessian(to_dev(x, R))).ravel()[pix]
+    assert rel(h, oracle.hessian(prob, x, pix=pix)) < TOL[prec]
+    psf = host(plan.make_psf())
+    ppix = rng.integers(0, 4 * 512 * 256, 300)
+    assert rel(psf.ravel()[ppix], oracle.psf(prob, pix=ppix)) < TOL[prec]
+    # convolution with the GPU's own PSF against the library convolution in FP64
+    xr = rng.normal(size=(1, 512, 256))
+    y = host(plan.psf_conv(to_dev(xr, R)))
+    assert rel(y, oracle.psf_conv(psf.astype(np.float64), xr)) < TOL[prec]
