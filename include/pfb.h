@@ -188,6 +188,23 @@ pfb_status pfb_power_iteration(pfb_plan *plan, int op, const void *v0, int iters
 pfb_status pfb_fb_step(pfb_plan *plan, const void *dirty, void *x, double sigma, double gamma,
                        double lambda, int cg_iters, hipStream_t stream);
 
+/* hipGraph capture of forward-backward iterations (for launch-bound loops).
+ * Captures `n_steps` consecutive pfb_fb_step(plan, dirty, x, sigma, gamma, lambda,
+ * cg_iters) calls into one instantiated HIP graph.  `stream` must be a
+ * non-default stream; it is used only during capture.  The graph reads and
+ * writes the same device buffers on every launch (x is updated in place) and
+ * contains no memset or host work; the plan's PSF spectrum must exist.  The
+ * graph borrows the plan, its workspace, dirty and x: keep them alive and do not
+ * run other calls on this plan concurrently with a launch. */
+typedef struct pfb_graph pfb_graph;
+pfb_status pfb_fb_graph_create(pfb_plan *plan, const void *dirty, void *x, double sigma, double gamma,
+                               double lambda, int cg_iters, int n_steps, hipStream_t stream,
+                               pfb_graph **graph);
+/* Launches the captured iterations on `stream` (asynchronous). */
+pfb_status pfb_graph_launch(pfb_graph *graph, hipStream_t stream);
+/* Frees the graph (NULL accepted). */
+pfb_status pfb_graph_destroy(pfb_graph *graph);
+
 /* Diagnostics: while enabled, every kernel that an operator call on this plan
  * launches is bracketed by HIP events recorded on that call's stream.  on != 0
  * discards earlier records and starts recording; on == 0 stops. */

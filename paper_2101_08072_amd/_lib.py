@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "PFB_OK", -1: "PFB_EINVAL", -2: "PFB_ENOMEM", -3: "PFB_EHIP",
 EXPORTS = ["pfb_plan_create", "pfb_plan_workspace_size", "pfb_plan_set_workspace",
            "pfb_plan_get_info", "pfb_plan_destroy", "pfb_grid", "pfb_degrid", "pfb_hessian",
            "pfb_psf_conv", "pfb_precond_solve", "pfb_power_iteration", "pfb_fb_step",
+           "pfb_fb_graph_create", "pfb_graph_launch", "pfb_graph_destroy",
            "pfb_profile_enable", "pfb_profile_report", "pfb_last_error", "pfb_version"]
 
 
@@ -72,6 +73,9 @@ def load():
         "pfb_precond_solve": [vp, vp, vp, f64, i32, vp, vp],
         "pfb_power_iteration": [vp, i32, vp, i32, vp, vp],
         "pfb_fb_step": [vp, vp, vp, f64, f64, f64, i32, vp],
+        "pfb_fb_graph_create": [vp, vp, vp, f64, f64, f64, i32, i32, vp, ctypes.POINTER(ctypes.c_void_p)],
+        "pfb_graph_launch": [vp, vp],
+        "pfb_graph_destroy": [vp],
         "pfb_profile_enable": [vp, i32],
         "pfb_profile_report": [vp, ctypes.c_char_p, sz],
     }

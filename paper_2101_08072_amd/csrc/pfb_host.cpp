@@ -694,7 +694,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     const size_t csz = 2 * P->rsz;
     const size_t per_band_planes = std::max((size_t)M.g.nwmax * M.g.gx * M.g.gy, (size_t)Q.g.gx * Q.g.gy) * csz;
     if (opt.band_batch == 0) {
-        const size_t budget = (size_t)96 << 30;   // planes + two intermediates
+        const size_t budget = (size_t)160 << 30;  // planes + two intermediates (MI355X: 288 GB HBM)
         while (P->band_batch > 1 && P->band_batch * 2 * per_band_planes > budget) --P->band_batch;
     }
     P->opt.band_batch = P->band_batch;
@@ -862,6 +862,60 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
 
 pfb_status pfb_plan_destroy(pfb_plan *P) {
     delete P;
+    return PFB_OK;
+}
+
+}  // extern "C"
+
+struct pfb_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~pfb_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+extern "C" {
+
+pfb_status pfb_fb_graph_create(pfb_plan *P, const void *dirty, void *x, double sigma, double gamma, double lambda,
+                               int cg_iters, int n_steps, hipStream_t s, pfb_graph **out) {
+    if (!out) return fail(PFB_EINVAL, "graph output pointer is NULL");
+    *out = nullptr;
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!s) return fail(PFB_EINVAL, "capture needs a non-default stream");
+    if (n_steps < 1) return fail(PFB_EINVAL, "n_steps must be >= 1");
+    if (P->prof_on) return fail(PFB_ESTATE, "disable profiling before capturing a graph");
+    if (!P->psf_ready) return fail(PFB_ESTATE, "no PSF spectrum: call pfb_grid with PFB_GRID_PSF first");
+    HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < n_steps && st == PFB_OK; ++k) st = pfb_fb_step(P, dirty, x, sigma, gamma, lambda, cg_iters, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != PFB_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(PFB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    pfb_graph *G = new pfb_graph();
+    G->graph = g;
+    e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        delete G;
+        return fail(PFB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *out = G;
+    return PFB_OK;
+}
+
+pfb_status pfb_graph_launch(pfb_graph *G, hipStream_t s) {
+    if (!G || !G->exec) return fail(PFB_EINVAL, "graph is NULL");
+    HIP_OK(hipGraphLaunch(G->exec, s));
+    return PFB_OK;
+}
+
+pfb_status pfb_graph_destroy(pfb_graph *G) {
+    delete G;
     return PFB_OK;
 }
 

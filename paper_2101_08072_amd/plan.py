@@ -116,6 +116,20 @@ class Plan:
         _lib.check(self.lib.pfb_plan_get_info(self.handle, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in inf._fields_}
 
+    def fb_graph(self, dirty: torch.Tensor, x: torch.Tensor, sigma: float, gamma: float, lam: float,
+                 cg_iters: int, n_steps: int = 1) -> "FbGraph":
+        """Capture `n_steps` FB iterations (eqs. 4, 6, 8 + prox) into a HIP graph; x updated in place."""
+        self._chk(dirty, (self.n_band, self.nx, self.ny), self.real)
+        self._chk(x, (self.n_band, self.nx, self.ny), self.real)
+        cap = torch.cuda.Stream(device=x.device)
+        cap.wait_stream(torch.cuda.current_stream())
+        g = ctypes.c_void_p()
+        _lib.check(self.lib.pfb_fb_graph_create(self.handle, _ptr(dirty), _ptr(x), float(sigma), float(gamma),
+                                                float(lam), int(cg_iters), int(n_steps),
+                                                ctypes.c_void_p(cap.cuda_stream), ctypes.byref(g)))
+        torch.cuda.current_stream().wait_stream(cap)
+        return FbGraph(self, g, (dirty, x))
+
     # -- diagnostics -------------------------------------------------------------------
     def profile(self, on: bool):
         """Record HIP events around every kernel launched by this plan's operator calls."""
@@ -214,3 +228,19 @@ class Plan:
         _lib.check(self.lib.pfb_fb_step(self.handle, _ptr(dirty), _ptr(x), float(sigma), float(gamma),
                                         float(lam), int(cg_iters), _stream()))
         return x
+
+
+class FbGraph:
+    """An instantiated HIP graph of FB iterations (keeps its plan and buffers alive)."""
+
+    def __init__(self, plan: Plan, handle, keep):
+        self.plan, self.handle, self._keep = plan, handle, keep
+
+    def launch(self):
+        _lib.check(self.plan.lib.pfb_graph_launch(self.handle, _stream()))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.plan.lib.pfb_graph_destroy(h)
+            self.handle = None
