@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--band-batch-compare", action="store_true",
+                    help="also time the Hessian with one band per launch (FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
@@ -70,6 +72,7 @@ def kernel_models(info, prob, M, W, csz, rsz):
     return {
         # ES spread / interpolation: W^3 complex*real multiply-adds + 3W kernel values per visibility
         "spread_kernel": ("alu", spread_flops),
+        "spread_run_kernel": ("alu", spread_flops),
         "interp_kernel": ("alu", spread_flops),
         # row inverse DFT of every w-plane: read plane, write the cropped rows
         "g1_rows_kernel": ("hbm", nw * gx * (gy + ny) * csz),
@@ -279,6 +282,19 @@ def main():
             plain = {"error": str(exc)}
         torch.cuda.empty_cache()
 
+    # all bands in one launch vs one band per launch (same FP32 kernels)
+    per_band = None
+    if args.band_batch_compare and prob.n_band > 1:
+        pb = Plan.from_problem(prob, device=dev, options=Options(precision="fp32", band_batch=1,
+                                                                 support=args.support, tile=args.tile))
+        hb = pb.image()
+        t_pb = timed(lambda: pb.hessian(xg, out=hb), n=2)
+        per_band = {"hessian_ms": round(t_pb, 3), "hessian_apps_per_s": round(1e3 / t_pb, 3),
+                    "batched_speedup": round(t_pb / breakdown["hessian"], 3)}
+        del pb, hb
+        torch.cuda.empty_cache()
+        log("one band per launch", per_band)
+
     # sampled parity against the FP64 oracle at the full size
     parity = None
     vis_host = None
@@ -325,6 +341,7 @@ def main():
         "grid_degrid_vis_per_s": round(grid_degrid_vis_s, 1),
         "hessian_apps_per_s": round(hess_apps, 3),
         "plain_fp64": plain,
+        "one_band_per_launch": per_band,
         "breakdown_ms": {k: round(v, 4) for k, v in breakdown.items()},
         "kernels": kernels,
         "parity_rel_l2": parity,

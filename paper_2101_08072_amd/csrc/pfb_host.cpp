@@ -167,7 +167,9 @@ struct GridderHost {
     std::vector<GridWork> gwork;
     std::vector<InterpWork> iwork;
     std::vector<int> gband_start, iband_start;  // per band first work item (n_band + 1)
+    std::vector<int64_t> sort_items;     // [start, count] of every non-empty bucket
     int64_t n_entries = 0;
+    size_t o_sortitems = 0;
     // workspace offsets
     size_t o_bands = 0, o_offsets = 0, o_cursor = 0, o_gwork = 0, o_iwork = 0, o_recs = 0, o_omega = 0;
     size_t o_corr2d = 0, o_corrx = 0, o_corry = 0;
@@ -210,6 +212,7 @@ struct pfb_plan {
     size_t o_planes = 0, o_t1 = 0, o_t2 = 0, o_vals = 0, o_psfimg = 0;
     size_t o_t1c = 0, o_t2c = 0, o_psfhat = 0, o_vec = 0, o_partials = 0, o_scal = 0, o_absmax = 0;
     size_t planes_bytes = 0, t_bytes = 0, vec_bytes = 0;
+    size_t o_sorttmp = 0;   // scratch for the plan-time sort (aliases the w-plane area when it fits)
     Profiler prof;
     bool prof_on = false;
     void *p(size_t off) const { return ws + off; }
@@ -665,6 +668,12 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         // that only tiles far heavier than the average are split
         const int chunk = opt.chunk ? opt.chunk : (int)std::min<int64_t>(std::max<int64_t>(4096, acc / 1024), 1 << 20);
         build_work(*G, cnt, chunk);
+        G->sort_items.clear();
+        for (size_t k2 = 0; k2 < cnt.size(); ++k2)
+            if (cnt[k2]) {
+                G->sort_items.push_back(G->offsets[k2]);
+                G->sort_items.push_back(cnt[k2]);
+            }
     }
 
     // grid correction: Chebyshev expansion of the ES kernel's Fourier transform
@@ -715,6 +724,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         G->o_cursor = L.take((G->offsets.size()) * sizeof(unsigned long long));
         G->o_gwork = L.take(std::max<size_t>(G->gwork.size(), 1) * sizeof(GridWork));
         G->o_iwork = L.take(std::max<size_t>(G->iwork.size(), 1) * sizeof(InterpWork));
+        G->o_sortitems = L.take(std::max<size_t>(G->sort_items.size(), 2) * sizeof(int64_t));
         G->o_recs = L.take(std::max<int64_t>(G->n_entries, 1) * (dbl ? sizeof(Rec<double>) : sizeof(Rec<float>)));
         G->o_omega = L.take(std::max<int64_t>(G->n_entries, 1) * P->rsz);
         if (G->corr2d) {
@@ -730,6 +740,13 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     P->o_planes = L.take(P->planes_bytes);
     P->o_t1 = L.take(P->t_bytes);
     P->o_t2 = L.take(M.cs.n2 > 1 ? P->t_bytes : 256);
+    {
+        const size_t recsz = dbl ? sizeof(Rec<double>) : sizeof(Rec<float>);
+        size_t need = 0;
+        for (GridderHost *G : {&M, &Q})
+            need = std::max(need, (((size_t)G->n_entries * recsz + 255) & ~size_t(255)) + (size_t)G->n_entries * P->rsz);
+        P->o_sorttmp = (L.off - P->o_planes >= need) ? P->o_planes : L.take(need);
+    }
     P->o_vals = L.take((size_t)pr.n_row * pr.n_chan * csz);
     P->o_psfimg = L.take((size_t)nb * 4 * Pimg * P->rsz);
     P->o_t1c = L.take((size_t)nb * 2 * pr.nx * P->ldh * csz);
@@ -826,6 +843,12 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
         if (!G->iwork.empty())
             HIP_OK(hipMemcpyAsync(G->d_iwork, G->iwork.data(), G->iwork.size() * sizeof(InterpWork),
                                   hipMemcpyHostToDevice, s));
+        if (!G->sort_items.empty())
+            HIP_OK(hipMemcpyAsync(P->p(G->o_sortitems), G->sort_items.data(), G->sort_items.size() * sizeof(int64_t),
+                                  hipMemcpyHostToDevice, s));
+        const size_t recsz = d ? sizeof(Rec<double>) : sizeof(Rec<float>);
+        void *tmp_recs = P->p(P->o_sorttmp);
+        void *tmp_om = P->p(P->o_sorttmp + (((size_t)G->n_entries * recsz + 255) & ~size_t(255)));
         BucketArgs ba{};
         ba.g = G->g;
         ba.uvw = pr.uvw;
@@ -837,13 +860,16 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
         ba.n_row = pr.n_row;
         ba.n_chan = pr.n_chan;
         ba.cursor = G->d_cursor;
-        ba.recs = G->d_recs;
-        ba.omega = G->d_omega;
+        ba.recs = tmp_recs;
+        ba.omega = tmp_om;
         if (G == &P->main) {
             ba.flagged = reinterpret_cast<uint32_t *>(P->p(P->o_flagged));
             ba.flag_cursor = reinterpret_cast<unsigned long long *>(P->p(P->o_flagcur));
         }
         LAUNCH_OK(launch_scatter(d, ba, s));
+        LAUNCH_OK(launch_sort(d, tmp_recs, tmp_om, G->d_recs, G->d_omega,
+                              reinterpret_cast<const int64_t *>(P->p(G->o_sortitems)), (int)(G->sort_items.size() / 2),
+                              G->g.T, G->g.W, s));
         const double *cheb = reinterpret_cast<const double *>(P->p(P->o_cheb));
         const int nch = (int)P->cheb.size();
         if (G->corr2d) {

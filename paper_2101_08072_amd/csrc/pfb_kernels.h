@@ -27,6 +27,9 @@ void set_thread_profiler(Profiler *p);
 
 hipError_t launch_count(bool dbl, const BucketArgs &a, hipStream_t s);
 hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s);
+// sorts each bucket (items: [start, count] pairs) by the footprint base cell; src -> dst
+hipError_t launch_sort(bool dbl, const void *src, const void *src_om, void *dst, void *dst_om, const int64_t *items,
+                       int n_items, int T, int W, hipStream_t s);
 hipError_t launch_corr2d(bool dbl, const GeomDev &g, const BandDev *bands, const double *cheb,
                          int ncheb, double xi_max, void *corr, hipStream_t s);
 hipError_t launch_corr1d(bool dbl, int n, int gsize, const double *cheb, int ncheb, double xi_max,

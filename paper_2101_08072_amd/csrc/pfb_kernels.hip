@@ -244,6 +244,71 @@ static hipError_t launch_bucket(bool dbl, const BucketArgs &a, hipStream_t s) {
 hipError_t launch_count(bool dbl, const BucketArgs &a, hipStream_t s) { return launch_bucket<false>(dbl, a, s); }
 hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s) { return launch_bucket<true>(dbl, a, s); }
 
+// Plan-time segmented counting sort: within every (band, tile, w-base-plane)
+// bucket, order entries by the base cell (i0, j0) of their footprint, so that
+// visibilities sharing a footprint sit next to each other (runs).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void sort_kernel(const Rec<R> *src, const R *src_om, Rec<R> *dst, R *dst_om,
+                                                        const int64_t *items, int T, int W) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    unsigned *hist = reinterpret_cast<unsigned *>(smem_raw);
+    __shared__ unsigned part[kThreads];
+    const int KS = T + W - 1, KEYS = KS * KS;
+    const int64_t start = items[2 * blockIdx.x], n = items[2 * blockIdx.x + 1];
+    const R hw = R(0.5) * R(W);
+    auto key_of = [&](const Rec<R> &r) {
+        const int i0 = (int)dev_floor(r.fu - hw) + 1, j0 = (int)dev_floor(r.fv - hw) + 1;
+        const int a = min(max(i0 + W - 1, 0), KS - 1), b = min(max(j0 + W - 1, 0), KS - 1);
+        return a * KS + b;
+    };
+    for (int k = threadIdx.x; k < KEYS; k += kThreads) hist[k] = 0u;
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < n; e += kThreads) atomicAdd(hist + key_of(src[start + e]), 1u);
+    __syncthreads();
+    // exclusive scan of hist: contiguous chunks per thread, then thread totals
+    const int per = (KEYS + kThreads - 1) / kThreads;
+    const int k0 = threadIdx.x * per, k1 = min(KEYS, k0 + per);
+    unsigned s = 0;
+    for (int k = k0; k < k1; ++k) s += hist[k];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned acc = 0;
+        for (int t = 0; t < kThreads; ++t) {
+            const unsigned v = part[t];
+            part[t] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    unsigned acc = part[threadIdx.x];
+    for (int k = k0; k < k1; ++k) {
+        const unsigned v = hist[k];
+        hist[k] = acc;
+        acc += v;
+    }
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < n; e += kThreads) {
+        const Rec<R> r = src[start + e];
+        const unsigned pos = atomicAdd(hist + key_of(r), 1u);
+        dst[start + pos] = r;
+        dst_om[start + pos] = src_om[start + e];
+    }
+}
+
+hipError_t launch_sort(bool dbl, const void *src, const void *src_om, void *dst, void *dst_om, const int64_t *items,
+                       int n_items, int T, int W, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    const size_t lds = (size_t)(T + W - 1) * (T + W - 1) * sizeof(unsigned);
+    if (dbl)
+        PFB_LAUNCH(sort_kernel<double>, n_items, lds, s, (const Rec<double> *)src, (const double *)src_om,
+                   (Rec<double> *)dst, (double *)dst_om, items, T, W);
+    else
+        PFB_LAUNCH(sort_kernel<float>, n_items, lds, s, (const Rec<float> *)src, (const float *)src_om,
+                   (Rec<float> *)dst, (float *)dst_om, items, T, W);
+    return hipSuccess;
+}
+
 // ---------------------------------------------------------------------------
 // grid correction
 // ---------------------------------------------------------------------------
@@ -461,6 +526,207 @@ __global__ __launch_bounds__(kTileThreads) void spread_kernel(SpreadLaunch a) {
     }
 }
 
+// FP32 spread over sorted buckets: one wave per visibility, register
+// accumulation across runs of visibilities that share a footprint.
+//
+// Buckets are sorted by footprint base cell (i0, j0), so consecutive entries
+// often cover the same W x W x W block.  Each wave takes a contiguous part of a
+// bucket; lane (j, k) owns footprint column j and plane q + k and keeps the W
+// row sums of its column in registers; when the base cell changes (or after
+// kRunMax visibilities) the wave adds its block to the LDS ring (64-bit fixed
+// point, ds_add_u64).  Values are pre-scaled by S = 2^26 / max|z|, so a partial
+// sum of at most kRunMax = 31 contributions is below 2^31 in magnitude and
+// converts with one rounding to int32.  The per-visibility quantities (1-D ES
+// weights, z) are computed for 8 visibilities at once, one visibility per
+// 8-lane group, then broadcast with readlane / shuffles.  FLAT (PSF gridder,
+// one plane): lane (j, i) owns cell (i, j) of the footprint.
+constexpr int kRunMax = 31;
+constexpr float kRunScale = 67108864.0f;   // 2^26
+
+__device__ __forceinline__ unsigned long long f2fix(float x) {
+    // |x| < 2^31: round to int32, sign-extend
+    return (unsigned long long)(long long)__float2int_rn(x);
+}
+__device__ __forceinline__ float rdlane(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ int rdlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+template <int W, bool FLAT, int VMODE>
+__global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a) {
+    using R = float;
+    using A = unsigned long long;
+    constexpr int WW = FLAT ? 1 : W;
+    constexpr int NWAVE = kTileThreads / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int T = a.g.T, TT = T * T;
+    A *sre = reinterpret_cast<A *>(smem_raw);
+    A *sim = sre + WW * TT;
+    const GridWork wk = a.work[blockIdx.x];
+    const BandDev bd = a.bands[wk.band];
+    const int ntiles = a.g.ntx * a.g.nty;
+    const int tu = wk.tile / a.g.nty, tv = wk.tile - tu * a.g.nty;
+    const int bb = wk.band - a.band0;
+    const Rec<R> *recs = reinterpret_cast<const Rec<R> *>(a.recs);
+    const R *omega = reinterpret_cast<const R *>(a.omega);
+    const cplx<R> *vis = reinterpret_cast<const cplx<R> *>(a.vis);
+    cplx<R> *planes = reinterpret_cast<cplx<R> *>(a.planes);
+    R fscale = R(1), finv = R(1);
+    {
+        const float am = *a.absmax;
+        if (am > 0.f) {
+            fscale = kRunScale / am;
+            finv = am / kRunScale;
+        }
+    }
+    for (int k = threadIdx.x; k < 2 * WW * TT; k += kTileThreads) sre[k] = A(0);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lj = lane & 7, ls = lane >> 3;         // column j; plane offset k (or row i when FLAT)
+    const bool lact = (lj < W) && (ls < (FLAT ? W : WW));
+    const R beta = (R)a.g.beta, inv_hw = R(2) / R(W), hw = R(0.5) * R(W);
+    const R w0 = (R)bd.w0, dw = (R)bd.dw, sc = (R)bd.sc;
+    const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
+    const int qstart = FLAT ? 0 : max(0, wk.p0 - W + 1);
+    const size_t plane_sz = (size_t)a.g.gx * a.g.gy;
+
+    for (int q = qstart; q < wk.p1; ++q) {
+        if (q < bd.nj0) {
+            const int64_t b0 = a.offsets[keybase + q], n = a.offsets[keybase + q + 1] - b0;
+            const int64_t per = (n + NWAVE - 1) / NWAVE;
+            const int64_t e_beg = b0 + min(n, wv * per), e_end = b0 + min(n, (wv + 1) * per);
+            R acc_re[FLAT ? 1 : W], acc_im[FLAT ? 1 : W];
+#pragma unroll
+            for (int i = 0; i < (FLAT ? 1 : W); ++i) acc_re[i] = acc_im[i] = R(0);
+            int cur = -1, run = 0;
+            auto flush = [&](int base) {
+                const int i0 = (base >> 16) - 64, j0 = (base & 0xffff) - 64;
+                if (!lact) return;
+                const int c = j0 + lj;
+                if (c < 0 || c >= T) return;
+                if (FLAT) {
+                    const int row = i0 + ls;
+                    if (row < 0 || row >= T) return;
+                    atomicAdd(sre + row * T + c, f2fix(acc_re[0]));
+                    atomicAdd(sim + row * T + c, f2fix(acc_im[0]));
+                } else {
+                    const int p = q + ls;
+                    if (p < wk.p0 || p >= wk.p1) return;
+                    A *re = sre + (p % W) * TT + c;
+                    A *im = sim + (p % W) * TT + c;
+#pragma unroll
+                    for (int i = 0; i < W; ++i) {
+                        const int row = i0 + i;
+                        if (row >= 0 && row < T) {
+                            atomicAdd(re + row * T, f2fix(acc_re[i]));
+                            atomicAdd(im + row * T, f2fix(acc_im[i]));
+                        }
+                    }
+                }
+            };
+            // software pipeline: the record of the next batch and the value it
+            // gathers are loaded while the current batch is being accumulated
+            auto load_rec = [&](int64_t eb) {
+                Rec<R> r{R(0), R(0), R(0), 0u};
+                if (eb < e_end) r = recs[eb];
+                return r;
+            };
+            auto load_val = [&](int64_t eb, const Rec<R> &r) {
+                cplx<R> v{R(0), R(0)};
+                if (eb < e_end) {
+                    if (VMODE == 0) {
+                        v = vis[r.idx & ~kHomeBit] * (omega[eb] * fscale);
+                    } else if (VMODE == 1) {
+                        v = cplx<R>{omega[eb] * fscale, R(0)};
+                    } else {
+                        v = vis[r.idx & ~kHomeBit] * fscale;
+                    }
+                }
+                return v;
+            };
+            Rec<R> rec_c = load_rec(e_beg + ls);
+            cplx<R> val_c = load_val(e_beg + ls, rec_c);
+            Rec<R> rec_n = load_rec(e_beg + 8 + ls);
+            for (int64_t e = e_beg; e < e_end; e += 8) {
+                const int nb = (int)min((int64_t)8, e_end - e);
+                // prefetch: value of the next batch, record of the one after
+                const cplx<R> val_n = load_val(e + 8 + ls, rec_n);
+                const Rec<R> rec_nn = load_rec(e + 16 + ls);
+                // batched prologue: group ls handles visibility e + ls, lane lj its 1-D weights
+                R pu = R(0), pv = R(0), pw = R(1), zr = R(0), zi = R(0);
+                int base = 0;
+                if (ls < nb) {
+                    const int i0 = (int)dev_floor(rec_c.fu - hw) + 1;
+                    const int j0 = (int)dev_floor(rec_c.fv - hw) + 1;
+                    base = ((i0 + 64) << 16) | (j0 + 64);
+                    if (lj < W) {
+                        pu = es_kernel<R>(R(i0 + lj) - rec_c.fu, beta, inv_hw);
+                        pv = es_kernel<R>(R(j0 + lj) - rec_c.fv, beta, inv_hw);
+                        if (!FLAT) pw = es_kernel<R>(R(q + lj) - rec_c.fw, beta, inv_hw);
+                    }
+                    cplx<R> z = val_c;
+                    if (VMODE == 0) z = z * cis_cycles<R>((w0 + rec_c.fw * dw) * sc);
+                    zr = z.re;
+                    zi = z.im;
+                }
+                // all shuffles of the batch first (one LDS round trip), then accumulate
+                R wgt[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    wgt[t] = __shfl(pv, t * 8 + lj) * (FLAT ? __shfl(pu, t * 8 + ls) : __shfl(pw, t * 8 + ls));
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    if (t < nb) {
+                        const int src = t * 8;
+                        const int bt = rdlane(base, src);
+                        if (bt != cur || run == kRunMax) {
+                            if (cur >= 0) flush(cur);
+#pragma unroll
+                            for (int i = 0; i < (FLAT ? 1 : W); ++i) acc_re[i] = acc_im[i] = R(0);
+                            cur = bt;
+                            run = 0;
+                        }
+                        ++run;
+                        const R cr = rdlane(zr, src) * wgt[t], ci = rdlane(zi, src) * wgt[t];
+                        if (FLAT) {
+                            acc_re[0] += cr;
+                            acc_im[0] += ci;
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < W; ++i) {
+                                const R u = rdlane(pu, src + i);
+                                acc_re[i] += cr * u;
+                                acc_im[i] += ci * u;
+                            }
+                        }
+                    }
+                }
+                rec_c = rec_n;
+                val_c = val_n;
+                rec_n = rec_nn;
+            }
+            if (cur >= 0) flush(cur);
+        }
+        __syncthreads();
+        const int slot = FLAT ? 0 : q % W;
+        if (FLAT || q >= wk.p0) {
+            cplx<R> *dst = planes + ((size_t)bb * a.g.nwmax + q) * plane_sz + (size_t)tu * T * a.g.gy + (size_t)tv * T;
+            for (int k = threadIdx.x; k < TT; k += kTileThreads) {
+                const int row = k / T, col = k - row * T;
+                dst[(size_t)row * a.g.gy + col] =
+                    cplx<R>{(R)((double)(long long)sre[slot * TT + k] * (double)finv),
+                            (R)((double)(long long)sim[slot * TT + k] * (double)finv)};
+            }
+        }
+        for (int k = threadIdx.x; k < TT; k += kTileThreads) {
+            sre[slot * TT + k] = A(0);
+            sim[slot * TT + k] = A(0);
+        }
+        __syncthreads();
+    }
+}
+
 // max |z| over active visibilities (FP32 path): per-block maxima, then one block
 __global__ __launch_bounds__(kThreads) void absmax_blocks_kernel(int vmode, const cplx<float> *vis,
                                                                  const float *weight, const uint8_t *flag,
@@ -532,11 +798,30 @@ static hipError_t spread_w(const SpreadLaunch &a, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+template <int W>
+static hipError_t spread_run_w(const SpreadLaunch &a, hipStream_t s) {
+    const bool flat = a.g.flat;
+    const size_t lds = 2 * (size_t)(flat ? 1 : W) * a.g.T * a.g.T * sizeof(unsigned long long);
+#define SPREAD_RUN_CASE(FL, VM)                                                                 \
+    if (flat == FL && a.vmode == VM) {                                                          \
+        PFB_LAUNCH_NT((spread_run_kernel<W, FL, VM>), a.n_work, kTileThreads, lds, s, a);       \
+        return hipSuccess;                                                                      \
+    }
+    SPREAD_RUN_CASE(false, 0)
+    SPREAD_RUN_CASE(false, 1)
+    SPREAD_RUN_CASE(false, 2)
+    SPREAD_RUN_CASE(true, 0)
+    SPREAD_RUN_CASE(true, 1)
+    SPREAD_RUN_CASE(true, 2)
+#undef SPREAD_RUN_CASE
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s) {
     if (a.n_work <= 0) return hipSuccess;
     if (dbl)
         return dispatch_int<9, 16>(a.g.W, [&](auto Wc) { return spread_w<double, decltype(Wc)::value, 16>(a, s); });
-    return dispatch_int<4, 8>(a.g.W, [&](auto Wc) { return spread_w<float, decltype(Wc)::value, 8>(a, s); });
+    return dispatch_int<4, 8>(a.g.W, [&](auto Wc) { return spread_run_w<decltype(Wc)::value>(a, s); });
 }
 
 // ---------------------------------------------------------------------------
