@@ -21,6 +21,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -54,6 +55,13 @@ def parse():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 3 times (HBM counter calibration) and exit")
+    ap.add_argument("--write-traffic", nargs=4, default=None,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv output of this bench "
+                         "and of --copy-calibration into per-launch HBM bytes in --traffic-file")
+    ap.add_argument("--copy-mib", type=int, default=2048, help="size used with --copy-calibration")
     return ap.parse_args()
 
 
@@ -85,6 +93,90 @@ def kernel_models(info, prob, M, W, csz, rsz):
     }
 
 
+def kernel_source_sha():
+    src = os.path.join(ROOT, "paper_2101_08072_amd", "csrc", "pfb_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size, the yardstick for the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * 2 ** 20 // 4
+    src = torch.empty(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4}), flush=True)
+
+
+def _pmc_rows(d, counter):
+    """(kernel name, value) per dispatch from rocprofv3's counter_collection csv files."""
+    import csv
+    import glob
+    rows = []
+    for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(fn, newline="") as f:
+            for r in csv.DictReader(f):
+                r = {k.lower(): v for k, v in r.items()}
+                if r.get("counter_name") == counter:
+                    rows.append((r["kernel_name"], float(r["counter_value"])))
+    if not rows:
+        raise SystemExit(f"no {counter} rows under {d}")
+    return rows
+
+
+def _base_name(full):
+    m = re.search(r"pfb::(\w+)", full)
+    return m.group(1) if m else None
+
+
+def write_traffic(dirs, workload, copy_mib, path, min_dispatches):
+    """Per-launch HBM bytes of every library kernel, from one FETCH_SIZE and one
+    WRITE_SIZE pass (KiB per dispatch), each scaled by what the same counter
+    reads for a plain copy of copy_mib MiB.  A kernel's figure is the mean over
+    its template instances that ran at least min_dispatches times (those run in
+    every step), each instance averaged over its dispatches."""
+    fetch, write, cfetch, cwrite = (_pmc_rows(d, c) for d, c in
+                                    zip(dirs, ("FETCH_SIZE", "WRITE_SIZE", "FETCH_SIZE", "WRITE_SIZE")))
+    nbytes = copy_mib * 2 ** 20
+
+    def copy_factor(rows):
+        vals = [v for k, v in rows if "copy" in k.lower()]
+        return nbytes / (max(vals) * 1024.0)
+
+    f_fetch, f_write = copy_factor(cfetch), copy_factor(cwrite)
+    out = {}
+    for key, rows, fac in (("fetch", fetch, f_fetch), ("write", write, f_write)):
+        per_inst = {}
+        for k, v in rows:
+            per_inst.setdefault(k, []).append(v * 1024.0 * fac)
+        for k, vals in per_inst.items():
+            b = _base_name(k)
+            if b is None or len(vals) < min_dispatches:
+                continue
+            e = out.setdefault(b, {"instances": {}})
+            e["instances"].setdefault(k, {})[key] = sum(vals) / len(vals)
+            e["instances"][k]["dispatches"] = len(vals)
+    for b, e in out.items():
+        inst = [v for v in e["instances"].values() if "fetch" in v and "write" in v]
+        e["fetch_bytes_per_launch"] = sum(v["fetch"] for v in inst) / len(inst)
+        e["write_bytes_per_launch"] = sum(v["write"] for v in inst) / len(inst)
+        e["bytes_per_launch"] = e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+        e["source_sha"] = kernel_source_sha()
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        rec = {}
+    rec["copy_calibration"] = {"bytes": nbytes, "fetch_factor": f_fetch, "write_factor": f_write}
+    rec[workload] = out
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    log(f"wrote {path}: copy factors fetch {f_fetch:.4f} write {f_write:.4f}")
+
+
 def traffic_for(kernel, workload, path):
     """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was taken
     on the current kernel source."""
@@ -93,10 +185,8 @@ def traffic_for(kernel, workload, path):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    src = os.path.join(ROOT, "paper_2101_08072_amd", "csrc", "pfb_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     entry = rec.get(workload, {}).get(kernel)
-    if not entry or entry.get("source_sha") != sha:
+    if not entry or entry.get("source_sha") != kernel_source_sha():
         return None
     return entry.get("bytes_per_launch")
 
@@ -151,6 +241,13 @@ def main():
               f"no multi-GPU path: bands would be sharded across GPUs with no exchange.",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.write_traffic:
+        write_traffic(args.write_traffic, args.workload, args.copy_mib, args.traffic_file,
+                      args.steps + args.warmup)
+        return
     import torch
 
     import synth
