@@ -475,6 +475,9 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     if (!is_pow2(opt.tile) || opt.tile < 8 || opt.tile > 64)
         return fail(PFB_EINVAL, "tile must be a power of two in [8, 64]");
     if (2 * std::min(pr.nx, pr.ny) < 2 * opt.tile) return fail(PFB_EINVAL, "tile larger than half the grid");
+    if (gridder_lds_bytes(dbl, opt.support, opt.tile, opt.flat != 0) > kMaxLdsBytes)
+        return fail(PFB_EINVAL, "tile %d with support %d needs %zu bytes of LDS per block (at most %zu)", opt.tile,
+                    opt.support, gridder_lds_bytes(dbl, opt.support, opt.tile, opt.flat != 0), kMaxLdsBytes);
     if (opt.flat != 0 && opt.flat != 1) return fail(PFB_EINVAL, "flat must be 0 or 1");
     if (opt.chunk != 0 && opt.chunk < 64) return fail(PFB_EINVAL, "chunk must be >= 64");
     // FFT length limits (LDS-resident rows)

@@ -48,6 +48,9 @@ struct SpreadLaunch {
     int vmode;            // 0 data, 1 unit visibilities, 2 precomputed values
     const float *absmax;  // FP32 path: device scalar, max |z| over active visibilities
 };
+// LDS bytes per block of the spread and interpolation kernels (the larger)
+size_t gridder_lds_bytes(bool dbl, int W, int T, bool flat);
+constexpr size_t kMaxLdsBytes = 160 * 1024;
 hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s);
 // FP32 path: absmax = max over unflagged, non-zero-weight entries of |w V| (vmode 0),
 // w (vmode 1) or |values| (vmode 2); partials holds >= kAbsmaxBlocks floats.

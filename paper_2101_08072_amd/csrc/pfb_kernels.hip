@@ -536,32 +536,47 @@ __global__ __launch_bounds__(kTileThreads) void spread_kernel(SpreadLaunch a) {
 // kRunMax visibilities) the wave adds its block to the LDS ring (64-bit fixed
 // point, ds_add_u64).  Values are pre-scaled by S = 2^26 / max|z|, so a partial
 // sum of at most kRunMax = 31 contributions is below 2^31 in magnitude and
-// converts with one rounding to int32.  The per-visibility quantities (1-D ES
-// weights, z) are computed for 8 visibilities at once, one visibility per
-// 8-lane group, then broadcast with readlane / shuffles.  FLAT (PSF gridder,
-// one plane): lane (j, i) owns cell (i, j) of the footprint.
+// converts to int32 with one truncation (zero-mean for values of either sign,
+// relative size 2^-26 for one-signed sums).  The per-visibility quantities
+// (1-D ES weights, z) are computed for 8 visibilities at once, one visibility
+// per 8-lane group, then broadcast with readlane / shuffles.  The wave index,
+// the bucket range and the run state are wave-uniform (scalar registers).
+// FLAT (PSF gridder, one plane): lane (j, i) owns cell (i, j) of the footprint.
 constexpr int kRunMax = 31;
 constexpr float kRunScale = 67108864.0f;   // 2^26
+// LDS stride of one plane slot, in 64-bit words.  A flush touches 7 columns of
+// 7 plane slots at once; padding each slot by 2 words spreads those 49
+// addresses over the 16 two-bank pairs (at most 4 per pair instead of 7).
+__host__ __device__ constexpr int run_slot_stride(int T, bool flat) { return flat ? T * T : T * T + 2; }
 
 __device__ __forceinline__ unsigned long long f2fix(float x) {
-    // |x| < 2^31: round to int32, sign-extend
-    return (unsigned long long)(long long)__float2int_rn(x);
+    // |x| < 2^31: truncate to int32, sign-extend
+    return (unsigned long long)(long long)(int)x;
 }
 __device__ __forceinline__ float rdlane(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 __device__ __forceinline__ int rdlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
+// ES kernel with the hardware square root and base-2 exponential (about one
+// ulp each); beta2 = beta * log2(e).
+__device__ __forceinline__ float es_kernel_fast(float z, float beta2, float inv_hw) {
+    const float t = z * inv_hw;
+    const float a = 1.f - t * t;
+    return a > 0.f ? __builtin_amdgcn_exp2f(beta2 * (__builtin_amdgcn_sqrtf(a) - 1.f)) : 0.f;
+}
+
 template <int W, bool FLAT, int VMODE>
 __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a) {
     using R = float;
     using A = unsigned long long;
     constexpr int WW = FLAT ? 1 : W;
+    constexpr int NACC = FLAT ? 1 : W;
     constexpr int NWAVE = kTileThreads / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int T = a.g.T, TT = T * T;
+    const int T = a.g.T, TT = T * T, TS = run_slot_stride(T, FLAT);
     A *sre = reinterpret_cast<A *>(smem_raw);
-    A *sim = sre + WW * TT;
+    A *sim = sre + WW * TS;
     const GridWork wk = a.work[blockIdx.x];
     const BandDev bd = a.bands[wk.band];
     const int ntiles = a.g.ntx * a.g.nty;
@@ -579,13 +594,14 @@ __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a
             finv = am / kRunScale;
         }
     }
-    for (int k = threadIdx.x; k < 2 * WW * TT; k += kTileThreads) sre[k] = A(0);
+    for (int k = threadIdx.x; k < 2 * WW * TS; k += kTileThreads) sre[k] = A(0);
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lj = lane & 7, ls = lane >> 3;         // column j; plane offset k (or row i when FLAT)
-    const bool lact = (lj < W) && (ls < (FLAT ? W : WW));
-    const R beta = (R)a.g.beta, inv_hw = R(2) / R(W), hw = R(0.5) * R(W);
+    const bool lact = (lj < W) && (ls < W);
+    const R beta2 = (R)(a.g.beta * 1.4426950408889634), inv_hw = R(2) / R(W), hw = R(0.5) * R(W);
     const R w0 = (R)bd.w0, dw = (R)bd.dw, sc = (R)bd.sc;
     const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
     const int qstart = FLAT ? 0 : max(0, wk.p0 - W + 1);
@@ -596,31 +612,46 @@ __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a
             const int64_t b0 = a.offsets[keybase + q], n = a.offsets[keybase + q + 1] - b0;
             const int64_t per = (n + NWAVE - 1) / NWAVE;
             const int64_t e_beg = b0 + min(n, wv * per), e_end = b0 + min(n, (wv + 1) * per);
-            R acc_re[FLAT ? 1 : W], acc_im[FLAT ? 1 : W];
+            // this lane's LDS word for footprint cell (row 0, column 0) of a base at (0, 0)
+            bool lane_ok;
+            int lane_off;
+            if (FLAT) {
+                lane_ok = lact;
+                lane_off = ls * T + lj;
+            } else {
+                const int p = q + ls;
+                lane_ok = lact && p >= wk.p0 && p < wk.p1;
+                lane_off = (p % W) * TS + lj;
+            }
+            R acc_re[NACC], acc_im[NACC];
 #pragma unroll
-            for (int i = 0; i < (FLAT ? 1 : W); ++i) acc_re[i] = acc_im[i] = R(0);
+            for (int i = 0; i < NACC; ++i) acc_re[i] = acc_im[i] = R(0);
             int cur = -1, run = 0;
             auto flush = [&](int base) {
                 const int i0 = (base >> 16) - 64, j0 = (base & 0xffff) - 64;
-                if (!lact) return;
                 const int c = j0 + lj;
-                if (c < 0 || c >= T) return;
+                if (!lane_ok || c < 0 || c >= T) return;
+                const int idx0 = lane_off + i0 * T + j0;
                 if (FLAT) {
                     const int row = i0 + ls;
                     if (row < 0 || row >= T) return;
-                    atomicAdd(sre + row * T + c, f2fix(acc_re[0]));
-                    atomicAdd(sim + row * T + c, f2fix(acc_im[0]));
+                    atomicAdd(sre + idx0, f2fix(acc_re[0]));
+                    atomicAdd(sim + idx0, f2fix(acc_im[0]));
                 } else {
-                    const int p = q + ls;
-                    if (p < wk.p0 || p >= wk.p1) return;
-                    A *re = sre + (p % W) * TT + c;
-                    A *im = sim + (p % W) * TT + c;
+                    const int ilo = max(0, -i0), ihi = min(W, T - i0);
+                    if (ilo == 0 && ihi == W) {
 #pragma unroll
-                    for (int i = 0; i < W; ++i) {
-                        const int row = i0 + i;
-                        if (row >= 0 && row < T) {
-                            atomicAdd(re + row * T, f2fix(acc_re[i]));
-                            atomicAdd(im + row * T, f2fix(acc_im[i]));
+                        for (int i = 0; i < W; ++i) {
+                            atomicAdd(sre + idx0 + i * T, f2fix(acc_re[i]));
+                            atomicAdd(sim + idx0 + i * T, f2fix(acc_im[i]));
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < W; ++i) {
+                            if (i >= ilo && i < ihi) {
+                                atomicAdd(sre + idx0 + i * T, f2fix(acc_re[i]));
+                                atomicAdd(sim + idx0 + i * T, f2fix(acc_im[i]));
+                            }
                         }
                     }
                 }
@@ -661,9 +692,9 @@ __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a
                     const int j0 = (int)dev_floor(rec_c.fv - hw) + 1;
                     base = ((i0 + 64) << 16) | (j0 + 64);
                     if (lj < W) {
-                        pu = es_kernel<R>(R(i0 + lj) - rec_c.fu, beta, inv_hw);
-                        pv = es_kernel<R>(R(j0 + lj) - rec_c.fv, beta, inv_hw);
-                        if (!FLAT) pw = es_kernel<R>(R(q + lj) - rec_c.fw, beta, inv_hw);
+                        pu = es_kernel_fast(R(i0 + lj) - rec_c.fu, beta2, inv_hw);
+                        pv = es_kernel_fast(R(j0 + lj) - rec_c.fv, beta2, inv_hw);
+                        if (!FLAT) pw = es_kernel_fast(R(q + lj) - rec_c.fw, beta2, inv_hw);
                     }
                     cplx<R> z = val_c;
                     if (VMODE == 0) z = z * cis_cycles<R>((w0 + rec_c.fw * dw) * sc);
@@ -683,7 +714,7 @@ __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a
                         if (bt != cur || run == kRunMax) {
                             if (cur >= 0) flush(cur);
 #pragma unroll
-                            for (int i = 0; i < (FLAT ? 1 : W); ++i) acc_re[i] = acc_im[i] = R(0);
+                            for (int i = 0; i < NACC; ++i) acc_re[i] = acc_im[i] = R(0);
                             cur = bt;
                             run = 0;
                         }
@@ -715,13 +746,13 @@ __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a
             for (int k = threadIdx.x; k < TT; k += kTileThreads) {
                 const int row = k / T, col = k - row * T;
                 dst[(size_t)row * a.g.gy + col] =
-                    cplx<R>{(R)((double)(long long)sre[slot * TT + k] * (double)finv),
-                            (R)((double)(long long)sim[slot * TT + k] * (double)finv)};
+                    cplx<R>{(R)((double)(long long)sre[slot * TS + k] * (double)finv),
+                            (R)((double)(long long)sim[slot * TS + k] * (double)finv)};
             }
         }
         for (int k = threadIdx.x; k < TT; k += kTileThreads) {
-            sre[slot * TT + k] = A(0);
-            sim[slot * TT + k] = A(0);
+            sre[slot * TS + k] = A(0);
+            sim[slot * TS + k] = A(0);
         }
         __syncthreads();
     }
@@ -801,7 +832,7 @@ static hipError_t spread_w(const SpreadLaunch &a, hipStream_t s) {
 template <int W>
 static hipError_t spread_run_w(const SpreadLaunch &a, hipStream_t s) {
     const bool flat = a.g.flat;
-    const size_t lds = 2 * (size_t)(flat ? 1 : W) * a.g.T * a.g.T * sizeof(unsigned long long);
+    const size_t lds = 2 * (size_t)(flat ? 1 : W) * run_slot_stride(a.g.T, flat) * sizeof(unsigned long long);
 #define SPREAD_RUN_CASE(FL, VM)                                                                 \
     if (flat == FL && a.vmode == VM) {                                                          \
         PFB_LAUNCH_NT((spread_run_kernel<W, FL, VM>), a.n_work, kTileThreads, lds, s, a);       \
@@ -815,6 +846,14 @@ static hipError_t spread_run_w(const SpreadLaunch &a, hipStream_t s) {
     SPREAD_RUN_CASE(true, 2)
 #undef SPREAD_RUN_CASE
     return hipErrorInvalidValue;
+}
+
+size_t gridder_lds_bytes(bool dbl, int W, int T, bool flat) {
+    const size_t ww = flat ? 1 : (size_t)W;
+    const size_t spread = dbl ? 2 * ww * T * T * sizeof(double)
+                              : 2 * ww * run_slot_stride(T, flat) * sizeof(unsigned long long);
+    const size_t interp = ww * (size_t)(T + W) * (T + W) * (dbl ? sizeof(cplx<double>) : sizeof(cplx<float>));
+    return spread > interp ? spread : interp;
 }
 
 hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s) {

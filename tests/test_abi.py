@@ -73,6 +73,11 @@ def test_shape_validation_without_gpu(lib):
     opt.oversample = 1.5
     assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -4
     opt.oversample = 0
+    prob.nx, prob.ny = 256, 256
+    opt.tile = 64                             # 7 w-planes of a 64 x 64 tile exceed the 160 KiB of LDS
+    assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
+    assert b"LDS" in lib.pfb_last_error()
+    opt.tile = 0
     cb[1] = 3
     assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
     assert b"chan_band" in lib.pfb_last_error()
