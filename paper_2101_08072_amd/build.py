@@ -18,7 +18,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libpfb.so")
 ARCH = os.environ.get("PFB_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["pfb_kernels.hip", "pfb_host.cpp"]
+SOURCES = ["pfb_kernels.hip", "pfb_sort.hip", "pfb_host.cpp"]
 COMMON = ["-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
           "-I", CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -167,7 +167,9 @@ struct GridderHost {
     std::vector<GridWork> gwork;
     std::vector<InterpWork> iwork;
     std::vector<int> gband_start, iband_start;  // per band first work item (n_band + 1)
-    std::vector<int64_t> sort_items;     // [start, count] of every non-empty bucket
+    std::vector<int64_t> sort_items;     // [start, count, band, bucket] of every non-empty bucket
+    bool mfma = false;                   // FP32 w-stacked: matrix-core spread (window sort, phase table)
+    int sort_rb = 1, sort_cb = 1;        // sort blocks of base rows x columns
     int64_t n_entries = 0;
     size_t o_sortitems = 0;
     // workspace offsets
@@ -181,6 +183,8 @@ struct GridderHost {
     GridWork *d_gwork = nullptr;
     InterpWork *d_iwork = nullptr;
     void *d_recs = nullptr, *d_omega = nullptr, *d_corr2d = nullptr, *d_corrx = nullptr, *d_corry = nullptr;
+    size_t o_phase = 0;
+    void *d_phase = nullptr;
     int64_t keys() const { return (int64_t)g.n_band * g.ntx * g.nty * g.nj0max; }
 };
 
@@ -367,6 +371,7 @@ SpreadLaunch spread_args(const pfb_plan *P, const GridderHost &G, int b0, int nb
     s.offsets = G.d_offsets;
     s.recs = G.d_recs;
     s.omega = G.d_omega;
+    s.phase = G.mfma ? G.d_phase : nullptr;
     s.vis = vis;
     s.planes = planes;
     s.band0 = b0;
@@ -567,6 +572,8 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         M.g.nj0max = std::max(M.g.nj0max, bd.nj0);
         M.g.nwmax = std::max(M.g.nwmax, bd.nw);
     }
+    M.mfma = !dbl && !opt.flat;
+    if (M.mfma) mfma_window(opt.support, &M.sort_rb, &M.sort_cb);
     GridderHost &Q = P->psf;
     Q.g = base_geom(*P, 2 * pr.nx, 2 * pr.ny, true);
     Q.cs = make_split(Q.g.gx);
@@ -676,7 +683,13 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
             if (cnt[k2]) {
                 G->sort_items.push_back(G->offsets[k2]);
                 G->sort_items.push_back(cnt[k2]);
+                G->sort_items.push_back((int64_t)(k2 / ((size_t)G->g.ntx * G->g.nty * G->g.nj0max)));
+                G->sort_items.push_back((int64_t)k2);
             }
+        if (sort_key_bits(G->keys(), G->g.T, G->g.W, G->sort_rb, G->sort_cb, pr.n_row * pr.n_chan) > 64) {
+            fail(PFB_EUNSUPPORTED, "bucket sort key exceeds 64 bits (too many buckets x visibilities)");
+            return bail(PFB_EUNSUPPORTED);
+        }
     }
 
     // grid correction: Chebyshev expansion of the ES kernel's Fourier transform
@@ -727,9 +740,10 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         G->o_cursor = L.take((G->offsets.size()) * sizeof(unsigned long long));
         G->o_gwork = L.take(std::max<size_t>(G->gwork.size(), 1) * sizeof(GridWork));
         G->o_iwork = L.take(std::max<size_t>(G->iwork.size(), 1) * sizeof(InterpWork));
-        G->o_sortitems = L.take(std::max<size_t>(G->sort_items.size(), 2) * sizeof(int64_t));
+        G->o_sortitems = L.take(std::max<size_t>(G->sort_items.size(), 4) * sizeof(int64_t));
         G->o_recs = L.take(std::max<int64_t>(G->n_entries, 1) * (dbl ? sizeof(Rec<double>) : sizeof(Rec<float>)));
         G->o_omega = L.take(std::max<int64_t>(G->n_entries, 1) * P->rsz);
+        if (G->mfma) G->o_phase = L.take(std::max<int64_t>(G->n_entries, 1) * 2 * sizeof(float));
         if (G->corr2d) {
             G->o_corr2d = L.take((size_t)nb * G->g.nx * G->g.ny * P->rsz);
         } else {
@@ -747,7 +761,9 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         const size_t recsz = dbl ? sizeof(Rec<double>) : sizeof(Rec<float>);
         size_t need = 0;
         for (GridderHost *G : {&M, &Q})
-            need = std::max(need, (((size_t)G->n_entries * recsz + 255) & ~size_t(255)) + (size_t)G->n_entries * P->rsz);
+            need = std::max(need, (((size_t)G->n_entries * recsz + 255) & ~size_t(255)) +
+                                      (((size_t)G->n_entries * P->rsz + 255) & ~size_t(255)) +
+                                      sort_scratch_bytes(G->n_entries));
         P->o_sorttmp = (L.off - P->o_planes >= need) ? P->o_planes : L.take(need);
     }
     P->o_vals = L.take((size_t)pr.n_row * pr.n_chan * csz);
@@ -829,6 +845,7 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
         G->d_iwork = reinterpret_cast<InterpWork *>(P->p(G->o_iwork));
         G->d_recs = P->p(G->o_recs);
         G->d_omega = P->p(G->o_omega);
+        G->d_phase = G->mfma ? P->p(G->o_phase) : nullptr;
         if (G->corr2d) {
             G->d_corr2d = P->p(G->o_corr2d);
         } else {
@@ -851,7 +868,9 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
                                   hipMemcpyHostToDevice, s));
         const size_t recsz = d ? sizeof(Rec<double>) : sizeof(Rec<float>);
         void *tmp_recs = P->p(P->o_sorttmp);
-        void *tmp_om = P->p(P->o_sorttmp + (((size_t)G->n_entries * recsz + 255) & ~size_t(255)));
+        const size_t tmp_rec_bytes = ((size_t)G->n_entries * recsz + 255) & ~size_t(255);
+        void *tmp_om = P->p(P->o_sorttmp + tmp_rec_bytes);
+        void *sort_scratch = P->p(P->o_sorttmp + tmp_rec_bytes + (((size_t)G->n_entries * P->rsz + 255) & ~size_t(255)));
         BucketArgs ba{};
         ba.g = G->g;
         ba.uvw = pr.uvw;
@@ -871,8 +890,10 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
         }
         LAUNCH_OK(launch_scatter(d, ba, s));
         LAUNCH_OK(launch_sort(d, tmp_recs, tmp_om, G->d_recs, G->d_omega,
-                              reinterpret_cast<const int64_t *>(P->p(G->o_sortitems)), (int)(G->sort_items.size() / 2),
-                              G->g.T, G->g.W, s));
+                              reinterpret_cast<const int64_t *>(P->p(G->o_sortitems)), (int)(G->sort_items.size() / 4),
+                              G->n_entries, G->keys(), (int64_t)G->g.ntx * G->g.nty * G->g.nj0max,
+                              pr.n_row * pr.n_chan, G->g.T, G->g.W, G->sort_rb, G->sort_cb, G->d_bands, G->d_phase,
+                              sort_scratch, s));
         const double *cheb = reinterpret_cast<const double *>(P->p(P->o_cheb));
         const int nch = (int)P->cheb.size();
         if (G->corr2d) {

@@ -27,9 +27,17 @@ void set_thread_profiler(Profiler *p);
 
 hipError_t launch_count(bool dbl, const BucketArgs &a, hipStream_t s);
 hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s);
-// sorts each bucket (items: [start, count] pairs) by the footprint base cell; src -> dst
+// Deterministic plan-time order of the entries of every bucket (pfb_sort.hip):
+// items are [start, count, band, bucket] quadruples of the non-empty buckets;
+// entries are ordered by (bucket, block of rb x cb base cells, visibility index);
+// src -> dst (records and weights); phase (optional, FP32 complex per entry)
+// receives the w-phase.  scratch holds sort_scratch_bytes(n_entries) bytes.
+size_t sort_scratch_bytes(int64_t n_entries);
+int sort_key_bits(int64_t n_buckets, int T, int W, int rb, int cb, int64_t n_vis);
 hipError_t launch_sort(bool dbl, const void *src, const void *src_om, void *dst, void *dst_om, const int64_t *items,
-                       int n_items, int T, int W, hipStream_t s);
+                       int n_items, int64_t n_entries, int64_t n_buckets, int64_t bucket_per_band, int64_t n_vis,
+                       int T, int W, int rb, int cb, const BandDev *bands, void *phase, void *scratch,
+                       hipStream_t s);
 hipError_t launch_corr2d(bool dbl, const GeomDev &g, const BandDev *bands, const double *cheb,
                          int ncheb, double xi_max, void *corr, hipStream_t s);
 hipError_t launch_corr1d(bool dbl, int n, int gsize, const double *cheb, int ncheb, double xi_max,
@@ -47,7 +55,11 @@ struct SpreadLaunch {
     int band0;
     int vmode;            // 0 data, 1 unit visibilities, 2 precomputed values
     const float *absmax;  // FP32 path: device scalar, max |z| over active visibilities
+    const void *phase;    // FP32 w-stacked gridder: exp(2 pi i s_c w) per entry (selects the MFMA spread)
 };
+// Window of the MFMA spread for support W (4..8): footprints whose base cells lie
+// in a block of rb rows x cb columns share one accumulator tile.
+void mfma_window(int W, int *rb, int *cb);
 // LDS bytes per block of the spread and interpolation kernels (the larger)
 size_t gridder_lds_bytes(bool dbl, int W, int T, bool flat);
 constexpr size_t kMaxLdsBytes = 160 * 1024;

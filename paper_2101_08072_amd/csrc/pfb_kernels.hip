@@ -244,71 +244,6 @@ static hipError_t launch_bucket(bool dbl, const BucketArgs &a, hipStream_t s) {
 hipError_t launch_count(bool dbl, const BucketArgs &a, hipStream_t s) { return launch_bucket<false>(dbl, a, s); }
 hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s) { return launch_bucket<true>(dbl, a, s); }
 
-// Plan-time segmented counting sort: within every (band, tile, w-base-plane)
-// bucket, order entries by the base cell (i0, j0) of their footprint, so that
-// visibilities sharing a footprint sit next to each other (runs).
-template <typename R>
-__global__ __launch_bounds__(kThreads) void sort_kernel(const Rec<R> *src, const R *src_om, Rec<R> *dst, R *dst_om,
-                                                        const int64_t *items, int T, int W) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    unsigned *hist = reinterpret_cast<unsigned *>(smem_raw);
-    __shared__ unsigned part[kThreads];
-    const int KS = T + W - 1, KEYS = KS * KS;
-    const int64_t start = items[2 * blockIdx.x], n = items[2 * blockIdx.x + 1];
-    const R hw = R(0.5) * R(W);
-    auto key_of = [&](const Rec<R> &r) {
-        const int i0 = (int)dev_floor(r.fu - hw) + 1, j0 = (int)dev_floor(r.fv - hw) + 1;
-        const int a = min(max(i0 + W - 1, 0), KS - 1), b = min(max(j0 + W - 1, 0), KS - 1);
-        return a * KS + b;
-    };
-    for (int k = threadIdx.x; k < KEYS; k += kThreads) hist[k] = 0u;
-    __syncthreads();
-    for (int64_t e = threadIdx.x; e < n; e += kThreads) atomicAdd(hist + key_of(src[start + e]), 1u);
-    __syncthreads();
-    // exclusive scan of hist: contiguous chunks per thread, then thread totals
-    const int per = (KEYS + kThreads - 1) / kThreads;
-    const int k0 = threadIdx.x * per, k1 = min(KEYS, k0 + per);
-    unsigned s = 0;
-    for (int k = k0; k < k1; ++k) s += hist[k];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned acc = 0;
-        for (int t = 0; t < kThreads; ++t) {
-            const unsigned v = part[t];
-            part[t] = acc;
-            acc += v;
-        }
-    }
-    __syncthreads();
-    unsigned acc = part[threadIdx.x];
-    for (int k = k0; k < k1; ++k) {
-        const unsigned v = hist[k];
-        hist[k] = acc;
-        acc += v;
-    }
-    __syncthreads();
-    for (int64_t e = threadIdx.x; e < n; e += kThreads) {
-        const Rec<R> r = src[start + e];
-        const unsigned pos = atomicAdd(hist + key_of(r), 1u);
-        dst[start + pos] = r;
-        dst_om[start + pos] = src_om[start + e];
-    }
-}
-
-hipError_t launch_sort(bool dbl, const void *src, const void *src_om, void *dst, void *dst_om, const int64_t *items,
-                       int n_items, int T, int W, hipStream_t s) {
-    if (n_items <= 0) return hipSuccess;
-    const size_t lds = (size_t)(T + W - 1) * (T + W - 1) * sizeof(unsigned);
-    if (dbl)
-        PFB_LAUNCH(sort_kernel<double>, n_items, lds, s, (const Rec<double> *)src, (const double *)src_om,
-                   (Rec<double> *)dst, (double *)dst_om, items, T, W);
-    else
-        PFB_LAUNCH(sort_kernel<float>, n_items, lds, s, (const Rec<float> *)src, (const float *)src_om,
-                   (Rec<float> *)dst, (float *)dst_om, items, T, W);
-    return hipSuccess;
-}
-
 // ---------------------------------------------------------------------------
 // grid correction
 // ---------------------------------------------------------------------------
@@ -758,6 +693,236 @@ __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a
     }
 }
 
+// FP32 w-stacked spread on the matrix cores.
+//
+// For visibilities whose footprints lie in one window of 8 rows, 16 columns
+// and the W planes q .. q + W - 1 of a bucket, the gridded block is a sum of
+// rank-one terms, G[(k, i), j] = sum_v (P_v[k] U_v[i]) (V_v[j] z_v): a matrix
+// product over the visibility index.  v_mfma_f32_16x16x4f32 takes 4
+// visibilities per instruction; the M dimension holds two planes x 8 rows per
+// 16-row tile (ceil(W / 2) tiles), N the 16 columns, and Re z and Im z are two
+// products.  The accumulators of a window stay in registers until the window
+// changes (buckets are sorted by window: base rows in blocks of rb = 9 - W,
+// base columns in blocks of cb = 17 - W) or kMfmaRunMax visibilities have been
+// added; they then go to the LDS plane ring as 64-bit fixed point (ds_add_u64).
+//
+// Operand layout (one wave, lane l = 16 s + r): A[16 t + r][s] and B[s][r] in
+// lane l, result D[16 t + 4 s + v][r] in register v of tile t.  The 16 lanes of
+// slot s evaluate the 1-D ES weights of visibility s of the group relative to
+// its window, U[r mod 8] (rows), V[r] (columns), P[r] (planes); the plane
+// weights of a tile are broadcast within the 16-lane row with DPP.
+constexpr int kMfmaRunMax = 124;                // visibilities per flush: 124 * 2^24 < 2^31
+constexpr float kMfmaScale = 16777216.0f;       // 2^24
+constexpr int kMfmaThreads = 1024;              // 16 waves (at most 128 registers per lane)
+template <int W> struct MfmaWin {
+    static constexpr int R = 8;                 // window rows
+    static constexpr int RB = R - W + 1;        // base rows per window
+    static constexpr int CB = 16 - W + 1;       // base columns per window
+    static constexpr int NT = (W + 1) / 2;      // 16-row tiles: two planes each
+};
+void mfma_window(int W, int *rb, int *cb) {
+    *rb = 8 - W + 1;
+    *cb = 16 - W + 1;
+}
+typedef float mfma_v4f __attribute__((ext_vector_type(4)));
+
+// value of lane N of this lane's 16-lane row (DPP row broadcast)
+template <int N> __device__ __forceinline__ float row_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + N, 0xf, 0xf, false));
+}
+
+template <int W, int VMODE>
+__global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch a) {
+    using R_ = float;
+    using A = unsigned long long;
+    constexpr int RB = MfmaWin<W>::RB, CB = MfmaWin<W>::CB, NT = MfmaWin<W>::NT;
+    constexpr int NWAVE = kMfmaThreads / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int T = a.g.T, TT = T * T, TS = run_slot_stride(T, false);
+    A *sre = reinterpret_cast<A *>(smem_raw);
+    A *sim = sre + W * TS;
+    const GridWork wk = a.work[blockIdx.x];
+    const BandDev bd = a.bands[wk.band];
+    const int ntiles = a.g.ntx * a.g.nty;
+    const int tu = wk.tile / a.g.nty, tv = wk.tile - tu * a.g.nty;
+    const int bb = wk.band - a.band0;
+    const Rec<R_> *recs = reinterpret_cast<const Rec<R_> *>(a.recs);
+    const R_ *omega = reinterpret_cast<const R_ *>(a.omega);
+    const cplx<R_> *phase = reinterpret_cast<const cplx<R_> *>(a.phase);
+    const cplx<R_> *vis = reinterpret_cast<const cplx<R_> *>(a.vis);
+    cplx<R_> *planes = reinterpret_cast<cplx<R_> *>(a.planes);
+    R_ fscale = R_(1), finv = R_(1);
+    {
+        const float am = *a.absmax;
+        if (am > 0.f) {
+            fscale = kMfmaScale / am;
+            finv = am / kMfmaScale;
+        }
+    }
+    for (int k = threadIdx.x; k < 2 * W * TS; k += kMfmaThreads) sre[k] = A(0);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sg = lane >> 4, r = lane & 15;    // K slot (visibility of a group of 4); row / column
+    const R_ beta2 = (R_)(a.g.beta * 1.4426950408889634), inv_hw = R_(2) / R_(W), hw = R_(0.5) * R_(W);
+    const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
+    const int qstart = max(0, wk.p0 - W + 1);
+    const size_t plane_sz = (size_t)a.g.gx * a.g.gy;
+
+    for (int q = qstart; q < wk.p1; ++q) {
+        if (q < bd.nj0) {
+            const int64_t b0 = a.offsets[keybase + q], n = a.offsets[keybase + q + 1] - b0;
+            const int64_t per = (n + NWAVE - 1) / NWAVE;
+            const int64_t e_beg = b0 + min(n, wv * per), e_end = b0 + min(n, (wv + 1) * per);
+            mfma_v4f cre[NT], cim[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) cre[t] = cim[t] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
+            constexpr int kNoRun = INT_MIN;
+            int cur = kNoRun, run = 0;
+            // add the accumulators of window `key` to the plane ring and clear them
+            auto flush = [&](int key) {
+                const int I = ((key >> 8) - 64) * RB - (W - 1), J = ((key & 0xff) - 64) * CB - (W - 1);
+                const int col = J + r;
+                const bool colok = col >= 0 && col < T;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int k = 2 * t + ((4 * sg + v) >> 3), row = I + ((4 * sg + v) & 7), p = q + k;
+                        if (colok && k < W && p >= wk.p0 && p < wk.p1 && row >= 0 && row < T) {
+                            const int idx = (p % W) * TS + row * T + col;
+                            atomicAdd(sre + idx, f2fix(cre[t][v]));
+                            atomicAdd(sim + idx, f2fix(cim[t][v]));
+                        }
+                    }
+                    cre[t] = cim[t] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
+                }
+            };
+            // Entries are loaded 64 at a time, lane l holding entry e + l (records
+            // coalesced, visibility gathers issued together); the loads of the
+            // next two batches are in flight while a batch is processed in 16
+            // groups of 4.  The owner lane of an entry derives its window and
+            // offsets once; each 16-lane slot fetches them with ds_bpermute.
+            auto load_rec = [&](int64_t eb) {
+                Rec<R_> rr{R_(0), R_(0), R_(0), 0u};
+                if (eb < e_end) rr = recs[eb];
+                return rr;
+            };
+            auto load_val = [&](int64_t eb, const Rec<R_> &rr) {
+                cplx<R_> v{R_(0), R_(0)};
+                if (eb < e_end) {
+                    if (VMODE == 0) {
+                        v = vis[rr.idx & ~kHomeBit] * phase[eb] * (omega[eb] * fscale);
+                    } else if (VMODE == 1) {
+                        v = cplx<R_>{omega[eb] * fscale, R_(0)};
+                    } else {
+                        v = vis[rr.idx & ~kHomeBit] * fscale;
+                    }
+                }
+                return v;
+            };
+            auto bperm_f = [](int addr, R_ x) {
+                return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+            };
+            Rec<R_> rec_c = load_rec(e_beg + lane);
+            cplx<R_> val_c = load_val(e_beg + lane, rec_c);
+            Rec<R_> rec_n = load_rec(e_beg + 64 + lane);
+            for (int64_t e = e_beg; e < e_end; e += 64) {
+                const cplx<R_> val_n = load_val(e + 64 + lane, rec_n);
+                const Rec<R_> rec_nn = load_rec(e + 128 + lane);
+                const int nbatch = (int)min((int64_t)64, e_end - e);
+                // owner lane: window of its entry and the offsets of the window origin
+                int okey;
+                R_ odu, odv, odq;
+                {
+                    const int i0 = (int)dev_floor(rec_c.fu - hw) + 1;
+                    const int j0 = (int)dev_floor(rec_c.fv - hw) + 1;
+                    const int wa = floordiv(i0 + W - 1, RB), wb = floordiv(j0 + W - 1, CB);
+                    okey = ((wa + 64) << 8) | (wb + 64);
+                    odu = R_(wa * RB - (W - 1)) - rec_c.fu;     // row 0 of the window minus fu
+                    odv = R_(wb * CB - (W - 1)) - rec_c.fv;
+                    odq = R_(q) - rec_c.fw;
+                }
+#pragma unroll 1
+                for (int g4 = 0; g4 < nbatch; g4 += 4) {
+                    const int nb = min(4, nbatch - g4);
+                    const int own = (g4 + sg) * 4;      // byte address of the owner lane
+                    const R_ du = bperm_f(own, odu), dv = bperm_f(own, odv), dq = bperm_f(own, odq);
+                    const R_ zr = bperm_f(own, val_c.re), zi = bperm_f(own, val_c.im);
+                    const int key = __builtin_amdgcn_ds_bpermute(own, okey);
+                    const R_ U = es_kernel_fast(du + R_(r & 7), beta2, inv_hw);
+                    const R_ V = es_kernel_fast(dv + R_(r), beta2, inv_hw);
+                    const R_ P = r < W ? es_kernel_fast(dq + R_(r), beta2, inv_hw) : R_(0);
+                    // plane weights of the tiles, broadcast with every lane active (a
+                    // DPP read of a lane outside the exec mask would give 0)
+                    const R_ p0 = row_bcast<0>(P), p1 = row_bcast<1>(P), p2 = row_bcast<2>(P),
+                             p3 = row_bcast<3>(P), p4 = row_bcast<4>(P), p5 = row_bcast<5>(P),
+                             p6 = row_bcast<6>(P), p7 = row_bcast<7>(P);
+                    const bool hi = r >= 8;               // rows 8..15 of a tile: its second plane
+                    R_ At[NT];
+                    At[0] = U * (hi ? p1 : p0);
+                    if constexpr (NT > 1) At[1] = U * (hi ? p3 : p2);
+                    if constexpr (NT > 2) At[2] = U * (hi ? p5 : p4);
+                    if constexpr (NT > 3) At[3] = U * (hi ? p7 : p6);
+                    const R_ Bre = V * zr, Bim = V * zi;
+                    // windows present in this group (wave-uniform); usually one
+                    int keys[4];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) keys[g] = rdlane(key, 16 * g);
+                    unsigned rem = (1u << nb) - 1u;
+                    while (rem) {
+                        const int f = __builtin_ctz(rem);
+                        int w = keys[0];
+#pragma unroll
+                        for (int g = 1; g < 4; ++g)
+                            if (f == g) w = keys[g];
+                        unsigned sel = 0;
+#pragma unroll
+                        for (int g = 0; g < 4; ++g)
+                            if (((rem >> g) & 1u) && keys[g] == w) sel |= 1u << g;
+                        const int cnt = __builtin_popcount(sel);
+                        if (w != cur || run + cnt > kMfmaRunMax) {
+                            if (cur != kNoRun) flush(cur);
+                            cur = w;
+                            run = 0;
+                        }
+                        run += cnt;
+                        const bool mine = (sel >> sg) & 1u;
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            const R_ at = mine ? At[t] : R_(0);
+                            cre[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, Bre, cre[t], 0, 0, 0);
+                            cim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, Bim, cim[t], 0, 0, 0);
+                        }
+                        rem &= ~sel;
+                    }
+                }
+                rec_c = rec_n;
+                val_c = val_n;
+                rec_n = rec_nn;
+            }
+            if (cur != kNoRun) flush(cur);
+        }
+        __syncthreads();
+        const int slot = q % W;
+        if (q >= wk.p0) {
+            cplx<R_> *dst = planes + ((size_t)bb * a.g.nwmax + q) * plane_sz + (size_t)tu * T * a.g.gy + (size_t)tv * T;
+            for (int k = threadIdx.x; k < TT; k += kMfmaThreads) {
+                const int row = k / T, col = k - row * T;
+                dst[(size_t)row * a.g.gy + col] =
+                    cplx<R_>{(R_)((double)(long long)sre[slot * TS + k] * (double)finv),
+                             (R_)((double)(long long)sim[slot * TS + k] * (double)finv)};
+            }
+        }
+        for (int k = threadIdx.x; k < TT; k += kMfmaThreads) {
+            sre[slot * TS + k] = A(0);
+            sim[slot * TS + k] = A(0);
+        }
+        __syncthreads();
+    }
+}
+
 // max |z| over active visibilities (FP32 path): per-block maxima, then one block
 __global__ __launch_bounds__(kThreads) void absmax_blocks_kernel(int vmode, const cplx<float> *vis,
                                                                  const float *weight, const uint8_t *flag,
@@ -832,6 +997,13 @@ static hipError_t spread_w(const SpreadLaunch &a, hipStream_t s) {
 template <int W>
 static hipError_t spread_run_w(const SpreadLaunch &a, hipStream_t s) {
     const bool flat = a.g.flat;
+    if (!flat && a.phase) {
+        const size_t lds = 2 * (size_t)W * run_slot_stride(a.g.T, false) * sizeof(unsigned long long);
+        if (a.vmode == 0) PFB_LAUNCH_NT((spread_mfma_kernel<W, 0>), a.n_work, kMfmaThreads, lds, s, a);
+        else if (a.vmode == 1) PFB_LAUNCH_NT((spread_mfma_kernel<W, 1>), a.n_work, kMfmaThreads, lds, s, a);
+        else PFB_LAUNCH_NT((spread_mfma_kernel<W, 2>), a.n_work, kMfmaThreads, lds, s, a);
+        return hipSuccess;
+    }
     const size_t lds = 2 * (size_t)(flat ? 1 : W) * run_slot_stride(a.g.T, flat) * sizeof(unsigned long long);
 #define SPREAD_RUN_CASE(FL, VM)                                                                 \
     if (flat == FL && a.vmode == VM) {                                                          \
