@@ -709,8 +709,9 @@ __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a
 // Operand layout (one wave, lane l = 16 s + r): A[16 t + r][s] and B[s][r] in
 // lane l, result D[16 t + 4 s + v][r] in register v of tile t.  The 16 lanes of
 // slot s evaluate the 1-D ES weights of visibility s of the group relative to
-// its window, U[r mod 8] (rows), V[r] (columns), P[r] (planes); the plane
-// weights of a tile are broadcast within the 16-lane row with DPP.
+// its window: lanes r < 8 the row weight U[r], lanes r >= 8 the plane weight
+// P[r - 8], all 16 the column weight V[r]; DPP within the 16-lane row gives
+// every lane U[r mod 8] and the plane weights of the tiles.
 constexpr int kMfmaRunMax = 124;                // visibilities per flush: 124 * 2^24 < 2^31
 constexpr float kMfmaScale = 16777216.0f;       // 2^24
 constexpr int kMfmaThreads = 1024;              // 16 waves (at most 128 registers per lane)
@@ -726,9 +727,14 @@ void mfma_window(int W, int *rb, int *cb) {
 }
 typedef float mfma_v4f __attribute__((ext_vector_type(4)));
 
-// value of lane N of this lane's 16-lane row (DPP row broadcast)
+// value of lane N of this lane's 16-lane row (DPP row broadcast); every lane
+// of the row must be active
 template <int N> __device__ __forceinline__ float row_bcast(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + N, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + N, 0xf, 0xf, false));
+}
+// value of lane (r + 8) mod 16 of this lane's row (DPP row rotate by 8)
+__device__ __forceinline__ float row_ror8(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, false));
 }
 
 template <int W, int VMODE>
@@ -780,18 +786,29 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
             for (int t = 0; t < NT; ++t) cre[t] = cim[t] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
             constexpr int kNoRun = INT_MIN;
             int cur = kNoRun, run = 0;
+            // LDS word of accumulator (t, v) for a window at the tile origin:
+            // plane 2 t + (s >= 2) of the tile, row 4 (s mod 2) + v, column r;
+            // koff[t] = -1 when that plane is not stored by this work item
+            int koff[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int k = 2 * t + (sg >> 1), p = q + k;
+                koff[t] = (k < W && p >= wk.p0 && p < wk.p1) ? (p % W) * TS : -1;
+            }
+            const int ioff = (4 * (sg & 1)) * T + r;
             // add the accumulators of window `key` to the plane ring and clear them
             auto flush = [&](int key) {
                 const int I = ((key >> 8) - 64) * RB - (W - 1), J = ((key & 0xff) - 64) * CB - (W - 1);
-                const int col = J + r;
-                const bool colok = col >= 0 && col < T;
+                const int base = I * T + J + ioff;
+                const bool colok = J + r >= 0 && J + r < T;
+                const bool rows_in = I >= 0 && I + 8 <= T;    // wave-uniform
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int k = 2 * t + ((4 * sg + v) >> 3), row = I + ((4 * sg + v) & 7), p = q + k;
-                        if (colok && k < W && p >= wk.p0 && p < wk.p1 && row >= 0 && row < T) {
-                            const int idx = (p % W) * TS + row * T + col;
+                        const int row = I + 4 * (sg & 1) + v;
+                        if (colok && koff[t] >= 0 && (rows_in || (row >= 0 && row < T))) {
+                            const int idx = koff[t] + base + v * T;
                             atomicAdd(sre + idx, f2fix(cre[t][v]));
                             atomicAdd(sim + idx, f2fix(cim[t][v]));
                         }
@@ -851,15 +868,15 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                     const R_ du = bperm_f(own, odu), dv = bperm_f(own, odv), dq = bperm_f(own, odq);
                     const R_ zr = bperm_f(own, val_c.re), zi = bperm_f(own, val_c.im);
                     const int key = __builtin_amdgcn_ds_bpermute(own, okey);
-                    const R_ U = es_kernel_fast(du + R_(r & 7), beta2, inv_hw);
-                    const R_ V = es_kernel_fast(dv + R_(r), beta2, inv_hw);
-                    const R_ P = r < W ? es_kernel_fast(dq + R_(r), beta2, inv_hw) : R_(0);
-                    // plane weights of the tiles, broadcast with every lane active (a
-                    // DPP read of a lane outside the exec mask would give 0)
-                    const R_ p0 = row_bcast<0>(P), p1 = row_bcast<1>(P), p2 = row_bcast<2>(P),
-                             p3 = row_bcast<3>(P), p4 = row_bcast<4>(P), p5 = row_bcast<5>(P),
-                             p6 = row_bcast<6>(P), p7 = row_bcast<7>(P);
                     const bool hi = r >= 8;               // rows 8..15 of a tile: its second plane
+                    const R_ E = (hi && r - 8 >= W) ? R_(0)
+                                                    : es_kernel_fast(hi ? dq + R_(r - 8) : du + R_(r), beta2, inv_hw);
+                    const R_ V = es_kernel_fast(dv + R_(r), beta2, inv_hw);
+                    const R_ Er = row_ror8(E);
+                    const R_ U = hi ? Er : E;             // U[r mod 8]
+                    const R_ p0 = row_bcast<8>(E), p1 = row_bcast<9>(E), p2 = row_bcast<10>(E),
+                             p3 = row_bcast<11>(E), p4 = row_bcast<12>(E), p5 = row_bcast<13>(E),
+                             p6 = row_bcast<14>(E), p7 = row_bcast<15>(E);
                     R_ At[NT];
                     At[0] = U * (hi ? p1 : p0);
                     if constexpr (NT > 1) At[1] = U * (hi ? p3 : p2);

@@ -153,6 +153,22 @@ def test_fused_hessian_matches_grid_of_degrid(tiny, tiny_plan):
     assert rel(h, gd) < (1e-13 if prec == "fp64" else 1e-6)
 
 
+def test_independent_plans_are_bitwise_identical(tiny):
+    """The plan-time entry order depends on the inputs only (radix sort on a
+    total key), so two plans of one problem grid, degrid and apply the Hessian
+    identically, bit for bit."""
+    import torch
+    outs = []
+    for _ in range(2):
+        plan = make_plan(tiny["prob"], "fp32")
+        v = to_dev(tiny["vis"], torch.complex64)
+        xg = to_dev(tiny["xd"], torch.float32)
+        outs.append((host(plan.grid(v)), host(plan.degrid(xg)), host(plan.hessian(xg))))
+        del plan
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 # --------------------------------------------------------------------------
 # wider field, two bands, flags, non-square image, split work items
 # --------------------------------------------------------------------------
