@@ -392,6 +392,7 @@ InterpLaunch interp_args(const GridderHost &G, int b0, int nbb, int omode, const
     s.out = out;
     s.band0 = b0;
     s.omode = omode;
+    s.phase = G.mfma ? G.d_phase : nullptr;
     return s;
 }
 

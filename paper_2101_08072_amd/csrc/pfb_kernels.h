@@ -81,6 +81,7 @@ struct InterpLaunch {
     void *out;            // OMODE 0: visibilities; OMODE 1: per-visibility values
     int band0;
     int omode;
+    const void *phase;    // FP32 w-stacked gridder: exp(2 pi i s_c w) per entry (else null: computed)
 };
 hipError_t launch_interp(bool dbl, const InterpLaunch &a, hipStream_t s);
 hipError_t launch_zero_flagged(bool dbl, const uint32_t *flagged, int64_t n, void *vis, hipStream_t s);
