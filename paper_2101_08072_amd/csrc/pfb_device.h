@@ -54,10 +54,21 @@ template <typename R> __device__ __forceinline__ R es_kernel(R z, R beta, R inv_
 // ---------------------------------------------------------------------------
 // LDS FFT
 // ---------------------------------------------------------------------------
-// Padding of LDS indices to spread power-of-two strides over banks.
-template <typename R> struct LdsPad { static constexpr int SH = sizeof(R) == 4 ? 3 : 4; };
-template <typename R> __device__ __forceinline__ int lpad(int p) { return p + (p >> LdsPad<R>::SH); }
-template <typename R> __host__ __device__ constexpr int lds_len(int L) { return L + (L >> LdsPad<R>::SH); }
+// LDS layout of vectors of length 2^LOG2L for the FFT passes.  Element p of a
+// vector sits at pad(p) = p + p / 2^SH + p / 2^(LOG2L-3): the first term
+// spreads the butterflies' power-of-two strides over the banks, the second the
+// digit-reversed scatter of the input (consecutive inputs land L/8 apart).
+// Vectors of a column group are ld elements apart, ld = 1 modulo the elements
+// per 128-byte bank row, so that lanes walking across columns hit distinct banks.
+template <typename R, int LOG2L> struct Lds {
+    static constexpr int L = 1 << LOG2L;
+    static constexpr int SH = sizeof(R) == 4 ? 3 : 4;
+    static constexpr int HS = LOG2L >= SH + 3 ? LOG2L - 3 : 30;
+    static constexpr int EB = 128 / (2 * (int)sizeof(R));
+    __host__ __device__ static constexpr int pad(int p) { return p + (p >> SH) + (p >> HS); }
+    static constexpr int len = pad(L - 1) + 1;
+    static constexpr int ld = len + ((1 - len) % EB + EB) % EB;
+};
 
 // Radix plan for L = 2^LOG2L: first stage of radix 2^(LOG2L % 3) (if non-zero), then radix 8.
 template <int LOG2L> struct FftPlan {
@@ -144,19 +155,19 @@ __device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, co
         cplx<R> *vb = buf + c * ld;
         cplx<R> v[RAD];
 #pragma unroll
-        for (int t = 0; t < RAD; ++t) v[t] = vb[lpad<R>(base + t * m)];
+        for (int t = 0; t < RAD; ++t) v[t] = vb[Lds<R, LOG2L>::pad(base + t * m)];
         if (m > 1) {
 #pragma unroll
             for (int t = 1; t < RAD; ++t) v[t] = v[t] * twiddle<R, INV>(tw, t * j * estep);
         }
         dft_small<R, INV, RAD>(v);
 #pragma unroll
-        for (int t = 0; t < RAD; ++t) vb[lpad<R>(base + t * m)] = v[t];
+        for (int t = 0; t < RAD; ++t) vb[Lds<R, LOG2L>::pad(base + t * m)] = v[t];
     }
 }
 
 // Full in-place FFT of C vectors of length 2^LOG2L already loaded in DIT order.
-// Ends with a barrier; the result is in natural order at lpad(k).
+// Ends with a barrier; the result is in natural order at Lds<R, LOG2L>::pad(k).
 template <typename R, bool INV, int LOG2L>
 __device__ __forceinline__ void lds_fft(cplx<R> *buf, int C, int ld, const cplx<R> *tw, int tw_shift) {
     using P = FftPlan<LOG2L>;

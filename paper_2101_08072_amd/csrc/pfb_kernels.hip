@@ -1227,7 +1227,7 @@ constexpr int kRowLds = 32768;   // target LDS bytes per row-transform workgroup
 template <typename R, int LOG2L>
 __host__ __device__ constexpr int rows_per_block() {
     constexpr int L = 1 << LOG2L;
-    constexpr int per = lds_len<R>(L) * (int)sizeof(cplx<R>);
+    constexpr int per = Lds<R, LOG2L>::ld * (int)sizeof(cplx<R>);
     int c = 1;
     while (2 * c * per <= kRowLds) c *= 2;
     return c;
@@ -1239,7 +1239,7 @@ __global__ __launch_bounds__(kThreads) void g1_rows_kernel(XformArgs a, int C) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int ld = lds_len<R>(L);
+    const int ld = Lds<R, LOG2L>::ld;
     const int gx = a.g.gx, ny = a.g.ny;
     const int ngrp = gx / C;
     int blk = blockIdx.x;
@@ -1254,14 +1254,14 @@ __global__ __launch_bounds__(kThreads) void g1_rows_kernel(XformArgs a, int C) {
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.t1) + (plane * gx + (size_t)ug * C) * ny;
     for (int id = threadIdx.x; id < C * L; id += kThreads) {
         const int c = id / L, r = id - c * L;
-        buf[c * ld + lpad<R>(dit_pos<LOG2L>(r))] = src[(size_t)c * L + r];
+        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = src[(size_t)c * L + r];
     }
     __syncthreads();
     lds_fft<R, true, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
     for (int id = threadIdx.x; id < C * ny; id += kThreads) {
         const int c = id / ny, iy = id - c * ny;
         const int k = wrapi(iy - ny / 2, L);
-        dst[(size_t)c * ny + iy] = buf[c * ld + lpad<R>(k)];
+        dst[(size_t)c * ny + iy] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
     }
 }
 
@@ -1279,7 +1279,7 @@ __global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int ld = lds_len<R>(N1);
+    const int ld = Lds<R, LOG2N1>::ld;
     const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny;
     const int n2 = a.cs.n2;
     const int ncg = (ny + C - 1) / C;
@@ -1321,7 +1321,7 @@ __global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
                 }
             }
         }
-        buf[c * ld + lpad<R>(dit_pos<LOG2N1>(r1))] = v;
+        buf[c * ld + Lds<R, LOG2N1>::pad(dit_pos<LOG2N1>(r1))] = v;
     }
     __syncthreads();
     const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
@@ -1332,7 +1332,7 @@ __global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
         const int c = id % C, k1 = id / C;
         const int col = col0 + c;
         if (col >= ny) continue;
-        cplx<R> v = buf[c * ld + lpad<R>(k1)];
+        cplx<R> v = buf[c * ld + Lds<R, LOG2N1>::pad(k1)];
         if (n2 > 1) v = v * twiddle<R, INV>(tw, ((r2 * k1) & nmask) << shift_n);
         t1[(size_t)(k1 * n2 + r2) * ny + col] = v;
     }
@@ -1347,9 +1347,10 @@ __global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int ld = lds_len<R>(N2);
-    R *acc = reinterpret_cast<R *>(buf + C * ld);     // [C][N2]
-    R *sv = acc + C * N2;                              // [C][N2] (n - 1 - sc)
+    const int ld = Lds<R, LOG2N2>::ld;
+    constexpr int NS = N2 + 1;                         // odd row stride of acc / sv (banks)
+    R *acc = reinterpret_cast<R *>(buf + C * ld);     // [C][NS]
+    R *sv = acc + C * NS;                              // [C][NS] (n - 1 - sc)
     const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny;
     const int n1 = a.cs.n1;
     const int ncg = (ny + C - 1) / C;
@@ -1365,10 +1366,10 @@ __global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
     const R sc = (R)bd.sc;
     for (int id = threadIdx.x; id < C * N2; id += kThreads) {
         const int c = id % C, k2 = id / C;
-        acc[c * N2 + k2] = R(0);
+        acc[c * NS + k2] = R(0);
         const int i = wrapi(k1 + n1 * k2 + nx / 2, gx);
         const int col = col0 + c;
-        sv[c * N2 + k2] = (!a.g.flat && i < nx && col < ny)
+        sv[c * NS + k2] = (!a.g.flat && i < nx && col < ny)
                               ? pixel_sm1<R>(i, col, nx, ny, (R)a.g.cellx, (R)a.g.celly) - sc
                               : R(0);
     }
@@ -1378,7 +1379,7 @@ __global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
         for (int id = threadIdx.x; id < C * N2; id += kThreads) {
             const int c = id % C, r2 = id / C;
             const int col = col0 + c;
-            buf[c * ld + lpad<R>(dit_pos<LOG2N2>(r2))] =
+            buf[c * ld + Lds<R, LOG2N2>::pad(dit_pos<LOG2N2>(r2))] =
                 col < ny ? t1[(size_t)(k1 * N2 + r2) * ny + col] : cplx<R>{R(0), R(0)};
         }
         __syncthreads();
@@ -1386,12 +1387,12 @@ __global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
         const R wj = (R)(bd.w0 + j * bd.dw);
         for (int id = threadIdx.x; id < C * N2; id += kThreads) {
             const int c = id % C, k2 = id / C;
-            const cplx<R> v = buf[c * ld + lpad<R>(k2)];
+            const cplx<R> v = buf[c * ld + Lds<R, LOG2N2>::pad(k2)];
             if (a.g.flat) {
-                acc[c * N2 + k2] += v.re;
+                acc[c * NS + k2] += v.re;
             } else {
-                const cplx<R> ph = cis_cycles<R>(wj * sv[c * N2 + k2]);
-                acc[c * N2 + k2] += v.re * ph.re - v.im * ph.im;
+                const cplx<R> ph = cis_cycles<R>(wj * sv[c * NS + k2]);
+                acc[c * NS + k2] += v.re * ph.re - v.im * ph.im;
             }
         }
         __syncthreads();
@@ -1405,7 +1406,7 @@ __global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
         const size_t pix = (size_t)i * ny + col;
         const R cr = a.corr2d ? reinterpret_cast<const R *>(a.corr2d)[(size_t)b * nx * ny + pix]
                               : reinterpret_cast<const R *>(a.corr_x)[i] * reinterpret_cast<const R *>(a.corr_y)[col];
-        R v = acc[c * N2 + k2] * cr;
+        R v = acc[c * NS + k2] * cr;
         if (a.zero_edge && (i == 0 || col == 0)) v = R(0);
         img[pix] = v;
     }
@@ -1418,7 +1419,7 @@ __global__ __launch_bounds__(kThreads) void d2_kernel(XformArgs a) {
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int ld = lds_len<R>(N2);
+    const int ld = Lds<R, LOG2N2>::ld;
     const int gx = a.g.gx, ny = a.g.ny;
     const int n1 = a.cs.n1;
     const int ncg = (ny + C - 1) / C;
@@ -1438,7 +1439,7 @@ __global__ __launch_bounds__(kThreads) void d2_kernel(XformArgs a) {
     for (int id = threadIdx.x; id < C * N2; id += kThreads) {
         const int c = id % C, r2 = id / C;
         const int col = col0 + c;
-        buf[c * ld + lpad<R>(dit_pos<LOG2N2>(r2))] =
+        buf[c * ld + Lds<R, LOG2N2>::pad(dit_pos<LOG2N2>(r2))] =
             col < ny ? t1[(size_t)(k1 * N2 + r2) * ny + col] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
@@ -1446,7 +1447,7 @@ __global__ __launch_bounds__(kThreads) void d2_kernel(XformArgs a) {
     for (int id = threadIdx.x; id < C * N2; id += kThreads) {
         const int c = id % C, k2 = id / C;
         const int col = col0 + c;
-        if (col < ny) t2[(size_t)(k1 + n1 * k2) * ny + col] = buf[c * ld + lpad<R>(k2)];
+        if (col < ny) t2[(size_t)(k1 + n1 * k2) * ny + col] = buf[c * ld + Lds<R, LOG2N2>::pad(k2)];
     }
 }
 
@@ -1456,7 +1457,7 @@ __global__ __launch_bounds__(kThreads) void d3_rows_kernel(XformArgs a, int C, c
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int ld = lds_len<R>(L);
+    const int ld = Lds<R, LOG2L>::ld;
     const int gx = a.g.gx, ny = a.g.ny;
     const int ngrp = gx / C;
     int blk = blockIdx.x;
@@ -1472,13 +1473,13 @@ __global__ __launch_bounds__(kThreads) void d3_rows_kernel(XformArgs a, int C, c
     for (int id = threadIdx.x; id < C * L; id += kThreads) {
         const int c = id / L, r = id - c * L;
         const int iy = wrapi(r + ny / 2, L);
-        buf[c * ld + lpad<R>(dit_pos<LOG2L>(r))] = iy < ny ? src[(size_t)c * ny + iy] : cplx<R>{R(0), R(0)};
+        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = iy < ny ? src[(size_t)c * ny + iy] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
     lds_fft<R, false, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
     for (int id = threadIdx.x; id < C * L; id += kThreads) {
         const int c = id / L, k = id - c * L;
-        dst[(size_t)c * L + k] = buf[c * ld + lpad<R>(k)];
+        dst[(size_t)c * L + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
     }
 }
 
@@ -1488,7 +1489,7 @@ static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
     hipError_t e = dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = std::min(rows_per_block<R, LG>(), a.g.gx);
-        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
         const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C);
         PFB_LAUNCH((g1_rows_kernel<R, LG>), nb, lds, s, a, C);
         return hipSuccess;
@@ -1499,7 +1500,7 @@ static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
     if (a.cs.n2 > 1) {
         e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
             constexpr int LG = decltype(Lc)::value;
-            const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+            const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
             const int nb = a.n_bb * a.g.nwmax * a.cs.n2 * ncg;
             PFB_LAUNCH((colA_kernel<R, LG, true, 0>), nb, lds, s, a);
             return hipSuccess;
@@ -1517,7 +1518,7 @@ static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
     return dispatch_int<3, 9>(lg3, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         constexpr int N2 = 1 << LG;
-        const size_t lds = (size_t)C * lds_len<R>(N2) * sizeof(cplx<R>) + 2 * (size_t)C * N2 * sizeof(R);
+        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>) + 2 * (size_t)C * (N2 + 1) * sizeof(R);
         const int nb = b.n_bb * b.cs.n1 * ncg;
         PFB_LAUNCH((g3_kernel<R, LG>), nb, lds, s, b);
         return hipSuccess;
@@ -1530,7 +1531,7 @@ static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
     const int ncg = (a.g.ny + C - 1) / C;
     hipError_t e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
         const int nb = a.n_bb * a.g.nwmax * a.cs.n2 * ncg;
         PFB_LAUNCH((colA_kernel<R, LG, false, 1>), nb, lds, s, a);
         return hipSuccess;
@@ -1540,7 +1541,7 @@ static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
     if (a.cs.n2 > 1) {
         e = dispatch_int<3, 9>(a.cs.log2n2, [&](auto Lc) -> hipError_t {
             constexpr int LG = decltype(Lc)::value;
-            const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+            const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
             const int nb = a.n_bb * a.g.nwmax * a.cs.n1 * ncg;
             PFB_LAUNCH((d2_kernel<R, LG>), nb, lds, s, a);
             return hipSuccess;
@@ -1552,7 +1553,7 @@ static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
     return dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C2 = std::min(rows_per_block<R, LG>(), a.g.gx);
-        const size_t lds = (size_t)C2 * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const size_t lds = (size_t)C2 * Lds<R, LG>::ld * sizeof(cplx<R>);
         const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C2);
         PFB_LAUNCH((d3_rows_kernel<R, LG>), nb, lds, s, a, C2, rows_src);
         return hipSuccess;
@@ -1580,7 +1581,7 @@ __global__ __launch_bounds__(kThreads) void s1_kernel(ConvArgs a, const R *x, R 
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int ld = lds_len<R>(L);
+    const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
     const int ngrp = nrows / C;
     const int ig = blockIdx.x % ngrp;
@@ -1606,14 +1607,14 @@ __global__ __launch_bounds__(kThreads) void s1_kernel(ConvArgs a, const R *x, R 
                 auxp[pix] = v;
             }
         }
-        buf[c * ld + lpad<R>(dit_pos<LOG2L>(r))] = cplx<R>{v, R(0)};
+        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = cplx<R>{v, R(0)};
     }
     __syncthreads();
     lds_fft<R, false, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
     cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * C) * a.ldh;
     for (int id = threadIdx.x; id < C * (ny + 1); id += kThreads) {
         const int c = id / (ny + 1), k = id - c * (ny + 1);
-        t1[(size_t)c * a.ldh + k] = buf[c * ld + lpad<R>(k)];
+        t1[(size_t)c * a.ldh + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
     }
 }
 
@@ -1631,7 +1632,7 @@ __device__ __forceinline__ void mul_reorder(cplx<R> *buf, int C, int ld, const R
         if (id < C * L) {
             const int c = id % C, k = id / C;
             const R hv = (col0 + c) < ncol ? h[(size_t)k * hstride + col0 + c] : R(0);
-            v[t] = buf[c * ld + lpad<R>(k)] * hv;
+            v[t] = buf[c * ld + Lds<R, LOG2L>::pad(k)] * hv;
         }
     }
     __syncthreads();
@@ -1640,7 +1641,7 @@ __device__ __forceinline__ void mul_reorder(cplx<R> *buf, int C, int ld, const R
         const int id = threadIdx.x + t * kThreads;
         if (id < C * L) {
             const int c = id % C, k = id / C;
-            buf[c * ld + lpad<R>(dit_pos<LOG2L>(k))] = v[t];
+            buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(k))] = v[t];
         }
     }
     __syncthreads();
@@ -1654,7 +1655,7 @@ __global__ __launch_bounds__(kThreads) void s2_single_kernel(ConvArgs a, int psf
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int ld = lds_len<R>(L);
+    const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ncol = a.ny + 1;
     const int ncg = (ncol + C - 1) / C;
     const int cg = blockIdx.x % ncg, b = blockIdx.x / ncg;
@@ -1665,7 +1666,7 @@ __global__ __launch_bounds__(kThreads) void s2_single_kernel(ConvArgs a, int psf
     for (int id = threadIdx.x; id < C * L; id += kThreads) {
         const int c = id % C, r = id / C;
         const int col = col0 + c;
-        buf[c * ld + lpad<R>(dit_pos<LOG2L>(r))] =
+        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] =
             (r < nin && col < ncol) ? t1[(size_t)r * a.ldh + col] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
@@ -1674,7 +1675,7 @@ __global__ __launch_bounds__(kThreads) void s2_single_kernel(ConvArgs a, int psf
     if (psf) {
         for (int id = threadIdx.x; id < C * L; id += kThreads) {
             const int c = id % C, k = id / C;
-            if (col0 + c < ncol) h[(size_t)k * a.ldh + col0 + c] = buf[c * ld + lpad<R>(k)].re;
+            if (col0 + c < ncol) h[(size_t)k * a.ldh + col0 + c] = buf[c * ld + Lds<R, LOG2L>::pad(k)].re;
         }
         return;
     }
@@ -1682,7 +1683,7 @@ __global__ __launch_bounds__(kThreads) void s2_single_kernel(ConvArgs a, int psf
     lds_fft<R, true, LOG2L>(buf, C, ld, tw, a.log2_lmax - LOG2L);
     for (int id = threadIdx.x; id < C * nx; id += kThreads) {
         const int c = id % C, r = id / C;
-        if (col0 + c < ncol) t1[(size_t)r * a.ldh + col0 + c] = buf[c * ld + lpad<R>(r)];
+        if (col0 + c < ncol) t1[(size_t)r * a.ldh + col0 + c] = buf[c * ld + Lds<R, LOG2L>::pad(r)];
     }
 }
 
@@ -1693,7 +1694,7 @@ __global__ __launch_bounds__(kThreads) void s2a_kernel(ConvArgs a, int psf) {
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int ld = lds_len<R>(N1);
+    const int ld = Lds<R, LOG2N1>::ld;
     const int nx = a.nx, ncol = a.ny + 1, n2 = a.cs.n2;
     const int ncg = (ncol + C - 1) / C;
     int blk = blockIdx.x;
@@ -1710,7 +1711,7 @@ __global__ __launch_bounds__(kThreads) void s2a_kernel(ConvArgs a, int psf) {
         const int c = id % C, r1 = id / C;
         const int r = r1 * n2 + r2;
         const int col = col0 + c;
-        buf[c * ld + lpad<R>(dit_pos<LOG2N1>(r1))] =
+        buf[c * ld + Lds<R, LOG2N1>::pad(dit_pos<LOG2N1>(r1))] =
             (r < nin && col < ncol) ? t1[(size_t)r * a.ldh + col] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
@@ -1722,7 +1723,7 @@ __global__ __launch_bounds__(kThreads) void s2a_kernel(ConvArgs a, int psf) {
         const int c = id % C, k1 = id / C;
         if (col0 + c >= ncol) continue;
         t2[(size_t)(k1 * n2 + r2) * a.ldh + col0 + c] =
-            buf[c * ld + lpad<R>(k1)] * twiddle<R, false>(tw, ((r2 * k1) & nmask) << shift_n);
+            buf[c * ld + Lds<R, LOG2N1>::pad(k1)] * twiddle<R, false>(tw, ((r2 * k1) & nmask) << shift_n);
     }
 }
 
@@ -1735,7 +1736,7 @@ __global__ __launch_bounds__(kThreads) void s2b_kernel(ConvArgs a, int psf) {
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int ld = lds_len<R>(N2);
+    const int ld = Lds<R, LOG2N2>::ld;
     const int nx = a.nx, ncol = a.ny + 1, n1 = a.cs.n1;
     const int ncg = (ncol + C - 1) / C;
     int blk = blockIdx.x;
@@ -1750,7 +1751,7 @@ __global__ __launch_bounds__(kThreads) void s2b_kernel(ConvArgs a, int psf) {
     for (int id = threadIdx.x; id < C * N2; id += kThreads) {
         const int c = id % C, r2 = id / C;
         const int col = col0 + c;
-        buf[c * ld + lpad<R>(dit_pos<LOG2N2>(r2))] = col < ncol ? t2[(size_t)r2 * a.ldh + col] : cplx<R>{R(0), R(0)};
+        buf[c * ld + Lds<R, LOG2N2>::pad(dit_pos<LOG2N2>(r2))] = col < ncol ? t2[(size_t)r2 * a.ldh + col] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
     const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
@@ -1758,7 +1759,7 @@ __global__ __launch_bounds__(kThreads) void s2b_kernel(ConvArgs a, int psf) {
     if (psf) {
         for (int id = threadIdx.x; id < C * N2; id += kThreads) {
             const int c = id % C, k2 = id / C;
-            if (col0 + c < ncol) h[(size_t)k2 * a.ldh + col0 + c] = buf[c * ld + lpad<R>(k2)].re;
+            if (col0 + c < ncol) h[(size_t)k2 * a.ldh + col0 + c] = buf[c * ld + Lds<R, LOG2N2>::pad(k2)].re;
         }
         return;
     }
@@ -1770,7 +1771,7 @@ __global__ __launch_bounds__(kThreads) void s2b_kernel(ConvArgs a, int psf) {
         const int c = id % C, r2 = id / C;
         if (col0 + c >= ncol) continue;
         t2[(size_t)r2 * a.ldh + col0 + c] =
-            buf[c * ld + lpad<R>(r2)] * twiddle<R, true>(tw, ((r2 * k1) & nmask) << shift_n);
+            buf[c * ld + Lds<R, LOG2N2>::pad(r2)] * twiddle<R, true>(tw, ((r2 * k1) & nmask) << shift_n);
     }
 }
 
@@ -1781,7 +1782,7 @@ __global__ __launch_bounds__(kThreads) void s2c_kernel(ConvArgs a) {
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int ld = lds_len<R>(N1);
+    const int ld = Lds<R, LOG2N1>::ld;
     const int nx = a.nx, ncol = a.ny + 1, n2 = a.cs.n2;
     const int ncg = (ncol + C - 1) / C;
     int blk = blockIdx.x;
@@ -1796,7 +1797,7 @@ __global__ __launch_bounds__(kThreads) void s2c_kernel(ConvArgs a) {
     for (int id = threadIdx.x; id < C * N1; id += kThreads) {
         const int c = id % C, k1 = id / C;
         const int col = col0 + c;
-        buf[c * ld + lpad<R>(dit_pos<LOG2N1>(k1))] =
+        buf[c * ld + Lds<R, LOG2N1>::pad(dit_pos<LOG2N1>(k1))] =
             col < ncol ? t2[(size_t)(k1 * n2 + r2) * a.ldh + col] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
@@ -1804,7 +1805,7 @@ __global__ __launch_bounds__(kThreads) void s2c_kernel(ConvArgs a) {
     for (int id = threadIdx.x; id < C * N1; id += kThreads) {
         const int c = id % C, r1 = id / C;
         const int r = r2 + n2 * r1;
-        if (r < nx && col0 + c < ncol) t1[(size_t)r * a.ldh + col0 + c] = buf[c * ld + lpad<R>(r1)];
+        if (r < nx && col0 + c < ncol) t1[(size_t)r * a.ldh + col0 + c] = buf[c * ld + Lds<R, LOG2N1>::pad(r1)];
     }
 }
 
@@ -1816,7 +1817,7 @@ __global__ __launch_bounds__(kThreads) void s3_kernel(ConvArgs a, R *y, const R 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
     __shared__ double red[kThreads / 64];
-    const int ld = lds_len<R>(L);
+    const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
     const int ngrp = nx / C;
     const int ig = blockIdx.x % ngrp;
@@ -1825,7 +1826,7 @@ __global__ __launch_bounds__(kThreads) void s3_kernel(ConvArgs a, R *y, const R 
     for (int id = threadIdx.x; id < C * L; id += kThreads) {
         const int c = id / L, k = id - c * L;
         const cplx<R> v = k <= ny ? t1[(size_t)c * a.ldh + k] : conj(t1[(size_t)c * a.ldh + (L - k)]);
-        buf[c * ld + lpad<R>(dit_pos<LOG2L>(k))] = v;
+        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(k))] = v;
     }
     __syncthreads();
     lds_fft<R, true, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
@@ -1834,7 +1835,7 @@ __global__ __launch_bounds__(kThreads) void s3_kernel(ConvArgs a, R *y, const R 
     for (int id = threadIdx.x; id < C * ny; id += kThreads) {
         const int c = id / ny, j = id - c * ny;
         const size_t pix = ((size_t)b * nx + ig * C + c) * ny + j;
-        R v = buf[c * ld + lpad<R>(j)].re * scale;
+        R v = buf[c * ld + Lds<R, LOG2L>::pad(j)].re * scale;
         if (OUT == CONV_OUT_SUB) v -= aux[pix];
         if (OUT == CONV_OUT_CG) {
             const R pv = aux[pix];
@@ -1858,28 +1859,28 @@ static hipError_t conv_columns(const ConvArgs &a, int psf, hipStream_t s) {
     if (a.cs.n2 == 1) {
         return dispatch_int<5, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
             constexpr int LG = decltype(Lc)::value;
-            const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+            const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
             PFB_LAUNCH((s2_single_kernel<R, LG>), a.n_band * ncg, lds, s, a, psf);
             return hipSuccess;
         });
     }
     hipError_t e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
         PFB_LAUNCH((s2a_kernel<R, LG>), a.n_band * a.cs.n2 * ncg, lds, s, a, psf);
         return hipSuccess;
     });
     if (e != hipSuccess) return e;
     e = dispatch_int<3, 9>(a.cs.log2n2, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
         PFB_LAUNCH((s2b_kernel<R, LG>), a.n_band * a.cs.n1 * ncg, lds, s, a, psf);
         return hipSuccess;
     });
     if (e != hipSuccess || psf) return e;
     return dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
         PFB_LAUNCH((s2c_kernel<R, LG>), a.n_band * a.cs.n2 * ncg, lds, s, a);
         return hipSuccess;
     });
@@ -1892,7 +1893,7 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
     hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = std::min(rows_per_block<R, LG>(), a.nx);
-        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
         const int nb = a.n_band * (a.nx / C);
         const R *xr = reinterpret_cast<const R *>(x);
         R *ap = reinterpret_cast<R *>(aux_in);
@@ -1907,7 +1908,7 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
     return dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = std::min(rows_per_block<R, LG>(), a.nx);
-        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
         const int nb = a.n_band * (a.nx / C);
         R *yr = reinterpret_cast<R *>(y);
         const R *ax = reinterpret_cast<const R *>(aux_out);
@@ -1947,7 +1948,7 @@ static hipError_t psfhat_t(const ConvArgs &a, const void *psf_img, hipStream_t s
     hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = std::min(rows_per_block<R, LG>(), a.nx);
-        const size_t lds = (size_t)C * lds_len<R>(1 << LG) * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
         const int nb = a.n_band * (2 * a.nx / C);
         PFB_LAUNCH((s1_kernel<R, LG, CONV_IN_X>), nb, lds, s, a, reinterpret_cast<const R *>(psf_img),
                    (R *)nullptr, 2 * a.nx, C, 1);
