@@ -434,9 +434,12 @@ pfb_status hessian_impl(pfb_plan *P, const void *x, void *y, hipStream_t s) {
         xa.image_in = x;
         xa.image_out = y;
         LAUNCH_OK(launch_degrid_xform(d, xa, s));
-        LAUNCH_OK(launch_interp(d, interp_args(G, b0, nbb, 1, P->p(P->o_planes), P->p(P->o_vals)), s));
-        pfb_status st = spread_prepass(P, 2, P->p(P->o_vals), s);
-        if (st) return st;
+        InterpLaunch ia = interp_args(G, b0, nbb, 1, P->p(P->o_planes), P->p(P->o_vals));
+        if (!d) {   // FP32: the interpolation also finds the fixed-point scale of the spread
+            ia.absmax = reinterpret_cast<float *>(P->p(P->o_absmax));
+            LAUNCH_OK(launch_absmax_clear(ia.absmax, s));
+        }
+        LAUNCH_OK(launch_interp(d, ia, s));
         LAUNCH_OK(launch_spread(d, spread_args(P, G, b0, nbb, 2, P->p(P->o_vals), P->p(P->o_planes)), s));
         LAUNCH_OK(launch_grid_xform(d, xa, s));
     }

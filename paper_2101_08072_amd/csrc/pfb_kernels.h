@@ -67,6 +67,7 @@ hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s);
 // FP32 path: absmax = max over unflagged, non-zero-weight entries of |w V| (vmode 0),
 // w (vmode 1) or |values| (vmode 2); partials holds >= kAbsmaxBlocks floats.
 constexpr int kAbsmaxBlocks = 1024;
+hipError_t launch_absmax_clear(float *absmax, hipStream_t s);
 hipError_t launch_absmax(int vmode, const void *vis, const void *weight, const uint8_t *flag, int64_t n,
                          float *partials, float *absmax, hipStream_t s);
 
@@ -82,6 +83,7 @@ struct InterpLaunch {
     int band0;
     int omode;
     const void *phase;    // FP32 w-stacked gridder: exp(2 pi i s_c w) per entry (else null: computed)
+    float *absmax;        // FP32, OMODE 1: raised to max |value| x 1.0001 (cleared by the caller), or null
 };
 hipError_t launch_interp(bool dbl, const InterpLaunch &a, hipStream_t s);
 hipError_t launch_zero_flagged(bool dbl, const uint32_t *flagged, int64_t n, void *vis, hipStream_t s);

@@ -981,6 +981,11 @@ __global__ __launch_bounds__(kThreads) void absmax_final_kernel(const float *par
         out[0] = t * 1.0001f;
     }
 }
+__global__ void absmax_clear_kernel(float *out) { out[0] = 0.f; }
+hipError_t launch_absmax_clear(float *absmax, hipStream_t s) {
+    PFB_LAUNCH_NT(absmax_clear_kernel, 1, 64, 0, s, absmax);
+    return hipSuccess;
+}
 hipError_t launch_absmax(int vmode, const void *vis, const void *weight, const uint8_t *flag, int64_t n,
                          float *partials, float *absmax, hipStream_t s) {
     int64_t nb = (n + kThreads - 1) / kThreads;
@@ -1101,6 +1106,7 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
     const R w0 = (R)bd.w0, dw = (R)bd.dw, sc = (R)bd.sc;
     const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
 
+    R vmax2 = R(0);   // OMODE 1: largest |value|^2 written (scale of the FP32 spread that follows)
     for (int q = wk.q0; q <= wk.q1; ++q) {
         const int64_t lo = max((int64_t)wk.e0, a.offsets[keybase + q]);
         const int64_t hi = min((int64_t)wk.e1, a.offsets[keybase + q + 1]);
@@ -1157,7 +1163,9 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
                     cplx<R> out = FLAT ? acc : acc * conj(cis_cycles<R>((w0 + rec.fw * dw) * sc));
                     reinterpret_cast<cplx<R> *>(a.out)[vid] = out;
                 } else {
-                    reinterpret_cast<cplx<R> *>(a.out)[vid] = acc * omega[e];
+                    const cplx<R> o = acc * omega[e];
+                    reinterpret_cast<cplx<R> *>(a.out)[vid] = o;
+                    vmax2 = max(vmax2, o.re * o.re + o.im * o.im);
                 }
             }
         }
@@ -1166,6 +1174,15 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
             load_plane(q + W, q % W);
         }
         __syncthreads();
+    }
+    if constexpr (sizeof(R) == 4 && OMODE == 1) {
+        if (a.absmax) {
+            float m = (float)vmax2;
+            for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+            m = sqrtf(m);
+            // non-negative floats order like their bit patterns; the margin matches the pre-pass
+            if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax(reinterpret_cast<unsigned *>(a.absmax), __float_as_uint(m * 1.0001f));
+        }
     }
 }
 
