@@ -132,15 +132,32 @@ template <typename R, bool INV, int RAD> __device__ __forceinline__ void dft_sma
     else dft8<R, INV>(v);
 }
 
-// twiddle exp(-+2 pi i e / Lmax) from the forward table of length Lmax
-template <typename R, bool INV> __device__ __forceinline__ cplx<R> twiddle(const cplx<R> *tw, int e) {
-    cplx<R> w = tw[e];
+// Twiddles exp(-+2 pi i e / Lmax) from a two-level table in LDS: for
+// e = e_hi 2^sh + e_lo, w^e = lo[e_lo] hi[e_hi], with lo[k] = w^k (k < 2^sh) and
+// hi[k] = w^(k 2^sh) copied from the FP64-accurate forward table in HBM (one
+// complex product, about 1.5 ulp; an LDS read instead of a scattered global one).
+constexpr int kTwEntries = 256;   // lo + hi entries for Lmax <= 2^14
+template <typename R> struct TwTab {
+    const cplx<R> *lo, *hi;
+    int sh, mask;
+    __device__ __forceinline__ cplx<R> get(int e) const { return lo[e & mask] * hi[e >> sh]; }
+};
+// fill the table at lds (kTwEntries elements) from the table of length 2^log2_lmax;
+// the caller synchronises the block before the first use
+template <typename R, int NT>
+__device__ __forceinline__ TwTab<R> tw_fill(cplx<R> *lds, const cplx<R> *tw, int log2_lmax) {
+    const int sh = (log2_lmax + 1) / 2, nlo = 1 << sh, nhi = 1 << (log2_lmax - sh);
+    for (int k = threadIdx.x; k < nlo + nhi; k += NT) lds[k] = k < nlo ? tw[k] : tw[(k - nlo) << sh];
+    return TwTab<R>{lds, lds + nlo, sh, nlo - 1};
+}
+template <typename R, bool INV> __device__ __forceinline__ cplx<R> twiddle(const TwTab<R> &tt, int e) {
+    cplx<R> w = tt.get(e);
     return INV ? conj(w) : w;
 }
 
 // One DIT stage of radix RAD at span m over C vectors stored at buf + c*ld.
 template <typename R, bool INV, int RAD, int LOG2L>
-__device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, const cplx<R> *tw, int tw_shift) {
+__device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, const TwTab<R> &tw, int tw_shift) {
     constexpr int L = 1 << LOG2L;
     constexpr int NB = L / RAD;               // butterflies per vector
     const int total = NB * C;
@@ -169,7 +186,7 @@ __device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, co
 // Full in-place FFT of C vectors of length 2^LOG2L already loaded in DIT order.
 // Ends with a barrier; the result is in natural order at Lds<R, LOG2L>::pad(k).
 template <typename R, bool INV, int LOG2L>
-__device__ __forceinline__ void lds_fft(cplx<R> *buf, int C, int ld, const cplx<R> *tw, int tw_shift) {
+__device__ __forceinline__ void lds_fft(cplx<R> *buf, int C, int ld, const TwTab<R> &tw, int tw_shift) {
     using P = FftPlan<LOG2L>;
     int m = 1;
 #pragma unroll

@@ -1255,7 +1255,9 @@ template <typename R, int LOG2L>
 __global__ __launch_bounds__(kThreads) void g1_rows_kernel(XformArgs a, int C) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int gx = a.g.gx, ny = a.g.ny;
     const int ngrp = gx / C;
@@ -1274,7 +1276,7 @@ __global__ __launch_bounds__(kThreads) void g1_rows_kernel(XformArgs a, int C) {
         buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = src[(size_t)c * L + r];
     }
     __syncthreads();
-    lds_fft<R, true, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
+    lds_fft<R, true, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     for (int id = threadIdx.x; id < C * ny; id += kThreads) {
         const int c = id / ny, iy = id - c * ny;
         const int k = wrapi(iy - ny / 2, L);
@@ -1295,7 +1297,9 @@ __global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
     constexpr int N1 = 1 << LOG2N1;
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2N1>::ld;
     const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny;
     const int n2 = a.cs.n2;
@@ -1341,8 +1345,7 @@ __global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
         buf[c * ld + Lds<R, LOG2N1>::pad(dit_pos<LOG2N1>(r1))] = v;
     }
     __syncthreads();
-    const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
-    lds_fft<R, INV, LOG2N1>(buf, C, ld, tw, a.log2_lmax - LOG2N1);
+    lds_fft<R, INV, LOG2N1>(buf, C, ld, tt, a.log2_lmax - LOG2N1);
     const int shift_n = a.log2_lmax - (a.cs.log2n1 + a.cs.log2n2);
     const int nmask = gx - 1;
     for (int id = threadIdx.x; id < C * N1; id += kThreads) {
@@ -1350,7 +1353,7 @@ __global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
         const int col = col0 + c;
         if (col >= ny) continue;
         cplx<R> v = buf[c * ld + Lds<R, LOG2N1>::pad(k1)];
-        if (n2 > 1) v = v * twiddle<R, INV>(tw, ((r2 * k1) & nmask) << shift_n);
+        if (n2 > 1) v = v * twiddle<R, INV>(tt, ((r2 * k1) & nmask) << shift_n);
         t1[(size_t)(k1 * n2 + r2) * ny + col] = v;
     }
 }
@@ -1363,7 +1366,9 @@ __global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
     constexpr int N2 = 1 << LOG2N2;
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2N2>::ld;
     constexpr int NS = N2 + 1;                         // odd row stride of acc / sv (banks)
     R *acc = reinterpret_cast<R *>(buf + C * ld);     // [C][NS]
@@ -1390,7 +1395,6 @@ __global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
                               ? pixel_sm1<R>(i, col, nx, ny, (R)a.g.cellx, (R)a.g.celly) - sc
                               : R(0);
     }
-    const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
     for (int j = 0; j < nw; ++j) {
         const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1) + ((size_t)bb * a.g.nwmax + j) * gx * ny;
         for (int id = threadIdx.x; id < C * N2; id += kThreads) {
@@ -1400,7 +1404,7 @@ __global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
                 col < ny ? t1[(size_t)(k1 * N2 + r2) * ny + col] : cplx<R>{R(0), R(0)};
         }
         __syncthreads();
-        lds_fft<R, true, LOG2N2>(buf, C, ld, tw, a.log2_lmax - LOG2N2);
+        lds_fft<R, true, LOG2N2>(buf, C, ld, tt, a.log2_lmax - LOG2N2);
         const R wj = (R)(bd.w0 + j * bd.dw);
         for (int id = threadIdx.x; id < C * N2; id += kThreads) {
             const int c = id % C, k2 = id / C;
@@ -1435,7 +1439,9 @@ __global__ __launch_bounds__(kThreads) void d2_kernel(XformArgs a) {
     constexpr int N2 = 1 << LOG2N2;
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2N2>::ld;
     const int gx = a.g.gx, ny = a.g.ny;
     const int n1 = a.cs.n1;
@@ -1460,7 +1466,7 @@ __global__ __launch_bounds__(kThreads) void d2_kernel(XformArgs a) {
             col < ny ? t1[(size_t)(k1 * N2 + r2) * ny + col] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
-    lds_fft<R, false, LOG2N2>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2N2);
+    lds_fft<R, false, LOG2N2>(buf, C, ld, tt, a.log2_lmax - LOG2N2);
     for (int id = threadIdx.x; id < C * N2; id += kThreads) {
         const int c = id % C, k2 = id / C;
         const int col = col0 + c;
@@ -1473,7 +1479,9 @@ template <typename R, int LOG2L>
 __global__ __launch_bounds__(kThreads) void d3_rows_kernel(XformArgs a, int C, const void *src_v) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int gx = a.g.gx, ny = a.g.ny;
     const int ngrp = gx / C;
@@ -1493,7 +1501,7 @@ __global__ __launch_bounds__(kThreads) void d3_rows_kernel(XformArgs a, int C, c
         buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = iy < ny ? src[(size_t)c * ny + iy] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
-    lds_fft<R, false, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
+    lds_fft<R, false, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     for (int id = threadIdx.x; id < C * L; id += kThreads) {
         const int c = id / L, k = id - c * L;
         dst[(size_t)c * L + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
@@ -1506,7 +1514,7 @@ static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
     hipError_t e = dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = std::min(rows_per_block<R, LG>(), a.g.gx);
-        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C);
         PFB_LAUNCH((g1_rows_kernel<R, LG>), nb, lds, s, a, C);
         return hipSuccess;
@@ -1517,7 +1525,7 @@ static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
     if (a.cs.n2 > 1) {
         e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
             constexpr int LG = decltype(Lc)::value;
-            const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+            const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
             const int nb = a.n_bb * a.g.nwmax * a.cs.n2 * ncg;
             PFB_LAUNCH((colA_kernel<R, LG, true, 0>), nb, lds, s, a);
             return hipSuccess;
@@ -1535,7 +1543,7 @@ static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
     return dispatch_int<3, 9>(lg3, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         constexpr int N2 = 1 << LG;
-        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>) + 2 * (size_t)C * (N2 + 1) * sizeof(R);
+        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>) + 2 * (size_t)C * (N2 + 1) * sizeof(R);
         const int nb = b.n_bb * b.cs.n1 * ncg;
         PFB_LAUNCH((g3_kernel<R, LG>), nb, lds, s, b);
         return hipSuccess;
@@ -1548,7 +1556,7 @@ static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
     const int ncg = (a.g.ny + C - 1) / C;
     hipError_t e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_bb * a.g.nwmax * a.cs.n2 * ncg;
         PFB_LAUNCH((colA_kernel<R, LG, false, 1>), nb, lds, s, a);
         return hipSuccess;
@@ -1558,7 +1566,7 @@ static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
     if (a.cs.n2 > 1) {
         e = dispatch_int<3, 9>(a.cs.log2n2, [&](auto Lc) -> hipError_t {
             constexpr int LG = decltype(Lc)::value;
-            const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+            const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
             const int nb = a.n_bb * a.g.nwmax * a.cs.n1 * ncg;
             PFB_LAUNCH((d2_kernel<R, LG>), nb, lds, s, a);
             return hipSuccess;
@@ -1570,7 +1578,7 @@ static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
     return dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C2 = std::min(rows_per_block<R, LG>(), a.g.gx);
-        const size_t lds = (size_t)C2 * Lds<R, LG>::ld * sizeof(cplx<R>);
+        const size_t lds = (size_t)C2 * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C2);
         PFB_LAUNCH((d3_rows_kernel<R, LG>), nb, lds, s, a, C2, rows_src);
         return hipSuccess;
@@ -1597,7 +1605,9 @@ template <typename R, int LOG2L, int IN>
 __global__ __launch_bounds__(kThreads) void s1_kernel(ConvArgs a, const R *x, R *auxp, int nrows, int C, int psf) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
     const int ngrp = nrows / C;
@@ -1627,7 +1637,7 @@ __global__ __launch_bounds__(kThreads) void s1_kernel(ConvArgs a, const R *x, R 
         buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = cplx<R>{v, R(0)};
     }
     __syncthreads();
-    lds_fft<R, false, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
+    lds_fft<R, false, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * C) * a.ldh;
     for (int id = threadIdx.x; id < C * (ny + 1); id += kThreads) {
         const int c = id / (ny + 1), k = id - c * (ny + 1);
@@ -1671,7 +1681,9 @@ __global__ __launch_bounds__(kThreads) void s2_single_kernel(ConvArgs a, int psf
     constexpr int L = 1 << LOG2L;
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ncol = a.ny + 1;
     const int ncg = (ncol + C - 1) / C;
@@ -1687,8 +1699,7 @@ __global__ __launch_bounds__(kThreads) void s2_single_kernel(ConvArgs a, int psf
             (r < nin && col < ncol) ? t1[(size_t)r * a.ldh + col] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
-    const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
-    lds_fft<R, false, LOG2L>(buf, C, ld, tw, a.log2_lmax - LOG2L);
+    lds_fft<R, false, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     if (psf) {
         for (int id = threadIdx.x; id < C * L; id += kThreads) {
             const int c = id % C, k = id / C;
@@ -1697,7 +1708,7 @@ __global__ __launch_bounds__(kThreads) void s2_single_kernel(ConvArgs a, int psf
         return;
     }
     mul_reorder<R, LOG2L>(buf, C, ld, h, a.ldh, col0, ncol);
-    lds_fft<R, true, LOG2L>(buf, C, ld, tw, a.log2_lmax - LOG2L);
+    lds_fft<R, true, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     for (int id = threadIdx.x; id < C * nx; id += kThreads) {
         const int c = id % C, r = id / C;
         if (col0 + c < ncol) t1[(size_t)r * a.ldh + col0 + c] = buf[c * ld + Lds<R, LOG2L>::pad(r)];
@@ -1710,7 +1721,9 @@ __global__ __launch_bounds__(kThreads) void s2a_kernel(ConvArgs a, int psf) {
     constexpr int N1 = 1 << LOG2N1;
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2N1>::ld;
     const int nx = a.nx, ncol = a.ny + 1, n2 = a.cs.n2;
     const int ncg = (ncol + C - 1) / C;
@@ -1732,15 +1745,14 @@ __global__ __launch_bounds__(kThreads) void s2a_kernel(ConvArgs a, int psf) {
             (r < nin && col < ncol) ? t1[(size_t)r * a.ldh + col] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
-    const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
-    lds_fft<R, false, LOG2N1>(buf, C, ld, tw, a.log2_lmax - LOG2N1);
+    lds_fft<R, false, LOG2N1>(buf, C, ld, tt, a.log2_lmax - LOG2N1);
     const int shift_n = a.log2_lmax - (a.cs.log2n1 + a.cs.log2n2);
     const int nmask = 2 * nx - 1;
     for (int id = threadIdx.x; id < C * N1; id += kThreads) {
         const int c = id % C, k1 = id / C;
         if (col0 + c >= ncol) continue;
         t2[(size_t)(k1 * n2 + r2) * a.ldh + col0 + c] =
-            buf[c * ld + Lds<R, LOG2N1>::pad(k1)] * twiddle<R, false>(tw, ((r2 * k1) & nmask) << shift_n);
+            buf[c * ld + Lds<R, LOG2N1>::pad(k1)] * twiddle<R, false>(tt, ((r2 * k1) & nmask) << shift_n);
     }
 }
 
@@ -1752,7 +1764,9 @@ __global__ __launch_bounds__(kThreads) void s2b_kernel(ConvArgs a, int psf) {
     constexpr int N2 = 1 << LOG2N2;
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2N2>::ld;
     const int nx = a.nx, ncol = a.ny + 1, n1 = a.cs.n1;
     const int ncg = (ncol + C - 1) / C;
@@ -1771,8 +1785,7 @@ __global__ __launch_bounds__(kThreads) void s2b_kernel(ConvArgs a, int psf) {
         buf[c * ld + Lds<R, LOG2N2>::pad(dit_pos<LOG2N2>(r2))] = col < ncol ? t2[(size_t)r2 * a.ldh + col] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
-    const cplx<R> *tw = reinterpret_cast<const cplx<R> *>(a.tw);
-    lds_fft<R, false, LOG2N2>(buf, C, ld, tw, a.log2_lmax - LOG2N2);
+    lds_fft<R, false, LOG2N2>(buf, C, ld, tt, a.log2_lmax - LOG2N2);
     if (psf) {
         for (int id = threadIdx.x; id < C * N2; id += kThreads) {
             const int c = id % C, k2 = id / C;
@@ -1781,14 +1794,14 @@ __global__ __launch_bounds__(kThreads) void s2b_kernel(ConvArgs a, int psf) {
         return;
     }
     mul_reorder<R, LOG2N2>(buf, C, ld, h, a.ldh, col0, ncol);
-    lds_fft<R, true, LOG2N2>(buf, C, ld, tw, a.log2_lmax - LOG2N2);
+    lds_fft<R, true, LOG2N2>(buf, C, ld, tt, a.log2_lmax - LOG2N2);
     const int shift_n = a.log2_lmax - (a.cs.log2n1 + a.cs.log2n2);
     const int nmask = 2 * nx - 1;
     for (int id = threadIdx.x; id < C * N2; id += kThreads) {
         const int c = id % C, r2 = id / C;
         if (col0 + c >= ncol) continue;
         t2[(size_t)r2 * a.ldh + col0 + c] =
-            buf[c * ld + Lds<R, LOG2N2>::pad(r2)] * twiddle<R, true>(tw, ((r2 * k1) & nmask) << shift_n);
+            buf[c * ld + Lds<R, LOG2N2>::pad(r2)] * twiddle<R, true>(tt, ((r2 * k1) & nmask) << shift_n);
     }
 }
 
@@ -1798,7 +1811,9 @@ __global__ __launch_bounds__(kThreads) void s2c_kernel(ConvArgs a) {
     constexpr int N1 = 1 << LOG2N1;
     constexpr int C = col_group<R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2N1>::ld;
     const int nx = a.nx, ncol = a.ny + 1, n2 = a.cs.n2;
     const int ncg = (ncol + C - 1) / C;
@@ -1818,7 +1833,7 @@ __global__ __launch_bounds__(kThreads) void s2c_kernel(ConvArgs a) {
             col < ncol ? t2[(size_t)(k1 * n2 + r2) * a.ldh + col] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
-    lds_fft<R, true, LOG2N1>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2N1);
+    lds_fft<R, true, LOG2N1>(buf, C, ld, tt, a.log2_lmax - LOG2N1);
     for (int id = threadIdx.x; id < C * N1; id += kThreads) {
         const int c = id % C, r1 = id / C;
         const int r = r2 + n2 * r1;
@@ -1832,7 +1847,9 @@ template <typename R, int LOG2L, int OUT>
 __global__ __launch_bounds__(kThreads) void s3_kernel(ConvArgs a, R *y, const R *aux, R sigma, int C) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     __shared__ double red[kThreads / 64];
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
@@ -1846,7 +1863,7 @@ __global__ __launch_bounds__(kThreads) void s3_kernel(ConvArgs a, R *y, const R 
         buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(k))] = v;
     }
     __syncthreads();
-    lds_fft<R, true, LOG2L>(buf, C, ld, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax - LOG2L);
+    lds_fft<R, true, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     const R scale = R(1) / (R(4) * R(nx) * R(ny));
     double part = 0.0;
     for (int id = threadIdx.x; id < C * ny; id += kThreads) {
@@ -1876,28 +1893,28 @@ static hipError_t conv_columns(const ConvArgs &a, int psf, hipStream_t s) {
     if (a.cs.n2 == 1) {
         return dispatch_int<5, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
             constexpr int LG = decltype(Lc)::value;
-            const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+            const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
             PFB_LAUNCH((s2_single_kernel<R, LG>), a.n_band * ncg, lds, s, a, psf);
             return hipSuccess;
         });
     }
     hipError_t e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         PFB_LAUNCH((s2a_kernel<R, LG>), a.n_band * a.cs.n2 * ncg, lds, s, a, psf);
         return hipSuccess;
     });
     if (e != hipSuccess) return e;
     e = dispatch_int<3, 9>(a.cs.log2n2, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         PFB_LAUNCH((s2b_kernel<R, LG>), a.n_band * a.cs.n1 * ncg, lds, s, a, psf);
         return hipSuccess;
     });
     if (e != hipSuccess || psf) return e;
     return dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         PFB_LAUNCH((s2c_kernel<R, LG>), a.n_band * a.cs.n2 * ncg, lds, s, a);
         return hipSuccess;
     });
@@ -1910,7 +1927,7 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
     hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = std::min(rows_per_block<R, LG>(), a.nx);
-        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_band * (a.nx / C);
         const R *xr = reinterpret_cast<const R *>(x);
         R *ap = reinterpret_cast<R *>(aux_in);
@@ -1925,7 +1942,7 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
     return dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = std::min(rows_per_block<R, LG>(), a.nx);
-        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_band * (a.nx / C);
         R *yr = reinterpret_cast<R *>(y);
         const R *ax = reinterpret_cast<const R *>(aux_out);
@@ -1965,7 +1982,7 @@ static hipError_t psfhat_t(const ConvArgs &a, const void *psf_img, hipStream_t s
     hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = std::min(rows_per_block<R, LG>(), a.nx);
-        const size_t lds = (size_t)C * Lds<R, LG>::ld * sizeof(cplx<R>);
+        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_band * (2 * a.nx / C);
         PFB_LAUNCH((s1_kernel<R, LG, CONV_IN_X>), nb, lds, s, a, reinterpret_cast<const R *>(psf_img),
                    (R *)nullptr, 2 * a.nx, C, 1);
