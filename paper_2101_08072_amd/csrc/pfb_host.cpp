@@ -164,6 +164,8 @@ struct GridderHost {
     ColSplit cs{};
     std::vector<BandDev> bands;
     std::vector<int64_t> offsets;        // n_band * ntiles * nj0max + 1
+    std::vector<int64_t> hoffsets;       // same, over the home-entry list
+    int64_t n_home = 0;
     std::vector<GridWork> gwork;
     std::vector<InterpWork> iwork;
     std::vector<int> gband_start, iband_start;  // per band first work item (n_band + 1)
@@ -185,6 +187,9 @@ struct GridderHost {
     void *d_recs = nullptr, *d_omega = nullptr, *d_corr2d = nullptr, *d_corrx = nullptr, *d_corry = nullptr;
     size_t o_phase = 0;
     void *d_phase = nullptr;
+    size_t o_hidx = 0, o_hoffsets = 0;
+    uint32_t *d_hidx = nullptr;
+    int64_t *d_hoffsets = nullptr;
     int64_t keys() const { return (int64_t)g.n_band * g.ntx * g.nty * g.nj0max; }
 };
 
@@ -243,7 +248,7 @@ GeomDev base_geom(const pfb_plan &P, int nx, int ny, bool flat) {
 }
 
 // Work lists from the per-(band, tile, base plane) counts.
-void build_work(GridderHost &G, const std::vector<unsigned> &counts, int chunk) {
+void build_work(GridderHost &G, const std::vector<unsigned> &counts, const std::vector<unsigned> &hcounts, int chunk) {
     const GeomDev &g = G.g;
     const int ntiles = g.ntx * g.nty;
     const int W = g.flat ? 1 : g.W;
@@ -276,17 +281,20 @@ void build_work(GridderHost &G, const std::vector<unsigned> &counts, int chunk) 
                 gw.push_back({cost(p0, p1) * (int64_t)W + 1, GridWork{b, t, p0, p1}});
                 p0 = p1;
             }
-            // interpolation items: runs of <= chunk entries
-            int64_t e = G.offsets[kb];
-            const int64_t eend = e + tot;
+            // interpolation items: runs of <= chunk home entries
+            const unsigned *hc = hcounts.data() + kb;
+            int64_t htot = 0;
+            for (int q2 = 0; q2 < bd.nj0; ++q2) htot += hc[q2];
+            int64_t e = G.hoffsets[kb];
+            const int64_t eend = e + htot;
             int q = 0;
-            int64_t qend = G.offsets[kb] + c[0];
+            int64_t qend = G.hoffsets[kb] + hc[0];
             while (e < eend) {
-                while (e >= qend) qend += c[++q];
+                while (e >= qend) qend += hc[++q];
                 const int64_t e1 = std::min(eend, e + chunk);
                 int q1 = q;
                 int64_t qe = qend;
-                while (e1 > qe) qe += c[++q1];
+                while (e1 > qe) qe += hc[++q1];
                 iw.push_back({e1 - e, InterpWork{b, t, (int)e, (int)e1, q, q1}});
                 e = e1;
             }
@@ -393,6 +401,8 @@ InterpLaunch interp_args(const GridderHost &G, int b0, int nbb, int omode, const
     s.band0 = b0;
     s.omode = omode;
     s.phase = G.mfma ? G.d_phase : nullptr;
+    s.hidx = G.d_hidx;
+    s.hoffsets = G.d_hoffsets;
     return s;
 }
 
@@ -596,6 +606,8 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     const size_t t_bq = tl.take(Q.bands.size() * sizeof(BandDev));
     const size_t t_cm = tl.take(kM * sizeof(unsigned));
     const size_t t_cq = tl.take(kQ * sizeof(unsigned));
+    const size_t t_hm = tl.take(kM * sizeof(unsigned));
+    const size_t t_hq = tl.take(kQ * sizeof(unsigned));
     const size_t t_ctr = tl.take(8 * sizeof(unsigned long long));
     tmp_bytes = tl.off;
     char *tmp = nullptr;
@@ -606,7 +618,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
             return bail(PFB_ENOMEM);
         }
     }
-    std::vector<unsigned> cM(kM), cQ(kQ);
+    std::vector<unsigned> cM(kM), cQ(kQ), hM(kM), hQ(kQ);
     unsigned long long ctr[8] = {0};
     pfb_status st = PFB_OK;
     do {
@@ -624,6 +636,8 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         TMP_OK(hipMemcpyAsync(tmp + t_bq, Q.bands.data(), Q.bands.size() * sizeof(BandDev), hipMemcpyHostToDevice, stream));
         TMP_OK(hipMemsetAsync(tmp + t_cm, 0, kM * sizeof(unsigned), stream));
         TMP_OK(hipMemsetAsync(tmp + t_cq, 0, kQ * sizeof(unsigned), stream));
+        TMP_OK(hipMemsetAsync(tmp + t_hm, 0, kM * sizeof(unsigned), stream));
+        TMP_OK(hipMemsetAsync(tmp + t_hq, 0, kQ * sizeof(unsigned), stream));
         TMP_OK(hipMemsetAsync(tmp + t_ctr, 0, 8 * sizeof(unsigned long long), stream));
         BucketArgs ba{};
         ba.uvw = pr.uvw;
@@ -637,6 +651,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         ba.g = M.g;
         ba.bands = reinterpret_cast<const BandDev *>(tmp + t_bm);
         ba.counts = reinterpret_cast<unsigned *>(tmp + t_cm);
+        ba.home_counts = reinterpret_cast<unsigned *>(tmp + t_hm);
         ba.n_active = c;
         ba.n_flagged = c + 1;
         ba.n_bad = c + 2;
@@ -644,12 +659,15 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         ba.g = Q.g;
         ba.bands = reinterpret_cast<const BandDev *>(tmp + t_bq);
         ba.counts = reinterpret_cast<unsigned *>(tmp + t_cq);
+        ba.home_counts = reinterpret_cast<unsigned *>(tmp + t_hq);
         ba.n_active = c + 3;
         ba.n_flagged = c + 4;
         ba.n_bad = c + 5;
         TMP_OK(launch_count(dbl, ba, stream));
         TMP_OK(hipMemcpyAsync(cM.data(), tmp + t_cm, kM * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
         TMP_OK(hipMemcpyAsync(cQ.data(), tmp + t_cq, kQ * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+        TMP_OK(hipMemcpyAsync(hM.data(), tmp + t_hm, kM * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+        TMP_OK(hipMemcpyAsync(hQ.data(), tmp + t_hq, kQ * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
         TMP_OK(hipMemcpyAsync(ctr, c, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
         TMP_OK(hipStreamSynchronize(stream));
 #undef TMP_OK
@@ -674,6 +692,15 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         }
         G->offsets[cnt.size()] = acc;
         G->n_entries = acc;
+        const std::vector<unsigned> &hcnt = (G == &M) ? hM : hQ;
+        G->hoffsets.resize(hcnt.size() + 1);
+        int64_t hacc = 0;
+        for (size_t k = 0; k < hcnt.size(); ++k) {
+            G->hoffsets[k] = hacc;
+            hacc += hcnt[k];
+        }
+        G->hoffsets[hcnt.size()] = hacc;
+        G->n_home = hacc;
         if (acc >= (int64_t(1) << 31)) {
             fail(PFB_EUNSUPPORTED, "%lld bucket entries exceed 2^31", (long long)acc);
             return bail(PFB_EUNSUPPORTED);
@@ -681,7 +708,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         // work-item size: a given chunk, else about 1/1024 of all entries (>= 4096), so
         // that only tiles far heavier than the average are split
         const int chunk = opt.chunk ? opt.chunk : (int)std::min<int64_t>(std::max<int64_t>(4096, acc / 1024), 1 << 20);
-        build_work(*G, cnt, chunk);
+        build_work(*G, cnt, hcnt, chunk);
         G->sort_items.clear();
         for (size_t k2 = 0; k2 < cnt.size(); ++k2)
             if (cnt[k2]) {
@@ -747,6 +774,8 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         G->o_sortitems = L.take(std::max<size_t>(G->sort_items.size(), 4) * sizeof(int64_t));
         G->o_recs = L.take(std::max<int64_t>(G->n_entries, 1) * (dbl ? sizeof(Rec<double>) : sizeof(Rec<float>)));
         G->o_omega = L.take(std::max<int64_t>(G->n_entries, 1) * P->rsz);
+        G->o_hoffsets = L.take(G->hoffsets.size() * sizeof(int64_t));
+        G->o_hidx = L.take(std::max<int64_t>(G->n_home, 1) * sizeof(uint32_t));
         if (G->mfma) G->o_phase = L.take(std::max<int64_t>(G->n_entries, 1) * 2 * sizeof(float));
         if (G->corr2d) {
             G->o_corr2d = L.take((size_t)nb * G->g.nx * G->g.ny * P->rsz);
@@ -850,6 +879,8 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
         G->d_recs = P->p(G->o_recs);
         G->d_omega = P->p(G->o_omega);
         G->d_phase = G->mfma ? P->p(G->o_phase) : nullptr;
+        G->d_hidx = reinterpret_cast<uint32_t *>(P->p(G->o_hidx));
+        G->d_hoffsets = reinterpret_cast<int64_t *>(P->p(G->o_hoffsets));
         if (G->corr2d) {
             G->d_corr2d = P->p(G->o_corr2d);
         } else {
@@ -857,6 +888,8 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
             G->d_corry = P->p(G->o_corry);
         }
         HIP_OK(hipMemcpyAsync(G->d_bands, G->bands.data(), G->bands.size() * sizeof(BandDev), hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(G->d_hoffsets, G->hoffsets.data(), G->hoffsets.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s));
         HIP_OK(hipMemcpyAsync(G->d_offsets, G->offsets.data(), G->offsets.size() * sizeof(int64_t),
                               hipMemcpyHostToDevice, s));
         HIP_OK(hipMemcpyAsync(G->d_cursor, G->d_offsets, G->offsets.size() * sizeof(int64_t),
@@ -898,6 +931,8 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
                               G->n_entries, G->keys(), (int64_t)G->g.ntx * G->g.nty * G->g.nj0max,
                               pr.n_row * pr.n_chan, G->g.T, G->g.W, G->sort_rb, G->sort_cb, G->d_bands, G->d_phase,
                               sort_scratch, s));
+        LAUNCH_OK(launch_home_list(d, G->d_recs, reinterpret_cast<const int64_t *>(P->p(G->o_sortitems)),
+                                   (int)(G->sort_items.size() / 4), G->d_hoffsets, G->d_hidx, s));
         const double *cheb = reinterpret_cast<const double *>(P->p(P->o_cheb));
         const int nch = (int)P->cheb.size();
         if (G->corr2d) {

@@ -33,7 +33,7 @@ struct BandDev {
 struct GridWork {
     int band, tile, p0, p1;
 };
-// Interpolation work item: entries [e0, e1) of one tile, base planes [q0, q1].
+// Interpolation work item: positions [e0, e1) of one tile's home-entry list, base planes [q0, q1].
 struct InterpWork {
     int band, tile, e0, e1, q0, q1;
 };
@@ -63,6 +63,7 @@ struct BucketArgs {
     int64_t n_row, n_chan;
     // count pass
     unsigned int *counts;       // [n_band * ntiles * nj0max]
+    unsigned int *home_counts;  // same shape: entries listed under their own (home) tile
     unsigned long long *n_active, *n_flagged, *n_bad;
     // scatter pass
     unsigned long long *cursor; // [n_band * ntiles * nj0max] (starts at offsets)

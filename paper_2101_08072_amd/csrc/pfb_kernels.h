@@ -27,6 +27,9 @@ void set_thread_profiler(Profiler *p);
 
 hipError_t launch_count(bool dbl, const BucketArgs &a, hipStream_t s);
 hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s);
+// home-entry list: items as for launch_sort (after it), hoffsets per bucket
+hipError_t launch_home_list(bool dbl, const void *recs, const int64_t *items, int n_items, const int64_t *hoffsets,
+                            uint32_t *hidx, hipStream_t s);
 // Deterministic plan-time order of the entries of every bucket (pfb_sort.hip):
 // items are [start, count, band, bucket] quadruples of the non-empty buckets;
 // entries are ordered by (bucket, block of rb x cb base cells, visibility index);
@@ -84,6 +87,8 @@ struct InterpLaunch {
     int omode;
     const void *phase;    // FP32 w-stacked gridder: exp(2 pi i s_c w) per entry (else null: computed)
     float *absmax;        // FP32, OMODE 1: raised to max |value| x 1.0001 (cleared by the caller), or null
+    const uint32_t *hidx;       // home-entry list (entry positions)
+    const int64_t *hoffsets;    // per bucket: start of its home entries in hidx
 };
 hipError_t launch_interp(bool dbl, const InterpLaunch &a, hipStream_t s);
 hipError_t launch_zero_flagged(bool dbl, const uint32_t *flagged, int64_t n, void *vis, hipStream_t s);

@@ -206,6 +206,7 @@ __global__ __launch_bounds__(kThreads) void bucket_kernel(BucketArgs a) {
                 const int64_t key = ((int64_t)b * ntiles + tile) * a.g.nj0max + k.j0;
                 if (!SCATTER) {
                     atomicAdd(a.counts + key, 1u);
+                    if (ou == 0 && ov == 0) atomicAdd(a.home_counts + key, 1u);
                 } else {
                     const unsigned long long pos = atomicAdd(a.cursor + key, 1ull);
                     Rec<R> rec;
@@ -243,6 +244,41 @@ static hipError_t launch_bucket(bool dbl, const BucketArgs &a, hipStream_t s) {
 }
 hipError_t launch_count(bool dbl, const BucketArgs &a, hipStream_t s) { return launch_bucket<false>(dbl, a, s); }
 hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s) { return launch_bucket<true>(dbl, a, s); }
+
+// Home-entry list of every bucket (plan time): the positions of the entries
+// that carry kHomeBit, in bucket order (a stable, deterministic compaction),
+// at hoffsets[bucket].  The interpolation walks this list, so it neither
+// visits nor balances its work over the copies listed for neighbouring tiles.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void home_list_kernel(const Rec<R> *recs, const int64_t *items,
+                                                             const int64_t *hoffsets, uint32_t *hidx) {
+    __shared__ unsigned wcount[kThreads / 64];
+    const int64_t start = items[4 * blockIdx.x], n = items[4 * blockIdx.x + 1], key = items[4 * blockIdx.x + 3];
+    int64_t out = hoffsets[key];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t base = 0; base < n; base += kThreads) {
+        const int64_t e = base + threadIdx.x;
+        const bool home = e < n && (recs[start + e].idx & kHomeBit);
+        const unsigned long long m = __ballot(home);
+        if (lane == 0) wcount[wv] = (unsigned)__popcll(m);
+        __syncthreads();
+        unsigned before = 0, total = 0;
+        for (int k = 0; k < kThreads / 64; ++k) {
+            if (k < wv) before += wcount[k];
+            total += wcount[k];
+        }
+        if (home) hidx[out + before + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)(start + e);
+        out += total;
+        __syncthreads();
+    }
+}
+hipError_t launch_home_list(bool dbl, const void *recs, const int64_t *items, int n_items, const int64_t *hoffsets,
+                            uint32_t *hidx, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    if (dbl) PFB_LAUNCH(home_list_kernel<double>, n_items, 0, s, (const Rec<double> *)recs, items, hoffsets, hidx);
+    else PFB_LAUNCH(home_list_kernel<float>, n_items, 0, s, (const Rec<float> *)recs, items, hoffsets, hidx);
+    return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // grid correction
@@ -1108,13 +1144,13 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
 
     R vmax2 = R(0);   // OMODE 1: largest |value|^2 written (scale of the FP32 spread that follows)
     for (int q = wk.q0; q <= wk.q1; ++q) {
-        const int64_t lo = max((int64_t)wk.e0, a.offsets[keybase + q]);
-        const int64_t hi = min((int64_t)wk.e1, a.offsets[keybase + q + 1]);
+        const int64_t lo = max((int64_t)wk.e0, a.hoffsets[keybase + q]);
+        const int64_t hi = min((int64_t)wk.e1, a.hoffsets[keybase + q + 1]);
         const int64_t n = max(hi - lo, (int64_t)0), per = (n + NGRP - 1) / NGRP;
         const int64_t e_end = lo + min(n, (grp + 1) * per);
-        for (int64_t e = lo + min(n, grp * per); e < e_end; ++e) {
+        for (int64_t h = lo + min(n, grp * per); h < e_end; ++h) {
+            const int64_t e = a.hidx[h];      // entry listed under its own tile
             const Rec<R> rec = recs[e];
-            if (!(rec.idx & kHomeBit)) continue;
             const int i0 = (int)dev_floor(rec.fu - hw) + 1;
             const int j0 = (int)dev_floor(rec.fv - hw) + 1;
             R pu = R(0), pv = R(0), pw = R(1);
