@@ -1139,6 +1139,7 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
     const int lane = threadIdx.x % LPV;
     const int grp = threadIdx.x / LPV;
     const R beta = (R)a.g.beta, inv_hw = R(2) / R(W), hw = R(0.5) * R(W);
+    const float beta2 = (float)(a.g.beta * 1.4426950408889634);
     const R w0 = (R)bd.w0, dw = (R)bd.dw, sc = (R)bd.sc;
     const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
 
@@ -1155,9 +1156,15 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
             const int j0 = (int)dev_floor(rec.fv - hw) + 1;
             R pu = R(0), pv = R(0), pw = R(1);
             if (lane < W) {
-                pu = es_kernel<R>(R(i0 + lane) - rec.fu, beta, inv_hw);
-                pv = es_kernel<R>(R(j0 + lane) - rec.fv, beta, inv_hw);
-                if (!FLAT) pw = es_kernel<R>(R(q + lane) - rec.fw, beta, inv_hw);
+                if constexpr (sizeof(R) == 4) {   // hardware exp2 / sqrt
+                    pu = es_kernel_fast(R(i0 + lane) - rec.fu, beta2, inv_hw);
+                    pv = es_kernel_fast(R(j0 + lane) - rec.fv, beta2, inv_hw);
+                    if (!FLAT) pw = es_kernel_fast(R(q + lane) - rec.fw, beta2, inv_hw);
+                } else {
+                    pu = es_kernel<R>(R(i0 + lane) - rec.fu, beta, inv_hw);
+                    pv = es_kernel<R>(R(j0 + lane) - rec.fv, beta, inv_hw);
+                    if (!FLAT) pw = es_kernel<R>(R(q + lane) - rec.fw, beta, inv_hw);
+                }
             }
             R wu[W];
 #pragma unroll
