@@ -156,14 +156,14 @@ template <typename R, bool INV> __device__ __forceinline__ cplx<R> twiddle(const
 }
 
 // One DIT stage of radix RAD at span m over C vectors stored at buf + c*ld.
-template <typename R, bool INV, int RAD, int LOG2L>
+template <typename R, bool INV, int RAD, int LOG2L, int NT>
 __device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, const TwTab<R> &tw, int tw_shift) {
     constexpr int L = 1 << LOG2L;
     constexpr int NB = L / RAD;               // butterflies per vector
     const int total = NB * C;
     // table index step for w_{RAD m}^{t j}: Lmax / (RAD m) = (Lmax / L) * (L / (RAD m))
     const int estep = (L / (RAD * m)) << tw_shift;
-    for (int id = threadIdx.x; id < total; id += kThreads) {
+    for (int id = threadIdx.x; id < total; id += NT) {
         const int c = id / NB;
         const int bfly = id - c * NB;
         const int j = bfly % m;
@@ -183,9 +183,10 @@ __device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, co
     }
 }
 
-// Full in-place FFT of C vectors of length 2^LOG2L already loaded in DIT order.
-// Ends with a barrier; the result is in natural order at Lds<R, LOG2L>::pad(k).
-template <typename R, bool INV, int LOG2L>
+// Full in-place FFT of C vectors of length 2^LOG2L already loaded in DIT order,
+// by a block of NT threads.  Ends with a barrier; the result is in natural
+// order at Lds<R, LOG2L>::pad(k).
+template <typename R, bool INV, int LOG2L, int NT = kThreads>
 __device__ __forceinline__ void lds_fft(cplx<R> *buf, int C, int ld, const TwTab<R> &tw, int tw_shift) {
     using P = FftPlan<LOG2L>;
     int m = 1;
@@ -194,9 +195,9 @@ __device__ __forceinline__ void lds_fft(cplx<R> *buf, int C, int ld, const TwTab
         constexpr int dummy = 0;
         (void)dummy;
         const int RAD = P::radix(st);
-        if (RAD == 2) dit_stage<R, INV, 2, LOG2L>(buf, C, ld, m, tw, tw_shift);
-        else if (RAD == 4) dit_stage<R, INV, 4, LOG2L>(buf, C, ld, m, tw, tw_shift);
-        else dit_stage<R, INV, 8, LOG2L>(buf, C, ld, m, tw, tw_shift);
+        if (RAD == 2) dit_stage<R, INV, 2, LOG2L, NT>(buf, C, ld, m, tw, tw_shift);
+        else if (RAD == 4) dit_stage<R, INV, 4, LOG2L, NT>(buf, C, ld, m, tw, tw_shift);
+        else dit_stage<R, INV, 8, LOG2L, NT>(buf, C, ld, m, tw, tw_shift);
         m *= RAD;
         __syncthreads();
     }

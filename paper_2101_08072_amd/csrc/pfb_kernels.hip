@@ -92,8 +92,8 @@ __device__ __forceinline__ int wrapi(int a, int n) {
     return a < 0 ? a + n : a;
 }
 
-// block-wide FP64 sum; result valid in thread 0
-__device__ double block_sum(double v, double *red) {
+// block-wide FP64 sum over NT threads; result valid in thread 0
+template <int NT = kThreads> __device__ double block_sum(double v, double *red) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     const int wid = threadIdx.x >> 6, ln = threadIdx.x & 63;
     __syncthreads();
@@ -101,7 +101,7 @@ __device__ double block_sum(double v, double *red) {
     __syncthreads();
     double t = 0;
     if (threadIdx.x == 0)
-        for (int k = 0; k < kThreads / 64; ++k) t += red[k];
+        for (int k = 0; k < NT / 64; ++k) t += red[k];
     return t;
 }
 
@@ -1283,6 +1283,11 @@ __device__ __forceinline__ R pixel_sm1(int i, int j, int nx, int ny, R cellx, R 
 
 constexpr int kRowLds = 32768;   // target LDS bytes per row-transform workgroup
 
+// Threads of a row-transform block: one radix-8 butterfly per thread and stage
+// for long rows (more waves in flight per row), at least kThreads.
+template <int LOG2L> __host__ __device__ constexpr int row_threads() {
+    return (1 << LOG2L) / 8 > 1024 ? 1024 : ((1 << LOG2L) / 8 < kThreads ? kThreads : (1 << LOG2L) / 8);
+}
 // rows per workgroup: the largest power of two whose LDS tiles fit kRowLds
 template <typename R, int LOG2L>
 __host__ __device__ constexpr int rows_per_block() {
@@ -1295,12 +1300,12 @@ __host__ __device__ constexpr int rows_per_block() {
 
 // G1: inverse row DFT of every plane row, keeping the ny cropped outputs.
 template <typename R, int LOG2L>
-__global__ __launch_bounds__(kThreads) void g1_rows_kernel(XformArgs a, int C) {
+__global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformArgs a, int C) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
     cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int gx = a.g.gx, ny = a.g.ny;
     const int ngrp = gx / C;
@@ -1314,13 +1319,13 @@ __global__ __launch_bounds__(kThreads) void g1_rows_kernel(XformArgs a, int C) {
     const size_t plane = (size_t)bb * a.g.nwmax + j;
     const cplx<R> *src = reinterpret_cast<const cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.t1) + (plane * gx + (size_t)ug * C) * ny;
-    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, r = id - c * L;
         buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = src[(size_t)c * L + r];
     }
     __syncthreads();
-    lds_fft<R, true, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
-    for (int id = threadIdx.x; id < C * ny; id += kThreads) {
+    lds_fft<R, true, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
+    for (int id = threadIdx.x; id < C * ny; id += row_threads<LOG2L>()) {
         const int c = id / ny, iy = id - c * ny;
         const int k = wrapi(iy - ny / 2, L);
         dst[(size_t)c * ny + iy] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
@@ -1519,12 +1524,12 @@ __global__ __launch_bounds__(kThreads) void d2_kernel(XformArgs a) {
 
 // D3: forward row DFT of the ny placed inputs of each row, full output to the plane.
 template <typename R, int LOG2L>
-__global__ __launch_bounds__(kThreads) void d3_rows_kernel(XformArgs a, int C, const void *src_v) {
+__global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformArgs a, int C, const void *src_v) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
     cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int gx = a.g.gx, ny = a.g.ny;
     const int ngrp = gx / C;
@@ -1538,14 +1543,14 @@ __global__ __launch_bounds__(kThreads) void d3_rows_kernel(XformArgs a, int C, c
     const size_t plane = (size_t)bb * a.g.nwmax + j;
     const cplx<R> *src = reinterpret_cast<const cplx<R> *>(src_v) + (plane * gx + (size_t)ug * C) * ny;
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
-    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, r = id - c * L;
         const int iy = wrapi(r + ny / 2, L);
         buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = iy < ny ? src[(size_t)c * ny + iy] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
-    lds_fft<R, false, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
-    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+    lds_fft<R, false, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
+    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, k = id - c * L;
         dst[(size_t)c * L + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
     }
@@ -1559,7 +1564,7 @@ static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
         const int C = std::min(rows_per_block<R, LG>(), a.g.gx);
         const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C);
-        PFB_LAUNCH((g1_rows_kernel<R, LG>), nb, lds, s, a, C);
+        PFB_LAUNCH_NT((g1_rows_kernel<R, LG>), nb, row_threads<LG>(), lds, s, a, C);
         return hipSuccess;
     });
     if (e != hipSuccess) return e;
@@ -1623,7 +1628,7 @@ static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
         const int C2 = std::min(rows_per_block<R, LG>(), a.g.gx);
         const size_t lds = (size_t)C2 * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C2);
-        PFB_LAUNCH((d3_rows_kernel<R, LG>), nb, lds, s, a, C2, rows_src);
+        PFB_LAUNCH_NT((d3_rows_kernel<R, LG>), nb, row_threads<LG>(), lds, s, a, C2, rows_src);
         return hipSuccess;
     });
 }
@@ -1645,12 +1650,12 @@ hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s) {
 //           CONV_IN_SCALED : x * scale
 //   psfhat mode (nrows = 2nx): row i of the PSF rolled by (nx, ny)
 template <typename R, int LOG2L, int IN>
-__global__ __launch_bounds__(kThreads) void s1_kernel(ConvArgs a, const R *x, R *auxp, int nrows, int C, int psf) {
+__global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a, const R *x, R *auxp, int nrows, int C, int psf) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
     cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
     const int ngrp = nrows / C;
@@ -1659,7 +1664,7 @@ __global__ __launch_bounds__(kThreads) void s1_kernel(ConvArgs a, const R *x, R 
     R bscale = R(1);
     if (IN == CONV_IN_CG_P) bscale = (R)a.scal[b * 8 + S_BETA];
     if (IN == CONV_IN_SCALED) bscale = (R)a.scal[b * 8 + S_SCALE];
-    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, r = id - c * L;
         const int i = ig * C + c;
         R v = R(0);
@@ -1680,9 +1685,9 @@ __global__ __launch_bounds__(kThreads) void s1_kernel(ConvArgs a, const R *x, R 
         buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = cplx<R>{v, R(0)};
     }
     __syncthreads();
-    lds_fft<R, false, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
+    lds_fft<R, false, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * C) * a.ldh;
-    for (int id = threadIdx.x; id < C * (ny + 1); id += kThreads) {
+    for (int id = threadIdx.x; id < C * (ny + 1); id += row_threads<LOG2L>()) {
         const int c = id / (ny + 1), k = id - c * (ny + 1);
         t1[(size_t)c * a.ldh + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
     }
@@ -1887,29 +1892,29 @@ __global__ __launch_bounds__(kThreads) void s2c_kernel(ConvArgs a) {
 // S3: inverse row DFT (length 2ny) of the Hermitian half spectrum, real part,
 // cropped to ny, scaled by 1 / (4 nx ny), with fused epilogues.
 template <typename R, int LOG2L, int OUT>
-__global__ __launch_bounds__(kThreads) void s3_kernel(ConvArgs a, R *y, const R *aux, R sigma, int C) {
+__global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a, R *y, const R *aux, R sigma, int C) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
     cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
-    __shared__ double red[kThreads / 64];
+    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    __shared__ double red[row_threads<LOG2L>() / 64];
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
     const int ngrp = nx / C;
     const int ig = blockIdx.x % ngrp;
     const int b = blockIdx.x / ngrp;
     const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * C) * a.ldh;
-    for (int id = threadIdx.x; id < C * L; id += kThreads) {
+    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, k = id - c * L;
         const cplx<R> v = k <= ny ? t1[(size_t)c * a.ldh + k] : conj(t1[(size_t)c * a.ldh + (L - k)]);
         buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(k))] = v;
     }
     __syncthreads();
-    lds_fft<R, true, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
+    lds_fft<R, true, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     const R scale = R(1) / (R(4) * R(nx) * R(ny));
     double part = 0.0;
-    for (int id = threadIdx.x; id < C * ny; id += kThreads) {
+    for (int id = threadIdx.x; id < C * ny; id += row_threads<LOG2L>()) {
         const int c = id / ny, j = id - c * ny;
         const size_t pix = ((size_t)b * nx + ig * C + c) * ny + j;
         R v = buf[c * ld + Lds<R, LOG2L>::pad(j)].re * scale;
@@ -1924,7 +1929,7 @@ __global__ __launch_bounds__(kThreads) void s3_kernel(ConvArgs a, R *y, const R 
         y[pix] = v;
     }
     if (OUT == CONV_OUT_CG || OUT == CONV_OUT_NORM || OUT == CONV_OUT_DOT) {
-        const double t = block_sum(part, red);
+        const double t = block_sum<row_threads<LOG2L>()>(part, red);
         if (threadIdx.x == 0) a.partials[(size_t)b * a.max_partials + ig] = t;
     }
 }
@@ -1974,9 +1979,9 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
         const int nb = a.n_band * (a.nx / C);
         const R *xr = reinterpret_cast<const R *>(x);
         R *ap = reinterpret_cast<R *>(aux_in);
-        if (in_mode == CONV_IN_X) PFB_LAUNCH((s1_kernel<R, LG, CONV_IN_X>), nb, lds, s, a, xr, ap, a.nx, C, 0);
-        else if (in_mode == CONV_IN_CG_P) PFB_LAUNCH((s1_kernel<R, LG, CONV_IN_CG_P>), nb, lds, s, a, xr, ap, a.nx, C, 0);
-        else PFB_LAUNCH((s1_kernel<R, LG, CONV_IN_SCALED>), nb, lds, s, a, xr, ap, a.nx, C, 0);
+        if (in_mode == CONV_IN_X) PFB_LAUNCH_NT((s1_kernel<R, LG, CONV_IN_X>), nb, row_threads<LG>(), lds, s, a, xr, ap, a.nx, C, 0);
+        else if (in_mode == CONV_IN_CG_P) PFB_LAUNCH_NT((s1_kernel<R, LG, CONV_IN_CG_P>), nb, row_threads<LG>(), lds, s, a, xr, ap, a.nx, C, 0);
+        else PFB_LAUNCH_NT((s1_kernel<R, LG, CONV_IN_SCALED>), nb, row_threads<LG>(), lds, s, a, xr, ap, a.nx, C, 0);
         return hipSuccess;
     });
     if (e != hipSuccess) return e;
@@ -1991,11 +1996,11 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
         const R *ax = reinterpret_cast<const R *>(aux_out);
         const R sg = (R)sigma;
         switch (out_mode) {
-            case CONV_OUT_Y: PFB_LAUNCH((s3_kernel<R, LG, CONV_OUT_Y>), nb, lds, s, a, yr, ax, sg, C); break;
-            case CONV_OUT_SUB: PFB_LAUNCH((s3_kernel<R, LG, CONV_OUT_SUB>), nb, lds, s, a, yr, ax, sg, C); break;
-            case CONV_OUT_CG: PFB_LAUNCH((s3_kernel<R, LG, CONV_OUT_CG>), nb, lds, s, a, yr, ax, sg, C); break;
-            case CONV_OUT_NORM: PFB_LAUNCH((s3_kernel<R, LG, CONV_OUT_NORM>), nb, lds, s, a, yr, ax, sg, C); break;
-            default: PFB_LAUNCH((s3_kernel<R, LG, CONV_OUT_DOT>), nb, lds, s, a, yr, ax, sg, C); break;
+            case CONV_OUT_Y: PFB_LAUNCH_NT((s3_kernel<R, LG, CONV_OUT_Y>), nb, row_threads<LG>(), lds, s, a, yr, ax, sg, C); break;
+            case CONV_OUT_SUB: PFB_LAUNCH_NT((s3_kernel<R, LG, CONV_OUT_SUB>), nb, row_threads<LG>(), lds, s, a, yr, ax, sg, C); break;
+            case CONV_OUT_CG: PFB_LAUNCH_NT((s3_kernel<R, LG, CONV_OUT_CG>), nb, row_threads<LG>(), lds, s, a, yr, ax, sg, C); break;
+            case CONV_OUT_NORM: PFB_LAUNCH_NT((s3_kernel<R, LG, CONV_OUT_NORM>), nb, row_threads<LG>(), lds, s, a, yr, ax, sg, C); break;
+            default: PFB_LAUNCH_NT((s3_kernel<R, LG, CONV_OUT_DOT>), nb, row_threads<LG>(), lds, s, a, yr, ax, sg, C); break;
         }
         return hipSuccess;
     });
@@ -2027,7 +2032,7 @@ static hipError_t psfhat_t(const ConvArgs &a, const void *psf_img, hipStream_t s
         const int C = std::min(rows_per_block<R, LG>(), a.nx);
         const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_band * (2 * a.nx / C);
-        PFB_LAUNCH((s1_kernel<R, LG, CONV_IN_X>), nb, lds, s, a, reinterpret_cast<const R *>(psf_img),
+        PFB_LAUNCH_NT((s1_kernel<R, LG, CONV_IN_X>), nb, row_threads<LG>(), lds, s, a, reinterpret_cast<const R *>(psf_img),
                    (R *)nullptr, 2 * a.nx, C, 1);
         return hipSuccess;
     });
