@@ -110,7 +110,7 @@ typedef struct {
     int32_t flat;         /* 1: drop the w term and the 1/n factor from R (w = 0, n = 1)     */
     int32_t band_batch;   /* bands whose w-planes are resident at once; default n_band       */
     int32_t chunk;        /* bucket entries per work item before a tile is split (>= 64);
-                             default max(4096, entries / 1024)                              */
+                             default max(4096, entries / compute units of the device)       */
     int32_t reserved[7];
 } pfb_options;
 

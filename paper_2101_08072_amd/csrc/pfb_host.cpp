@@ -705,9 +705,17 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
             fail(PFB_EUNSUPPORTED, "%lld bucket entries exceed 2^31", (long long)acc);
             return bail(PFB_EUNSUPPORTED);
         }
-        // work-item size: a given chunk, else about 1/1024 of all entries (>= 4096), so
-        // that only tiles far heavier than the average are split
-        const int chunk = opt.chunk ? opt.chunk : (int)std::min<int64_t>(std::max<int64_t>(4096, acc / 1024), 1 << 20);
+        // work-item size: a given chunk, else one compute unit's share of all entries
+        // (>= 4096): a spread item split by plane range re-reads the entries of the
+        // W - 1 base planes its neighbour also covers, so only tiles heavier than a
+        // unit's share are split
+        int n_cu = 0;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+            n_cu = 256;
+        const int chunk = opt.chunk ? opt.chunk
+                                    : (int)std::min<int64_t>(std::max<int64_t>(4096, acc / n_cu), 1 << 24);
         build_work(*G, cnt, hcnt, chunk);
         G->sort_items.clear();
         for (size_t k2 = 0; k2 < cnt.size(); ++k2)

@@ -22,7 +22,7 @@ class Options:
     tile: int = 0               # uv tile side (0 = default: 32 fp32, 8 fp64)
     flat: bool = False          # drop the w term and 1/n (w = 0, n = 1)
     band_batch: int = 0         # bands whose w-planes are resident together (0 = all that fit)
-    chunk: int = 0              # visibilities per work item (0 = 4096)
+    chunk: int = 0              # bucket entries per work item (0 = entries / compute units)
 
     def to_c(self) -> _lib.PfbOptions:
         o = _lib.PfbOptions()
