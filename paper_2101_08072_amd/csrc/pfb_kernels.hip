@@ -838,12 +838,27 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                 const int base = I * T + J + ioff;
                 const bool colok = J + r >= 0 && J + r < T;
                 const bool rows_in = I >= 0 && I + 8 <= T;    // wave-uniform
+                if (rows_in) {    // one lane mask per tile, no per-row tests
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        if (colok && koff[t] >= 0) {
+                            const int idx = koff[t] + base;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                atomicAdd(sre + idx + v * T, f2fix(cre[t][v]));
+                                atomicAdd(sim + idx + v * T, f2fix(cim[t][v]));
+                            }
+                        }
+                        cre[t] = cim[t] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
+                    }
+                    return;
+                }
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int row = I + 4 * (sg & 1) + v;
-                        if (colok && koff[t] >= 0 && (rows_in || (row >= 0 && row < T))) {
+                        if (colok && koff[t] >= 0 && row >= 0 && row < T) {
                             const int idx = koff[t] + base + v * T;
                             atomicAdd(sre + idx, f2fix(cre[t][v]));
                             atomicAdd(sim + idx, f2fix(cim[t][v]));
@@ -897,13 +912,15 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                     odv = R_(wb * CB - (W - 1)) - rec_c.fv;
                     odq = R_(q) - rec_c.fw;
                 }
+                // operands of group 0 of the batch; each group fetches those of the next
+                // one before its matrix products, so the crossbar latency overlaps them
+                const int own0 = sg * 4;                // byte address of the owner lane
+                R_ du = bperm_f(own0, odu), dv = bperm_f(own0, odv), dq = bperm_f(own0, odq);
+                R_ zr = bperm_f(own0, val_c.re), zi = bperm_f(own0, val_c.im);
+                int key = __builtin_amdgcn_ds_bpermute(own0, okey);
 #pragma unroll 1
                 for (int g4 = 0; g4 < nbatch; g4 += 4) {
                     const int nb = min(4, nbatch - g4);
-                    const int own = (g4 + sg) * 4;      // byte address of the owner lane
-                    const R_ du = bperm_f(own, odu), dv = bperm_f(own, odv), dq = bperm_f(own, odq);
-                    const R_ zr = bperm_f(own, val_c.re), zi = bperm_f(own, val_c.im);
-                    const int key = __builtin_amdgcn_ds_bpermute(own, okey);
                     const bool hi = r >= 8;               // rows 8..15 of a tile: its second plane
                     const R_ E = (hi && r - 8 >= W) ? R_(0)
                                                     : es_kernel_fast(hi ? dq + R_(r - 8) : du + R_(r), beta2, inv_hw);
@@ -923,6 +940,16 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                     int keys[4];
 #pragma unroll
                     for (int g = 0; g < 4; ++g) keys[g] = rdlane(key, 16 * g);
+                    {
+                        // next group (after the last group of the batch: unused)
+                        const int own = ((g4 + 4 + sg) & 63) * 4;
+                        du = bperm_f(own, odu);
+                        dv = bperm_f(own, odv);
+                        dq = bperm_f(own, odq);
+                        zr = bperm_f(own, val_c.re);
+                        zi = bperm_f(own, val_c.im);
+                        key = __builtin_amdgcn_ds_bpermute(own, okey);
+                    }
                     unsigned rem = (1u << nb) - 1u;
                     while (rem) {
                         const int f = __builtin_ctz(rem);
