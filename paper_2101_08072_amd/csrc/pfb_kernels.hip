@@ -1128,6 +1128,29 @@ hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s) {
 // slides one plane at a time.  Each visibility is computed once, from its home
 // tile; lanes of a group own footprint columns and the partial sums are
 // reduced across the group with lane shuffles.
+// Lane exchange inside groups of 8 lanes (FP32 interpolation) with DPP instead
+// of the LDS crossbar, which the tap reads keep busy; all 8 lanes of a group must
+// be active.  Value of lane I of the group: row_newbcast of lane I (lanes 0-7 of
+// the 16-lane row, banks 0-1) and of lane 8 + I (lanes 8-15, banks 2-3).
+template <int I> __device__ __forceinline__ float grp8_bcast(float v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + I, 0xf, 0x3, false);
+    return __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x158 + I, 0xf, 0xc, false));
+}
+template <int N, int I = 0> __device__ __forceinline__ void grp8_bcast_all(float v, float *out) {
+    if constexpr (I < N) {
+        out[I] = grp8_bcast<I>(v);
+        grp8_bcast_all<N, I + 1>(v, out);
+    }
+}
+// sum over the group, valid in its lane 0: quad_perm [1,0,3,2], [2,3,0,1], then
+// row_half_mirror (lane i of the 8 takes lane 7 - i) adds the other quad
+__device__ __forceinline__ float grp8_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4e, 0xf, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xf, 0xf, false));
+    return v;
+}
+
 template <typename R, int W, int LPV, bool FLAT, int OMODE>
 __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
     constexpr int WW = FLAT ? 1 : W;
@@ -1194,14 +1217,20 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
                 }
             }
             R wu[W];
-#pragma unroll
-            for (int i = 0; i < W; ++i) wu[i] = __shfl(pu, i, LPV);
             R ww[WW];
-            if (FLAT) {
-                ww[0] = R(1);
+            if constexpr (sizeof(R) == 4 && LPV == 8) {
+                grp8_bcast_all<W>(pu, wu);
+                if constexpr (FLAT) ww[0] = R(1);
+                else grp8_bcast_all<WW>(pw, ww);
             } else {
 #pragma unroll
-                for (int k = 0; k < WW; ++k) ww[k] = __shfl(pw, k, LPV);
+                for (int i = 0; i < W; ++i) wu[i] = __shfl(pu, i, LPV);
+                if (FLAT) {
+                    ww[0] = R(1);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < WW; ++k) ww[k] = __shfl(pw, k, LPV);
+                }
             }
             cplx<R> acc{R(0), R(0)};
             if (lane < W) {
@@ -1222,10 +1251,15 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
                 acc.re *= pv;
                 acc.im *= pv;
             }
+            if constexpr (sizeof(R) == 4 && LPV == 8) {
+                acc.re = grp8_sum(acc.re);
+                acc.im = grp8_sum(acc.im);
+            } else {
 #pragma unroll
-            for (int off = LPV / 2; off >= 1; off >>= 1) {
-                acc.re += __shfl_xor(acc.re, off, LPV);
-                acc.im += __shfl_xor(acc.im, off, LPV);
+                for (int off = LPV / 2; off >= 1; off >>= 1) {
+                    acc.re += __shfl_xor(acc.re, off, LPV);
+                    acc.im += __shfl_xor(acc.im, off, LPV);
+                }
             }
             if (lane == 0) {
                 const uint32_t vid = rec.idx & ~kHomeBit;
