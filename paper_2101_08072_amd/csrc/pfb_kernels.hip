@@ -1199,9 +1199,32 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
         const int64_t hi = min((int64_t)wk.e1, a.hoffsets[keybase + q + 1]);
         const int64_t n = max(hi - lo, (int64_t)0), per = (n + NGRP - 1) / NGRP;
         const int64_t e_end = lo + min(n, (grp + 1) * per);
-        for (int64_t h = lo + min(n, grp * per); h < e_end; ++h) {
-            const int64_t e = a.hidx[h];      // entry listed under its own tile
-            const Rec<R> rec = recs[e];
+        // FP32: the entry index (home list) and record of the next visibility are
+        // loaded while the current one is interpolated (FP64 has no registers to spare)
+        constexpr bool kPrefetch = sizeof(R) == 4;
+        int64_t h = lo + min(n, grp * per);
+        int64_t e_n = 0, e_nn = 0;
+        Rec<R> rec_n{R(0), R(0), R(0), 0u};
+        if constexpr (kPrefetch) {
+            if (h < e_end) {
+                e_n = a.hidx[h];
+                rec_n = recs[e_n];
+            }
+            if (h + 1 < e_end) e_nn = a.hidx[h + 1];
+        }
+        for (; h < e_end; ++h) {
+            int64_t e;                        // entry listed under its own tile
+            Rec<R> rec;
+            if constexpr (kPrefetch) {
+                e = e_n;
+                rec = rec_n;
+                e_n = e_nn;
+                if (h + 1 < e_end) rec_n = recs[e_n];
+                e_nn = h + 2 < e_end ? (int64_t)a.hidx[h + 2] : 0;
+            } else {
+                e = a.hidx[h];
+                rec = recs[e];
+            }
             const int i0 = (int)dev_floor(rec.fu - hw) + 1;
             const int j0 = (int)dev_floor(rec.fv - hw) + 1;
             R pu = R(0), pv = R(0), pw = R(1);
