@@ -170,13 +170,16 @@ struct GridderHost {
     std::vector<InterpWork> iwork;
     std::vector<int> gband_start, iband_start;  // per band first work item (n_band + 1)
     std::vector<int64_t> sort_items;     // [start, count, band, bucket] of every non-empty bucket
+    // per (band, plane, tile): occ = the spread puts non-zero values there; need = the
+    // interpolation may read it (occ dilated by one tile, the halo reach)
+    std::vector<uint8_t> occ, need;
     bool mfma = false;                   // FP32 w-stacked: matrix-core spread (window sort, phase table)
     int sort_rb = 1, sort_cb = 1;        // sort blocks of base rows x columns
     int64_t n_entries = 0;
     size_t o_sortitems = 0;
     // workspace offsets
     size_t o_bands = 0, o_offsets = 0, o_cursor = 0, o_gwork = 0, o_iwork = 0, o_recs = 0, o_omega = 0;
-    size_t o_corr2d = 0, o_corrx = 0, o_corry = 0;
+    size_t o_corr2d = 0, o_corrx = 0, o_corry = 0, o_occ = 0, o_need = 0;
     bool corr2d = true;
     // device pointers (valid after set_workspace)
     BandDev *d_bands = nullptr;
@@ -190,6 +193,7 @@ struct GridderHost {
     size_t o_hidx = 0, o_hoffsets = 0;
     uint32_t *d_hidx = nullptr;
     int64_t *d_hoffsets = nullptr;
+    const uint8_t *d_occ = nullptr, *d_need = nullptr;
     int64_t keys() const { return (int64_t)g.n_band * g.ntx * g.nty * g.nj0max; }
 };
 
@@ -258,6 +262,9 @@ void build_work(GridderHost &G, const std::vector<unsigned> &counts, const std::
     G.iband_start.assign(g.n_band + 1, 0);
     std::vector<std::pair<int64_t, GridWork>> gw;
     std::vector<std::pair<int64_t, InterpWork>> iw;
+    const size_t nflag = (size_t)g.n_band * g.nwmax * ntiles;
+    G.occ.assign(nflag, 0);
+    G.need.assign(nflag, 0);
     for (int b = 0; b < g.n_band; ++b) {
         const BandDev &bd = G.bands[b];
         gw.clear();
@@ -266,9 +273,14 @@ void build_work(GridderHost &G, const std::vector<unsigned> &counts, const std::
             const int64_t kb = ((int64_t)b * ntiles + t) * g.nj0max;
             const unsigned *c = counts.data() + kb;
             int64_t tot = 0;
-            for (int q = 0; q < bd.nj0; ++q) tot += c[q];
-            // spread items: split the plane range so each item sees <= chunk entries
-            const int nw = bd.nw;
+            for (int q = 0; q < bd.nj0; ++q) {
+                tot += c[q];
+                if (c[q])   // base plane q reaches planes q .. q + W - 1
+                    for (int p = q; p < std::min(q + W, bd.nw); ++p) G.occ[((size_t)b * g.nwmax + p) * ntiles + t] = 1;
+            }
+            // spread items: split the plane range so each item sees <= chunk entries;
+            // tiles without entries get none (the row transforms read them as zero)
+            const int nw = tot ? bd.nw : 0;
             int p0 = 0;
             while (p0 < nw) {
                 int p1 = p0 + 1;
@@ -298,6 +310,18 @@ void build_work(GridderHost &G, const std::vector<unsigned> &counts, const std::
                 iw.push_back({e1 - e, InterpWork{b, t, (int)e, (int)e1, q, q1}});
                 e = e1;
             }
+        }
+        // need: occ of the tile or of one of its 8 neighbours (periodic grid)
+        for (int p = 0; p < g.nwmax; ++p) {
+            const uint8_t *o = G.occ.data() + ((size_t)b * g.nwmax + p) * ntiles;
+            uint8_t *nd = G.need.data() + ((size_t)b * g.nwmax + p) * ntiles;
+            for (int tu = 0; tu < g.ntx; ++tu)
+                for (int tv = 0; tv < g.nty; ++tv) {
+                    if (!o[tu * g.nty + tv]) continue;
+                    for (int du = -1; du <= 1; ++du)
+                        for (int dv = -1; dv <= 1; ++dv)
+                            nd[((tu + du + g.ntx) % g.ntx) * g.nty + (tv + dv + g.nty) % g.nty] = 1;
+                }
         }
         std::stable_sort(gw.begin(), gw.end(), [](auto &a, auto &b) { return a.first > b.first; });
         std::stable_sort(iw.begin(), iw.end(), [](auto &a, auto &b) { return a.first > b.first; });
@@ -337,6 +361,8 @@ XformArgs xform_args(const pfb_plan *P, const GridderHost &G, int b0, int nbb) {
     a.corr2d = G.corr2d ? G.d_corr2d : nullptr;
     a.corr_x = G.d_corrx;
     a.corr_y = G.d_corry;
+    a.occ = G.d_occ;
+    a.need = G.d_need;
     return a;
 }
 
@@ -785,6 +811,8 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         G->o_hoffsets = L.take(G->hoffsets.size() * sizeof(int64_t));
         G->o_hidx = L.take(std::max<int64_t>(G->n_home, 1) * sizeof(uint32_t));
         if (G->mfma) G->o_phase = L.take(std::max<int64_t>(G->n_entries, 1) * 2 * sizeof(float));
+        G->o_occ = L.take(std::max<size_t>(G->occ.size(), 1));
+        G->o_need = L.take(std::max<size_t>(G->need.size(), 1));
         if (G->corr2d) {
             G->o_corr2d = L.take((size_t)nb * G->g.nx * G->g.ny * P->rsz);
         } else {
@@ -889,6 +917,10 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
         G->d_phase = G->mfma ? P->p(G->o_phase) : nullptr;
         G->d_hidx = reinterpret_cast<uint32_t *>(P->p(G->o_hidx));
         G->d_hoffsets = reinterpret_cast<int64_t *>(P->p(G->o_hoffsets));
+        G->d_occ = reinterpret_cast<const uint8_t *>(P->p(G->o_occ));
+        G->d_need = reinterpret_cast<const uint8_t *>(P->p(G->o_need));
+        HIP_OK(hipMemcpyAsync(P->p(G->o_occ), G->occ.data(), G->occ.size(), hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(P->p(G->o_need), G->need.data(), G->need.size(), hipMemcpyHostToDevice, s));
         if (G->corr2d) {
             G->d_corr2d = P->p(G->o_corr2d);
         } else {

@@ -108,6 +108,10 @@ struct XformArgs {
     const void *image_in;  // degrid input [n_band][nx][ny]
     void *image_out;       // grid output [n_band][nx][ny]
     int zero_edge;         // PSF: zero row 0 and column 0 of the output
+    // [n_band][nwmax][ntx * nty] tile flags: the grid transform reads a tile of a
+    // plane only where occ is set (elsewhere it is zero), the degrid transform
+    // writes it only where need is set
+    const uint8_t *occ, *need;
 };
 hipError_t launch_grid_xform(bool dbl, const XformArgs &a, hipStream_t s);    // planes -> image
 hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s);  // image -> planes

@@ -1403,9 +1403,24 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformA
     const size_t plane = (size_t)bb * a.g.nwmax + j;
     const cplx<R> *src = reinterpret_cast<const cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.t1) + (plane * gx + (size_t)ug * C) * ny;
+    // tiles of these rows that hold spread values (the rest of the plane is zero
+    // and is not read); rows whose tiles are all empty transform to zero
+    const int T = a.g.T, nty = a.g.nty;
+    const uint8_t *occ = a.occ + ((size_t)(a.band0 + bb) * a.g.nwmax + j) * a.g.ntx * nty;
+    const int row0 = ug * C;
+    bool any = false;
+    for (int k = threadIdx.x; k < C * nty; k += row_threads<LOG2L>()) {
+        const int c = k / nty, tv = k - c * nty;
+        any |= occ[((row0 + c) / T) * nty + tv] != 0;
+    }
+    if (!__syncthreads_or(any)) {
+        for (int id = threadIdx.x; id < C * ny; id += row_threads<LOG2L>()) dst[id] = cplx<R>{R(0), R(0)};
+        return;
+    }
     for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, r = id - c * L;
-        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = src[(size_t)c * L + r];
+        const bool live = occ[((row0 + c) / T) * nty + r / T] != 0;
+        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = live ? src[(size_t)c * L + r] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
     lds_fft<R, true, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
@@ -1627,6 +1642,16 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformA
     const size_t plane = (size_t)bb * a.g.nwmax + j;
     const cplx<R> *src = reinterpret_cast<const cplx<R> *>(src_v) + (plane * gx + (size_t)ug * C) * ny;
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
+    // only tiles the interpolation may read are written; rows with none are skipped
+    const int T = a.g.T, nty = a.g.nty;
+    const uint8_t *need = a.need + ((size_t)(a.band0 + bb) * a.g.nwmax + j) * a.g.ntx * nty;
+    const int row0 = ug * C;
+    bool any = false;
+    for (int k = threadIdx.x; k < C * nty; k += row_threads<LOG2L>()) {
+        const int c = k / nty, tv = k - c * nty;
+        any |= need[((row0 + c) / T) * nty + tv] != 0;
+    }
+    if (!__syncthreads_or(any)) return;
     for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, r = id - c * L;
         const int iy = wrapi(r + ny / 2, L);
@@ -1636,7 +1661,7 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformA
     lds_fft<R, false, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, k = id - c * L;
-        dst[(size_t)c * L + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
+        if (need[((row0 + c) / T) * nty + k / T]) dst[(size_t)c * L + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
     }
 }
 
