@@ -73,9 +73,10 @@ def kernel_models(info, prob, M, W, csz, rsz):
     """Algorithmic bytes (HBM-bound passes) or flops (ALU-bound spread/interp)
     per launch, from the method's data structures moved once each."""
     nx, ny = prob.nx, prob.ny
-    gx, gy = info["grid_x"], info["grid_y"]
-    nw = info["n_wplanes_max"]
-    P = nx * ny
+    gx = info["grid_x"]
+    T = info["tile"]
+    nwt = info["n_wplanes_total"]          # w-planes summed over bands
+    P = prob.n_band * nx * ny
     spread_flops = M * (4.0 * W ** 3 + 60.0 * W)
     return {
         # ES spread / interpolation: W^3 complex*real multiply-adds + 3W kernel values per visibility
@@ -84,14 +85,17 @@ def kernel_models(info, prob, M, W, csz, rsz):
         # same algorithmic work, computed as FP32 matrix products on the matrix cores
         "spread_mfma_kernel": ("mfma", spread_flops),
         "interp_kernel": ("alu", spread_flops),
-        # row inverse DFT of every w-plane: read plane, write the cropped rows
-        "g1_rows_kernel": ("hbm", nw * gx * (gy + ny) * csz),
+        # row inverse DFT of every w-plane: read its occupied tiles (the rest of the
+        # plane is zero), write the cropped rows
+        "g1_rows_kernel": ("hbm", (info["occ_tiles"] * T * T + nwt * gx * ny) * csz),
         # column step A (in place on the cropped rows)
-        "colA_kernel": ("hbm", nw * gx * ny * 2 * csz),
+        "colA_kernel": ("hbm", nwt * gx * ny * 2 * csz),
         # column step B + w-phase + accumulation over planes + correction
-        "g3_kernel": ("hbm", nw * gx * ny * csz + 2 * P * rsz),
-        "d2_kernel": ("hbm", nw * gx * ny * 2 * csz),
-        "d3_rows_kernel": ("hbm", nw * gx * (ny + gy) * csz),
+        "g3_kernel": ("hbm", nwt * gx * ny * csz + 2 * P * rsz),
+        "d2_kernel": ("hbm", nwt * gx * ny * 2 * csz),
+        # forward row DFT: read the cropped rows of tile rows the interpolation
+        # reaches, write the tiles it reads
+        "d3_rows_kernel": ("hbm", (info["need_tile_rows"] * T * ny + info["need_tiles"] * T * T) * csz),
     }
 
 
@@ -358,6 +362,19 @@ def main():
         roof["traffic"] = traffic_for(name, args.workload, args.traffic_file)
     kernels = {k: {"launches_per_step": n / args.steps, "ms_per_step": round(t / args.steps, 4)}
                for k, (n, t) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    # every modelled kernel against its own bound (same event timings)
+    for k, (n, t) in prof.items():
+        if k in models and n:
+            bound, work = models[k]
+            a_ms = t / n
+            if bound == "hbm":
+                ach = work / (a_ms * 1e-3) / 1e9
+                kernels[k].update(bound="hbm", achieved_GBps=round(ach, 1),
+                                  frac=round(ach / PEAK["hbm_GBps"], 4))
+            else:
+                ach = work / (a_ms * 1e-3) / 1e12
+                peak = PEAK["fp32_matrix_TFLOPs"] if bound == "mfma" else PEAK["fp32_vector_TFLOPs"]
+                kernels[k].update(bound=bound, achieved_TFLOPs=round(ach, 3), frac=round(ach / peak, 4))
     log("kernels:", json.dumps(kernels))
 
     # plain per-band FP64 path on the same GPU (Hessian applications/s)

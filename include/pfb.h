@@ -127,6 +127,13 @@ typedef struct {
     double  s_min;                 /* min over pixels of n - 1                              */
     double  es_beta;               /* ES kernel shape parameter                             */
     int64_t workspace_bytes;
+    /* occupancy of the operator's (band, w-plane, uv tile) cells, summed over bands
+       and their own planes: the spread writes occ_tiles of them (the rest is zero
+       and is not read by the grid transform), the degrid transform writes the
+       need_tiles the interpolation may read; *_tile_rows count the (band, plane,
+       tile row) triples with at least one such tile                           */
+    int64_t n_wplanes_total;       /* sum over bands of their w-planes                      */
+    int64_t occ_tiles, occ_tile_rows, need_tiles, need_tile_rows;
 } pfb_plan_info;
 
 /* Creates a plan: validates the problem, analyses uvw (copied to the host),

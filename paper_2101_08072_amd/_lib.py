@@ -43,7 +43,10 @@ class PfbPlanInfo(ctypes.Structure):
                 ("n_wplanes_max", ctypes.c_int32), ("band_batch", ctypes.c_int32),
                 ("n_vis_active", ctypes.c_int64), ("n_entries", ctypes.c_int64),
                 ("n_psf_entries", ctypes.c_int64), ("s_min", ctypes.c_double),
-                ("es_beta", ctypes.c_double), ("workspace_bytes", ctypes.c_int64)]
+                ("es_beta", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
+                ("n_wplanes_total", ctypes.c_int64), ("occ_tiles", ctypes.c_int64),
+                ("occ_tile_rows", ctypes.c_int64), ("need_tiles", ctypes.c_int64),
+                ("need_tile_rows", ctypes.c_int64)]
 
 
 _lib = None

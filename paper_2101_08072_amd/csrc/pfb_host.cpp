@@ -879,6 +879,26 @@ pfb_status pfb_plan_get_info(const pfb_plan *P, pfb_plan_info *info) {
     info->s_min = P->s_min;
     info->es_beta = P->main.g.beta;
     info->workspace_bytes = (int64_t)P->ws_bytes;
+    const GridderHost &G = P->main;
+    const int ntiles = G.g.ntx * G.g.nty;
+    for (int b = 0; b < G.g.n_band; ++b) {
+        const int nw = G.g.flat ? 1 : G.bands[b].nw;
+        info->n_wplanes_total += nw;
+        for (int p = 0; p < nw; ++p) {
+            const size_t base = ((size_t)b * G.g.nwmax + p) * ntiles;
+            for (int tu = 0; tu < G.g.ntx; ++tu) {
+                int no = 0, nn = 0;
+                for (int tv = 0; tv < G.g.nty; ++tv) {
+                    no += G.occ[base + (size_t)tu * G.g.nty + tv];
+                    nn += G.need[base + (size_t)tu * G.g.nty + tv];
+                }
+                info->occ_tiles += no;
+                info->need_tiles += nn;
+                info->occ_tile_rows += no > 0;
+                info->need_tile_rows += nn > 0;
+            }
+        }
+    }
     return PFB_OK;
 }
 
