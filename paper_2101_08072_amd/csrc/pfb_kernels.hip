@@ -1131,9 +1131,10 @@ hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s) {
 // Lane exchange inside groups of 8 lanes (FP32 interpolation) with DPP instead
 // of the LDS crossbar, which the tap reads keep busy; all 8 lanes of a group must
 // be active.  Value of lane I of the group: row_newbcast of lane I (lanes 0-7 of
-// the 16-lane row, banks 0-1) and of lane 8 + I (lanes 8-15, banks 2-3).
+// the 16-lane row, banks 0-1; lanes 8-15 left undefined) and of lane 8 + I
+// (lanes 8-15, banks 2-3).
 template <int I> __device__ __forceinline__ float grp8_bcast(float v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + I, 0xf, 0x3, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + I, 0xf, 0x3, false);
     return __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x158 + I, 0xf, 0xc, false));
 }
 template <int N, int I = 0> __device__ __forceinline__ void grp8_bcast_all(float v, float *out) {
@@ -1197,12 +1198,15 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
     for (int q = wk.q0; q <= wk.q1; ++q) {
         const int64_t lo = max((int64_t)wk.e0, a.hoffsets[keybase + q]);
         const int64_t hi = min((int64_t)wk.e1, a.hoffsets[keybase + q + 1]);
-        const int64_t n = max(hi - lo, (int64_t)0), per = (n + NGRP - 1) / NGRP;
-        const int64_t e_end = lo + min(n, (grp + 1) * per);
+        // group grp takes entries lo + grp, lo + grp + NGRP, ...: the 8 groups of a
+        // wave read neighbouring footprints (same window), so their LDS reads share
+        // banks and addresses instead of colliding
+        const int64_t n = max(hi - lo, (int64_t)0);
+        const int64_t e_end = lo + n;
         // FP32: the entry index (home list) and record of the next visibility are
         // loaded while the current one is interpolated (FP64 has no registers to spare)
         constexpr bool kPrefetch = sizeof(R) == 4;
-        int64_t h = lo + min(n, grp * per);
+        int64_t h = lo + grp;
         int64_t e_n = 0, e_nn = 0;
         Rec<R> rec_n{R(0), R(0), R(0), 0u};
         if constexpr (kPrefetch) {
@@ -1210,17 +1214,17 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
                 e_n = a.hidx[h];
                 rec_n = recs[e_n];
             }
-            if (h + 1 < e_end) e_nn = a.hidx[h + 1];
+            if (h + NGRP < e_end) e_nn = a.hidx[h + NGRP];
         }
-        for (; h < e_end; ++h) {
+        for (; h < e_end; h += NGRP) {
             int64_t e;                        // entry listed under its own tile
             Rec<R> rec;
             if constexpr (kPrefetch) {
                 e = e_n;
                 rec = rec_n;
                 e_n = e_nn;
-                if (h + 1 < e_end) rec_n = recs[e_n];
-                e_nn = h + 2 < e_end ? (int64_t)a.hidx[h + 2] : 0;
+                if (h + NGRP < e_end) rec_n = recs[e_n];
+                e_nn = h + 2 * NGRP < e_end ? (int64_t)a.hidx[h + 2 * NGRP] : 0;
             } else {
                 e = a.hidx[h];
                 rec = recs[e];
