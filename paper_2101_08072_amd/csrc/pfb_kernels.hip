@@ -747,7 +747,8 @@ __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a
 // slot s evaluate the 1-D ES weights of visibility s of the group relative to
 // its window: lanes r < 8 the row weight U[r], lanes r >= 8 the plane weight
 // P[r - 8], all 16 the column weight V[r]; DPP within the 16-lane row gives
-// every lane U[r mod 8] and the plane weights of the tiles.
+// every lane U[r mod 8] and the plane weights of the tiles.  Slots outside the
+// window of an MFMA round get a zero B row.
 constexpr int kMfmaRunMax = 124;                // visibilities per flush: 124 * 2^24 < 2^31
 constexpr float kMfmaScale = 16777216.0f;       // 2^24
 constexpr int kMfmaThreads = 1024;              // 16 waves (at most 128 registers per lane)
@@ -763,14 +764,17 @@ void mfma_window(int W, int *rb, int *cb) {
 }
 typedef float mfma_v4f __attribute__((ext_vector_type(4)));
 
-// value of lane N of this lane's 16-lane row (DPP row broadcast); every lane
-// of the row must be active
-template <int N> __device__ __forceinline__ float row_bcast(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + N, 0xf, 0xf, false));
+// DPP within 16-lane rows, bank masks selecting half-rows (banks 0-1 = lanes
+// 0-7, banks 2-3 = lanes 8-15); every lane of the row must be active.
+// Lanes 8-15 of each 16-lane row take the value of lane r - 8 (row_ror 8 into
+// banks 2-3), lanes 0-7 keep their own
+__device__ __forceinline__ float row_lo_to_hi(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x128, 0xf, 0xc, false));
 }
-// value of lane (r + 8) mod 16 of this lane's row (DPP row rotate by 8)
-__device__ __forceinline__ float row_ror8(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, false));
+// lanes 0-7 of each row take lane A of the row, lanes 8-15 lane B
+template <int A, int B> __device__ __forceinline__ float row_half_bcast(float v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + A, 0xf, 0x3, false);
+    return __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x150 + B, 0xf, 0xc, false));
 }
 
 template <int W, int VMODE>
@@ -922,19 +926,16 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                 for (int g4 = 0; g4 < nbatch; g4 += 4) {
                     const int nb = min(4, nbatch - g4);
                     const bool hi = r >= 8;               // rows 8..15 of a tile: its second plane
-                    const R_ E = (hi && r - 8 >= W) ? R_(0)
-                                                    : es_kernel_fast(hi ? dq + R_(r - 8) : du + R_(r), beta2, inv_hw);
+                    // plane weights k = r - 8 >= W fall outside the support (zero) and
+                    // their planes are never flushed
+                    const R_ E = es_kernel_fast(hi ? dq + R_(r - 8) : du + R_(r), beta2, inv_hw);
                     const R_ V = es_kernel_fast(dv + R_(r), beta2, inv_hw);
-                    const R_ Er = row_ror8(E);
-                    const R_ U = hi ? Er : E;             // U[r mod 8]
-                    const R_ p0 = row_bcast<8>(E), p1 = row_bcast<9>(E), p2 = row_bcast<10>(E),
-                             p3 = row_bcast<11>(E), p4 = row_bcast<12>(E), p5 = row_bcast<13>(E),
-                             p6 = row_bcast<14>(E), p7 = row_bcast<15>(E);
-                    R_ At[NT];
-                    At[0] = U * (hi ? p1 : p0);
-                    if constexpr (NT > 1) At[1] = U * (hi ? p3 : p2);
-                    if constexpr (NT > 2) At[2] = U * (hi ? p5 : p4);
-                    if constexpr (NT > 3) At[3] = U * (hi ? p7 : p6);
+                    const R_ U = row_lo_to_hi(E);         // U[r mod 8]
+                    R_ At[NT];                            // U x plane weight (2t, 2t + 1 for rows 8-15)
+                    At[0] = U * row_half_bcast<8, 9>(E);
+                    if constexpr (NT > 1) At[1] = U * row_half_bcast<10, 11>(E);
+                    if constexpr (NT > 2) At[2] = U * row_half_bcast<12, 13>(E);
+                    if constexpr (NT > 3) At[3] = U * row_half_bcast<14, 15>(E);
                     const R_ Bre = V * zr, Bim = V * zi;
                     // windows present in this group (wave-uniform); usually one
                     int keys[4];
@@ -968,12 +969,13 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                             run = 0;
                         }
                         run += cnt;
+                        // slots of other windows contribute nothing: zero their B rows
                         const bool mine = (sel >> sg) & 1u;
+                        const R_ bre = mine ? Bre : R_(0), bim = mine ? Bim : R_(0);
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
-                            const R_ at = mine ? At[t] : R_(0);
-                            cre[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, Bre, cre[t], 0, 0, 0);
-                            cim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, Bim, cim[t], 0, 0, 0);
+                            cre[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(At[t], bre, cre[t], 0, 0, 0);
+                            cim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(At[t], bim, cim[t], 0, 0, 0);
                         }
                         rem &= ~sel;
                     }
