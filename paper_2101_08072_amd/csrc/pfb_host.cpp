@@ -173,13 +173,15 @@ struct GridderHost {
     // per (band, plane, tile): occ = the spread puts non-zero values there; need = the
     // interpolation may read it (occ dilated by one tile, the halo reach)
     std::vector<uint8_t> occ, need;
+    std::vector<uint8_t> occ_row, need_row;   // per (band, plane, tile row): any such tile
+    bool row_skip = false;   // column passes skip empty rows (worth it when many rows are empty)
     bool mfma = false;                   // FP32 w-stacked: matrix-core spread (window sort, phase table)
     int sort_rb = 1, sort_cb = 1;        // sort blocks of base rows x columns
     int64_t n_entries = 0;
     size_t o_sortitems = 0;
     // workspace offsets
     size_t o_bands = 0, o_offsets = 0, o_cursor = 0, o_gwork = 0, o_iwork = 0, o_recs = 0, o_omega = 0;
-    size_t o_corr2d = 0, o_corrx = 0, o_corry = 0, o_occ = 0, o_need = 0;
+    size_t o_corr2d = 0, o_corrx = 0, o_corry = 0, o_occ = 0, o_need = 0, o_occ_row = 0, o_need_row = 0;
     bool corr2d = true;
     // device pointers (valid after set_workspace)
     BandDev *d_bands = nullptr;
@@ -193,7 +195,7 @@ struct GridderHost {
     size_t o_hidx = 0, o_hoffsets = 0;
     uint32_t *d_hidx = nullptr;
     int64_t *d_hoffsets = nullptr;
-    const uint8_t *d_occ = nullptr, *d_need = nullptr;
+    const uint8_t *d_occ = nullptr, *d_need = nullptr, *d_occ_row = nullptr, *d_need_row = nullptr;
     int64_t keys() const { return (int64_t)g.n_band * g.ntx * g.nty * g.nj0max; }
 };
 
@@ -265,6 +267,8 @@ void build_work(GridderHost &G, const std::vector<unsigned> &counts, const std::
     const size_t nflag = (size_t)g.n_band * g.nwmax * ntiles;
     G.occ.assign(nflag, 0);
     G.need.assign(nflag, 0);
+    G.occ_row.assign((size_t)g.n_band * g.nwmax * g.ntx, 0);
+    G.need_row.assign((size_t)g.n_band * g.nwmax * g.ntx, 0);
     for (int b = 0; b < g.n_band; ++b) {
         const BandDev &bd = G.bands[b];
         gw.clear();
@@ -322,8 +326,23 @@ void build_work(GridderHost &G, const std::vector<unsigned> &counts, const std::
                         for (int dv = -1; dv <= 1; ++dv)
                             nd[((tu + du + g.ntx) % g.ntx) * g.nty + (tv + dv + g.nty) % g.nty] = 1;
                 }
+            uint8_t *orow = G.occ_row.data() + ((size_t)b * g.nwmax + p) * g.ntx;
+            uint8_t *nrow = G.need_row.data() + ((size_t)b * g.nwmax + p) * g.ntx;
+            for (int tu = 0; tu < g.ntx; ++tu)
+                for (int tv = 0; tv < g.nty; ++tv) {
+                    orow[tu] |= o[tu * g.nty + tv];
+                    nrow[tu] |= nd[tu * g.nty + tv];
+                }
         }
         std::stable_sort(gw.begin(), gw.end(), [](auto &a, auto &b) { return a.first > b.first; });
+        if (b == g.n_band - 1) {
+            // per-row flag tests cost the column passes about 8 %; they pay when at
+            // least half of the tile rows (over bands and planes) have no occupied
+            // tile (measured: break-even near 40 %, a 4 % shorter step at 70 %)
+            size_t empty = 0;
+            for (uint8_t f : G.occ_row) empty += f == 0;
+            G.row_skip = empty * 2 >= G.occ_row.size();
+        }
         std::stable_sort(iw.begin(), iw.end(), [](auto &a, auto &b) { return a.first > b.first; });
         for (auto &x : gw) G.gwork.push_back(x.second);
         for (auto &x : iw) G.iwork.push_back(x.second);
@@ -363,6 +382,8 @@ XformArgs xform_args(const pfb_plan *P, const GridderHost &G, int b0, int nbb) {
     a.corr_y = G.d_corry;
     a.occ = G.d_occ;
     a.need = G.d_need;
+    a.occ_row = G.row_skip ? G.d_occ_row : nullptr;
+    a.need_row = G.row_skip ? G.d_need_row : nullptr;
     return a;
 }
 
@@ -813,6 +834,8 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         if (G->mfma) G->o_phase = L.take(std::max<int64_t>(G->n_entries, 1) * 2 * sizeof(float));
         G->o_occ = L.take(std::max<size_t>(G->occ.size(), 1));
         G->o_need = L.take(std::max<size_t>(G->need.size(), 1));
+        G->o_occ_row = L.take(std::max<size_t>(G->occ_row.size(), 1));
+        G->o_need_row = L.take(std::max<size_t>(G->need_row.size(), 1));
         if (G->corr2d) {
             G->o_corr2d = L.take((size_t)nb * G->g.nx * G->g.ny * P->rsz);
         } else {
@@ -941,6 +964,11 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
         G->d_need = reinterpret_cast<const uint8_t *>(P->p(G->o_need));
         HIP_OK(hipMemcpyAsync(P->p(G->o_occ), G->occ.data(), G->occ.size(), hipMemcpyHostToDevice, s));
         HIP_OK(hipMemcpyAsync(P->p(G->o_need), G->need.data(), G->need.size(), hipMemcpyHostToDevice, s));
+        G->d_occ_row = reinterpret_cast<const uint8_t *>(P->p(G->o_occ_row));
+        G->d_need_row = reinterpret_cast<const uint8_t *>(P->p(G->o_need_row));
+        HIP_OK(hipMemcpyAsync(P->p(G->o_occ_row), G->occ_row.data(), G->occ_row.size(), hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(P->p(G->o_need_row), G->need_row.data(), G->need_row.size(), hipMemcpyHostToDevice,
+                              s));
         if (G->corr2d) {
             G->d_corr2d = P->p(G->o_corr2d);
         } else {

@@ -112,6 +112,12 @@ struct XformArgs {
     // plane only where occ is set (elsewhere it is zero), the degrid transform
     // writes it only where need is set
     const uint8_t *occ, *need;
+    // [n_band][nwmax][ntx]: some tile of that tile row is occ / need, or null.
+    // When set, cropped rows of tile rows without occupied tiles are not written
+    // by the inverse row pass and are read as zero by the first column pass, and
+    // rows of tile rows without needed tiles are not written by the last column
+    // pass of the degrid
+    const uint8_t *occ_row, *need_row;
 };
 hipError_t launch_grid_xform(bool dbl, const XformArgs &a, hipStream_t s);    // planes -> image
 hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s);  // image -> planes

@@ -1411,21 +1411,24 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformA
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.t1) + (plane * gx + (size_t)ug * C) * ny;
     // tiles of these rows that hold spread values (the rest of the plane is zero
     // and is not read); rows whose tiles are all empty transform to zero
-    const int T = a.g.T, nty = a.g.nty;
+    const int lgT = __builtin_ctz(a.g.T), nty = a.g.nty;   // tiles are powers of two
     const uint8_t *occ = a.occ + ((size_t)(a.band0 + bb) * a.g.nwmax + j) * a.g.ntx * nty;
     const int row0 = ug * C;
     bool any = false;
     for (int k = threadIdx.x; k < C * nty; k += row_threads<LOG2L>()) {
         const int c = k / nty, tv = k - c * nty;
-        any |= occ[((row0 + c) / T) * nty + tv] != 0;
+        any |= occ[((row0 + c) >> lgT) * nty + tv] != 0;
     }
     if (!__syncthreads_or(any)) {
-        for (int id = threadIdx.x; id < C * ny; id += row_threads<LOG2L>()) dst[id] = cplx<R>{R(0), R(0)};
+        // rows without occupied tiles transform to zero; with row flags the column
+        // pass reads them as zero, else they are written
+        if (!a.occ_row)
+            for (int id = threadIdx.x; id < C * ny; id += row_threads<LOG2L>()) dst[id] = cplx<R>{R(0), R(0)};
         return;
     }
     for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, r = id - c * L;
-        const bool live = occ[((row0 + c) / T) * nty + r / T] != 0;
+        const bool live = occ[((row0 + c) >> lgT) * nty + (r >> lgT)] != 0;
         buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = live ? src[(size_t)c * L + r] : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
@@ -1472,6 +1475,10 @@ __global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
     cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1) + plane * gx * ny;
     const int col0 = cg * C;
     const R wj = (R)(bd.w0 + j * bd.dw), sc = (R)bd.sc;
+    const int lgT = __builtin_ctz(a.g.T);
+    // row flags (null: rows are dense, every row is read and written)
+    const uint8_t *occ_row = a.occ_row ? a.occ_row + ((size_t)b * a.g.nwmax + j) * a.g.ntx : nullptr;
+    const uint8_t *need_row = a.need_row ? a.need_row + ((size_t)b * a.g.nwmax + j) * a.g.ntx : nullptr;
     for (int id = threadIdx.x; id < C * N1; id += kThreads) {
         const int c = id % C, r1 = id / C;
         const int col = col0 + c;
@@ -1479,7 +1486,7 @@ __global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
         cplx<R> v{R(0), R(0)};
         if (col < ny) {
             if (MODE == 0) {
-                v = t1[(size_t)r * ny + col];
+                if (!occ_row || occ_row[r >> lgT]) v = t1[(size_t)r * ny + col];
             } else {
                 const int i = wrapi(r + nx / 2, gx);
                 if (i < nx) {
@@ -1505,6 +1512,8 @@ __global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
         const int c = id % C, k1 = id / C;
         const int col = col0 + c;
         if (col >= ny) continue;
+        // single-pass degrid: rows the forward row pass skips are not written
+        if (MODE == 1 && n2 == 1 && need_row && !need_row[k1 >> lgT]) continue;
         cplx<R> v = buf[c * ld + Lds<R, LOG2N1>::pad(k1)];
         if (n2 > 1) v = v * twiddle<R, INV>(tt, ((r2 * k1) & nmask) << shift_n);
         t1[(size_t)(k1 * n2 + r2) * ny + col] = v;
@@ -1550,11 +1559,17 @@ __global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
     }
     for (int j = 0; j < nw; ++j) {
         const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1) + ((size_t)bb * a.g.nwmax + j) * gx * ny;
+        // single pass (n1 == 1): t1 holds the inverse row pass's output, whose
+        // rows of tile rows without occupied tiles are zero and not written
+        const uint8_t *occ_row =
+            n1 == 1 && a.occ_row ? a.occ_row + ((size_t)b * a.g.nwmax + j) * a.g.ntx : nullptr;
         for (int id = threadIdx.x; id < C * N2; id += kThreads) {
             const int c = id % C, r2 = id / C;
             const int col = col0 + c;
+            const int row = k1 * N2 + r2;
             buf[c * ld + Lds<R, LOG2N2>::pad(dit_pos<LOG2N2>(r2))] =
-                col < ny ? t1[(size_t)(k1 * N2 + r2) * ny + col] : cplx<R>{R(0), R(0)};
+                col < ny && (!occ_row || occ_row[row >> __builtin_ctz(a.g.T)]) ? t1[(size_t)row * ny + col]
+                                                                                : cplx<R>{R(0), R(0)};
         }
         __syncthreads();
         lds_fft<R, true, LOG2N2>(buf, C, ld, tt, a.log2_lmax - LOG2N2);
@@ -1612,6 +1627,10 @@ __global__ __launch_bounds__(kThreads) void d2_kernel(XformArgs a) {
     const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1) + plane * gx * ny;
     cplx<R> *t2 = reinterpret_cast<cplx<R> *>(a.t2) + plane * gx * ny;
     const int col0 = cg * C;
+    const int lgT = __builtin_ctz(a.g.T);
+    // rows the forward row pass skips are not written (null: all rows)
+    const uint8_t *need_row =
+        a.need_row ? a.need_row + ((size_t)(a.band0 + bb) * a.g.nwmax + j) * a.g.ntx : nullptr;
     for (int id = threadIdx.x; id < C * N2; id += kThreads) {
         const int c = id % C, r2 = id / C;
         const int col = col0 + c;
@@ -1623,7 +1642,8 @@ __global__ __launch_bounds__(kThreads) void d2_kernel(XformArgs a) {
     for (int id = threadIdx.x; id < C * N2; id += kThreads) {
         const int c = id % C, k2 = id / C;
         const int col = col0 + c;
-        if (col < ny) t2[(size_t)(k1 + n1 * k2) * ny + col] = buf[c * ld + Lds<R, LOG2N2>::pad(k2)];
+        const int row = k1 + n1 * k2;
+        if (col < ny && (!need_row || need_row[row >> lgT])) t2[(size_t)row * ny + col] = buf[c * ld + Lds<R, LOG2N2>::pad(k2)];
     }
 }
 
@@ -1649,13 +1669,13 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformA
     const cplx<R> *src = reinterpret_cast<const cplx<R> *>(src_v) + (plane * gx + (size_t)ug * C) * ny;
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
     // only tiles the interpolation may read are written; rows with none are skipped
-    const int T = a.g.T, nty = a.g.nty;
+    const int lgT = __builtin_ctz(a.g.T), nty = a.g.nty;   // tiles are powers of two
     const uint8_t *need = a.need + ((size_t)(a.band0 + bb) * a.g.nwmax + j) * a.g.ntx * nty;
     const int row0 = ug * C;
     bool any = false;
     for (int k = threadIdx.x; k < C * nty; k += row_threads<LOG2L>()) {
         const int c = k / nty, tv = k - c * nty;
-        any |= need[((row0 + c) / T) * nty + tv] != 0;
+        any |= need[((row0 + c) >> lgT) * nty + tv] != 0;
     }
     if (!__syncthreads_or(any)) return;
     for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
@@ -1667,7 +1687,7 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformA
     lds_fft<R, false, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, k = id - c * L;
-        if (need[((row0 + c) / T) * nty + k / T]) dst[(size_t)c * L + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
+        if (need[((row0 + c) >> lgT) * nty + (k >> lgT)]) dst[(size_t)c * L + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
     }
 }
 

@@ -256,6 +256,43 @@ def test_single_visibility(prec):
     assert rel(host(plan.degrid(to_dev(x, R))), oracle.degrid(prob, x)) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", PRECISIONS)
+@pytest.mark.parametrize("nx", [64, 512])
+def test_sparse_tiles_at_corners_and_wrap(prec, nx):
+    """Visibilities clustered on a tile corner and across the periodic edge, with
+    w spread over several planes: most tiles and tile rows are empty (no spread
+    items; the row transforms read them as zero or skip them; the column passes
+    skip empty rows) while footprints straddle tiles next to empty ones and the
+    interpolation halo wraps.  nx = 512 gives 1024-row columns (two-pass)."""
+    R, C = _dtypes(prec)
+    ny = 64
+    prob = synth.tiny_problem(seed=97, nx=nx, ny=ny, n_row=240, freqs=(1.3e9,), cell_arcsec=20.0)
+    rng = np.random.default_rng(98)
+    gx, gy = 2 * nx, 2 * ny
+    # grid coordinates (cells): half the rows near the corner (32, 96), half
+    # near (0, gy - 1), i.e. across the wrap of both axes
+    tu = np.where(np.arange(prob.n_row) < prob.n_row // 2, 32.0, 0.5) + rng.normal(0, 2.0, prob.n_row)
+    tv = np.where(np.arange(prob.n_row) < prob.n_row // 2, 96.0, gy - 0.5) + rng.normal(0, 2.0, prob.n_row)
+    lam = synth.C_LIGHT / prob.freq[0]
+    u = tu / (prob.cellx * gx)
+    v = tv / (prob.celly * gy)
+    w = rng.normal(0.0, 6.0e4 * (64.0 / nx) ** 2, prob.n_row)   # a few w-planes at either size
+    prob.uvw = np.stack([u, v, w], axis=1) * lam
+    vis = rng.normal(size=(prob.n_row, 1)) + 1j * rng.normal(size=(prob.n_row, 1))
+    x = rng.normal(size=(1, nx, ny))
+    plan = make_plan(prob, prec)
+    inf = plan.info()
+    say(f"sparse tiles {prec} {nx}x{ny}: {inf['n_wplanes_max']} planes, occupied tiles "
+        f"{inf['occ_tiles']} in {inf['occ_tile_rows']} tile rows, needed {inf['need_tiles']}")
+    assert inf["n_wplanes_max"] >= 3
+    assert inf["occ_tiles"] < inf["n_wplanes_total"] * (gx // inf["tile"]) * (gy // inf["tile"])
+    if nx == 512:   # >= half of the tile rows empty: the column passes skip rows
+        assert inf["occ_tile_rows"] * 2 <= inf["n_wplanes_total"] * (gx // inf["tile"])
+    assert rel(host(plan.degrid(to_dev(x, R))), oracle.degrid(prob, x)) < TOL[prec]
+    assert rel(host(plan.grid(to_dev(vis, C))), oracle.grid(prob, vis)) < TOL[prec]
+    assert rel(host(plan.hessian(to_dev(x, R))), oracle.hessian(prob, x)) < TOL[prec]
+
+
 def test_error_paths():
     from paper_2101_08072_amd import PfbError
     prob = synth.tiny_problem(seed=94, nx=16, ny=16, n_row=10)
