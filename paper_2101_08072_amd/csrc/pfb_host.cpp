@@ -195,6 +195,8 @@ struct GridderHost {
     size_t o_hidx = 0, o_hoffsets = 0;
     uint32_t *d_hidx = nullptr;
     int64_t *d_hoffsets = nullptr;
+    size_t o_home_pos = 0;           // main gridder: per entry, home-list position of its visibility
+    uint32_t *d_home_pos = nullptr;
     const uint8_t *d_occ = nullptr, *d_need = nullptr, *d_occ_row = nullptr, *d_need_row = nullptr;
     int64_t keys() const { return (int64_t)g.n_band * g.ntx * g.nty * g.nj0max; }
 };
@@ -431,6 +433,7 @@ SpreadLaunch spread_args(const pfb_plan *P, const GridderHost &G, int b0, int nb
     s.planes = planes;
     s.band0 = b0;
     s.vmode = vmode;
+    s.home_pos = G.d_home_pos;
     return s;
 }
 
@@ -832,6 +835,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         G->o_hoffsets = L.take(G->hoffsets.size() * sizeof(int64_t));
         G->o_hidx = L.take(std::max<int64_t>(G->n_home, 1) * sizeof(uint32_t));
         if (G->mfma) G->o_phase = L.take(std::max<int64_t>(G->n_entries, 1) * 2 * sizeof(float));
+        if (G == &M) G->o_home_pos = L.take(std::max<int64_t>(G->n_entries, 1) * sizeof(uint32_t));
         G->o_occ = L.take(std::max<size_t>(G->occ.size(), 1));
         G->o_need = L.take(std::max<size_t>(G->need.size(), 1));
         G->o_occ_row = L.take(std::max<size_t>(G->occ_row.size(), 1));
@@ -1021,6 +1025,11 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
                               sort_scratch, s));
         LAUNCH_OK(launch_home_list(d, G->d_recs, reinterpret_cast<const int64_t *>(P->p(G->o_sortitems)),
                                    (int)(G->sort_items.size() / 4), G->d_hoffsets, G->d_hidx, s));
+        if (G == &P->main) {   // Hessian values travel in home-list order; o_vals is scratch here
+            G->d_home_pos = reinterpret_cast<uint32_t *>(P->p(G->o_home_pos));
+            LAUNCH_OK(launch_home_pos(d, G->d_recs, G->d_hidx, G->n_home, G->n_entries,
+                                      reinterpret_cast<uint32_t *>(P->p(P->o_vals)), G->d_home_pos, s));
+        }
         const double *cheb = reinterpret_cast<const double *>(P->p(P->o_cheb));
         const int nch = (int)P->cheb.size();
         if (G->corr2d) {

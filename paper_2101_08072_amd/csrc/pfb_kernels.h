@@ -30,6 +30,10 @@ hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s);
 // home-entry list: items as for launch_sort (after it), hoffsets per bucket
 hipError_t launch_home_list(bool dbl, const void *recs, const int64_t *items, int n_items, const int64_t *hoffsets,
                             uint32_t *hidx, hipStream_t s);
+// home_pos[e] = home-list position of entry e's visibility (after the home list);
+// vis2h is scratch of one word per visibility
+hipError_t launch_home_pos(bool dbl, const void *recs, const uint32_t *hidx, int64_t n_home, int64_t n_entries,
+                           uint32_t *vis2h, uint32_t *home_pos, hipStream_t s);
 // Deterministic plan-time order of the entries of every bucket (pfb_sort.hip):
 // items are [start, count, band, bucket] quadruples of the non-empty buckets;
 // entries are ordered by (bucket, block of rb x cb base cells, visibility index);
@@ -53,12 +57,13 @@ struct SpreadLaunch {
     int n_work;
     const int64_t *offsets;
     const void *recs, *omega;
-    const void *vis;      // VMODE 0: caller visibilities; VMODE 2: per-visibility values
+    const void *vis;      // VMODE 0: caller visibilities; VMODE 2: values in home-list order
     void *planes;         // [band_batch][nwmax][gx][gy]
     int band0;
     int vmode;            // 0 data, 1 unit visibilities, 2 precomputed values
     const float *absmax;  // FP32 path: device scalar, max |z| over active visibilities
     const void *phase;    // FP32 w-stacked gridder: exp(2 pi i s_c w) per entry (selects the MFMA spread)
+    const uint32_t *home_pos;  // VMODE 2: per entry, the home-list position of its visibility
 };
 // Window of the MFMA spread for support W (4..8): footprints whose base cells lie
 // in a block of rb rows x cb columns share one accumulator tile.
@@ -82,7 +87,7 @@ struct InterpLaunch {
     const int64_t *offsets;
     const void *recs, *omega;
     const void *planes;
-    void *out;            // OMODE 0: visibilities; OMODE 1: per-visibility values
+    void *out;            // OMODE 0: visibilities; OMODE 1: values in home-list order
     int band0;
     int omode;
     const void *phase;    // FP32 w-stacked gridder: exp(2 pi i s_c w) per entry (else null: computed)

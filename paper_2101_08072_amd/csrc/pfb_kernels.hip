@@ -272,6 +272,33 @@ __global__ __launch_bounds__(kThreads) void home_list_kernel(const Rec<R> *recs,
         __syncthreads();
     }
 }
+// home_pos[e]: home-list position of the home entry of entry e's visibility
+// (vis2h: visibility index -> home-list position, n_vis words of scratch)
+template <typename R>
+__global__ __launch_bounds__(kThreads) void vis_home_kernel(const Rec<R> *recs, const uint32_t *hidx, int64_t n_home,
+                                                            uint32_t *vis2h) {
+    for (int64_t h = (int64_t)blockIdx.x * kThreads + threadIdx.x; h < n_home; h += (int64_t)gridDim.x * kThreads)
+        vis2h[recs[hidx[h]].idx & ~kHomeBit] = (uint32_t)h;
+}
+template <typename R>
+__global__ __launch_bounds__(kThreads) void home_pos_kernel(const Rec<R> *recs, int64_t n_entries,
+                                                            const uint32_t *vis2h, uint32_t *home_pos) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n_entries; e += (int64_t)gridDim.x * kThreads)
+        home_pos[e] = vis2h[recs[e].idx & ~kHomeBit];
+}
+hipError_t launch_home_pos(bool dbl, const void *recs, const uint32_t *hidx, int64_t n_home, int64_t n_entries,
+                           uint32_t *vis2h, uint32_t *home_pos, hipStream_t s) {
+    if (n_entries <= 0) return hipSuccess;
+    const int nb = (int)std::min<int64_t>(4096, (std::max(n_home, n_entries) + kThreads - 1) / kThreads);
+    if (dbl) {
+        if (n_home > 0) PFB_LAUNCH(vis_home_kernel<double>, nb, 0, s, (const Rec<double> *)recs, hidx, n_home, vis2h);
+        PFB_LAUNCH(home_pos_kernel<double>, nb, 0, s, (const Rec<double> *)recs, n_entries, vis2h, home_pos);
+    } else {
+        if (n_home > 0) PFB_LAUNCH(vis_home_kernel<float>, nb, 0, s, (const Rec<float> *)recs, hidx, n_home, vis2h);
+        PFB_LAUNCH(home_pos_kernel<float>, nb, 0, s, (const Rec<float> *)recs, n_entries, vis2h, home_pos);
+    }
+    return hipSuccess;
+}
 hipError_t launch_home_list(bool dbl, const void *recs, const int64_t *items, int n_items, const int64_t *hoffsets,
                             uint32_t *hidx, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
@@ -424,7 +451,7 @@ __global__ __launch_bounds__(kTileThreads) void spread_kernel(SpreadLaunch a) {
                 } else if (VMODE == 1) {
                     z = cplx<R>{omega[e], R(0)};
                 } else {
-                    z = vis[vid];
+                    z = vis[a.home_pos[e]];
                 }
                 const int i0 = (int)dev_floor(rec.fu - hw) + 1;
                 const int j0 = (int)dev_floor(rec.fv - hw) + 1;
@@ -642,7 +669,7 @@ __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a
                     } else if (VMODE == 1) {
                         v = cplx<R>{omega[eb] * fscale, R(0)};
                     } else {
-                        v = vis[r.idx & ~kHomeBit] * fscale;
+                        v = vis[a.home_pos[eb]] * fscale;
                     }
                 }
                 return v;
@@ -889,7 +916,7 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                     } else if (VMODE == 1) {
                         v = cplx<R_>{omega[eb] * fscale, R_(0)};
                     } else {
-                        v = vis[rr.idx & ~kHomeBit] * fscale;
+                        v = vis[a.home_pos[eb]] * fscale;
                     }
                 }
                 return v;
@@ -1297,7 +1324,7 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
                     reinterpret_cast<cplx<R> *>(a.out)[vid] = out;
                 } else {
                     const cplx<R> o = acc * omega[e];
-                    reinterpret_cast<cplx<R> *>(a.out)[vid] = o;
+                    reinterpret_cast<cplx<R> *>(a.out)[h] = o;   // home-list order
                     vmax2 = max(vmax2, o.re * o.re + o.im * o.im);
                 }
             }
