@@ -1811,6 +1811,10 @@ hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s) {
 //           CONV_IN_CG_P   : p = r + beta p, written back, then transformed
 //           CONV_IN_SCALED : x * scale
 //   psfhat mode (nrows = 2nx): row i of the PSF rolled by (nx, ny)
+// Two real rows share one complex transform: rows 2c and 2c + 1 of the block
+// are the real and imaginary parts of vector c, and their half spectra come
+// out as X_a[k] = (Z[k] + conj Z[L - k]) / 2, X_b[k] = (Z[k] - conj Z[L - k]) / 2i.
+// C vectors (2C rows) per block.
 template <typename R, int LOG2L, int IN>
 __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a, const R *x, R *auxp, int nrows, int C, int psf) {
     constexpr int L = 1 << LOG2L;
@@ -1820,15 +1824,13 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a,
     const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
-    const int ngrp = nrows / C;
+    const int ngrp = nrows / (2 * C);
     const int ig = blockIdx.x % ngrp;
     const int b = blockIdx.x / ngrp;
     R bscale = R(1);
     if (IN == CONV_IN_CG_P) bscale = (R)a.scal[b * 8 + S_BETA];
     if (IN == CONV_IN_SCALED) bscale = (R)a.scal[b * 8 + S_SCALE];
-    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
-        const int c = id / L, r = id - c * L;
-        const int i = ig * C + c;
+    auto load = [&](int i, int r) -> R {
         R v = R(0);
         if (psf) {
             const int si = wrapi(i + nx, 2 * nx), sj = wrapi(r + ny, 2 * ny);
@@ -1844,14 +1846,22 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a,
                 auxp[pix] = v;
             }
         }
-        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = cplx<R>{v, R(0)};
+        return v;
+    };
+    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
+        const int c = id / L, r = id - c * L;
+        const int i = ig * 2 * C + 2 * c;
+        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = cplx<R>{load(i, r), load(i + 1, r)};
     }
     __syncthreads();
     lds_fft<R, false, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
-    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * C) * a.ldh;
+    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * 2 * C) * a.ldh;
     for (int id = threadIdx.x; id < C * (ny + 1); id += row_threads<LOG2L>()) {
         const int c = id / (ny + 1), k = id - c * (ny + 1);
-        t1[(size_t)c * a.ldh + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
+        const cplx<R> z = buf[c * ld + Lds<R, LOG2L>::pad(k)];
+        const cplx<R> zc = conj(buf[c * ld + Lds<R, LOG2L>::pad((L - k) & (L - 1))]);
+        t1[(size_t)(2 * c) * a.ldh + k] = cplx<R>{(z.re + zc.re) * R(0.5), (z.im + zc.im) * R(0.5)};
+        t1[(size_t)(2 * c + 1) * a.ldh + k] = cplx<R>{(z.im - zc.im) * R(0.5), (zc.re - z.re) * R(0.5)};
     }
 }
 
@@ -2053,6 +2063,9 @@ __global__ __launch_bounds__(kThreads) void s2c_kernel(ConvArgs a) {
 
 // S3: inverse row DFT (length 2ny) of the Hermitian half spectrum, real part,
 // cropped to ny, scaled by 1 / (4 nx ny), with fused epilogues.
+// Inverse of s1's pairing: rows 2c and 2c + 1 have Hermitian half spectra X_a,
+// X_b; Z = X_a + i X_b transforms to row a in the real part and row b in the
+// imaginary part.  C vectors (2C rows) per block.
 template <typename R, int LOG2L, int OUT>
 __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a, R *y, const R *aux, R sigma, int C) {
     constexpr int L = 1 << LOG2L;
@@ -2063,23 +2076,26 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a,
     __shared__ double red[row_threads<LOG2L>() / 64];
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
-    const int ngrp = nx / C;
+    const int ngrp = nx / (2 * C);
     const int ig = blockIdx.x % ngrp;
     const int b = blockIdx.x / ngrp;
-    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * C) * a.ldh;
+    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * 2 * C) * a.ldh;
     for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
         const int c = id / L, k = id - c * L;
-        const cplx<R> v = k <= ny ? t1[(size_t)c * a.ldh + k] : conj(t1[(size_t)c * a.ldh + (L - k)]);
-        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(k))] = v;
+        const cplx<R> *ra = t1 + (size_t)(2 * c) * a.ldh, *rb = ra + a.ldh;
+        const cplx<R> xa = k <= ny ? ra[k] : conj(ra[L - k]);
+        const cplx<R> xb = k <= ny ? rb[k] : conj(rb[L - k]);
+        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(k))] = cplx<R>{xa.re - xb.im, xa.im + xb.re};
     }
     __syncthreads();
     lds_fft<R, true, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     const R scale = R(1) / (R(4) * R(nx) * R(ny));
     double part = 0.0;
-    for (int id = threadIdx.x; id < C * ny; id += row_threads<LOG2L>()) {
-        const int c = id / ny, j = id - c * ny;
-        const size_t pix = ((size_t)b * nx + ig * C + c) * ny + j;
-        R v = buf[c * ld + Lds<R, LOG2L>::pad(j)].re * scale;
+    for (int id = threadIdx.x; id < 2 * C * ny; id += row_threads<LOG2L>()) {
+        const int c2 = id / ny, j = id - c2 * ny;   // output row 2C ig + c2: vector c2 / 2, part c2 % 2
+        const size_t pix = ((size_t)b * nx + ig * 2 * C + c2) * ny + j;
+        const cplx<R> z = buf[(c2 >> 1) * ld + Lds<R, LOG2L>::pad(j)];
+        R v = ((c2 & 1) ? z.im : z.re) * scale;
         if (OUT == CONV_OUT_SUB) v -= aux[pix];
         if (OUT == CONV_OUT_CG) {
             const R pv = aux[pix];
@@ -2136,9 +2152,9 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
     const int lg = __builtin_ctz(2 * a.ny);
     hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const int C = std::min(rows_per_block<R, LG>(), a.nx);
+        const int C = std::min(rows_per_block<R, LG>(), a.nx / 2);   // vectors = row pairs
         const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-        const int nb = a.n_band * (a.nx / C);
+        const int nb = a.n_band * (a.nx / (2 * C));
         const R *xr = reinterpret_cast<const R *>(x);
         R *ap = reinterpret_cast<R *>(aux_in);
         if (in_mode == CONV_IN_X) PFB_LAUNCH_NT((s1_kernel<R, LG, CONV_IN_X>), nb, row_threads<LG>(), lds, s, a, xr, ap, a.nx, C, 0);
@@ -2151,9 +2167,9 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
     if (e != hipSuccess) return e;
     return dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const int C = std::min(rows_per_block<R, LG>(), a.nx);
+        const int C = std::min(rows_per_block<R, LG>(), a.nx / 2);   // vectors = row pairs
         const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-        const int nb = a.n_band * (a.nx / C);
+        const int nb = a.n_band * (a.nx / (2 * C));
         R *yr = reinterpret_cast<R *>(y);
         const R *ax = reinterpret_cast<const R *>(aux_out);
         const R sg = (R)sigma;
@@ -2175,7 +2191,7 @@ hipError_t launch_psf_conv(bool dbl, const ConvArgs &a, const void *x, void *aux
 }
 
 int conv_partials_per_band(bool dbl, const ConvArgs &a) {
-    // S3 writes one partial per row group; rows per group depend on the row length
+    // S3 writes one partial per block of 2C rows; C depends on the row length
     const int lg = __builtin_ctz(2 * a.ny);
     int C = 1;
     (void)dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
@@ -2183,7 +2199,7 @@ int conv_partials_per_band(bool dbl, const ConvArgs &a) {
         C = dbl ? rows_per_block<double, LG>() : rows_per_block<float, LG>();
         return hipSuccess;
     });
-    return a.nx / std::min(C, a.nx);
+    return a.nx / (2 * std::min(C, a.nx / 2));
 }
 
 template <typename R>
@@ -2191,9 +2207,9 @@ static hipError_t psfhat_t(const ConvArgs &a, const void *psf_img, hipStream_t s
     const int lg = __builtin_ctz(2 * a.ny);
     hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const int C = std::min(rows_per_block<R, LG>(), a.nx);
+        const int C = std::min(rows_per_block<R, LG>(), a.nx);          // vectors = row pairs of 2nx rows
         const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-        const int nb = a.n_band * (2 * a.nx / C);
+        const int nb = a.n_band * (a.nx / C);
         PFB_LAUNCH_NT((s1_kernel<R, LG, CONV_IN_X>), nb, row_threads<LG>(), lds, s, a, reinterpret_cast<const R *>(psf_img),
                    (R *)nullptr, 2 * a.nx, C, 1);
         return hipSuccess;
