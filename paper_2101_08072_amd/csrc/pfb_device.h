@@ -169,17 +169,20 @@ __device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, co
         const int j = bfly % m;
         const int g = bfly / m;
         const int base = g * RAD * m + j;
-        cplx<R> *vb = buf + c * ld;
+        // base = g RAD m + j (j < m) and t m (t < RAD) occupy disjoint bits, so the
+        // sum never carries and pad(base + t m) = pad(base) + pad(t m): one
+        // address per butterfly plus constant offsets once the stage is unrolled
+        cplx<R> *vb = buf + c * ld + Lds<R, LOG2L>::pad(base);
         cplx<R> v[RAD];
 #pragma unroll
-        for (int t = 0; t < RAD; ++t) v[t] = vb[Lds<R, LOG2L>::pad(base + t * m)];
+        for (int t = 0; t < RAD; ++t) v[t] = vb[Lds<R, LOG2L>::pad(t * m)];
         if (m > 1) {
 #pragma unroll
             for (int t = 1; t < RAD; ++t) v[t] = v[t] * twiddle<R, INV>(tw, t * j * estep);
         }
         dft_small<R, INV, RAD>(v);
 #pragma unroll
-        for (int t = 0; t < RAD; ++t) vb[Lds<R, LOG2L>::pad(base + t * m)] = v[t];
+        for (int t = 0; t < RAD; ++t) vb[Lds<R, LOG2L>::pad(t * m)] = v[t];
     }
 }
 
