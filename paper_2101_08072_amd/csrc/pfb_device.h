@@ -177,8 +177,23 @@ __device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, co
 #pragma unroll
         for (int t = 0; t < RAD; ++t) v[t] = vb[Lds<R, LOG2L>::pad(t * m)];
         if (m > 1) {
+            const int e = j * estep;
+            if constexpr (RAD == 8) {
+                // three table reads; w^3, w^5, w^6, w^7 as products (a few ulp)
+                const cplx<R> w1 = twiddle<R, INV>(tw, e), w2 = twiddle<R, INV>(tw, 2 * e),
+                              w4 = twiddle<R, INV>(tw, 4 * e);
+                const cplx<R> w3 = w1 * w2;
+                v[1] = v[1] * w1;
+                v[2] = v[2] * w2;
+                v[3] = v[3] * w3;
+                v[4] = v[4] * w4;
+                v[5] = v[5] * (w1 * w4);
+                v[6] = v[6] * (w2 * w4);
+                v[7] = v[7] * (w3 * w4);
+            } else {
 #pragma unroll
-            for (int t = 1; t < RAD; ++t) v[t] = v[t] * twiddle<R, INV>(tw, t * j * estep);
+                for (int t = 1; t < RAD; ++t) v[t] = v[t] * twiddle<R, INV>(tw, t * e);
+            }
         }
         dft_small<R, INV, RAD>(v);
 #pragma unroll
