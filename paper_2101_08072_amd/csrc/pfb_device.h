@@ -155,6 +155,26 @@ template <typename R, bool INV> __device__ __forceinline__ cplx<R> twiddle(const
     return INV ? conj(w) : w;
 }
 
+// v[t] *= w^(t e) for t = 1 .. RAD - 1
+template <typename R, bool INV, int RAD>
+__device__ __forceinline__ void stage_twiddles(cplx<R> *v, const TwTab<R> &tw, int e) {
+    if constexpr (RAD == 8) {
+        // three table reads; w^3, w^5, w^6, w^7 as products (a few ulp)
+        const cplx<R> w1 = twiddle<R, INV>(tw, e), w2 = twiddle<R, INV>(tw, 2 * e), w4 = twiddle<R, INV>(tw, 4 * e);
+        const cplx<R> w3 = w1 * w2;
+        v[1] = v[1] * w1;
+        v[2] = v[2] * w2;
+        v[3] = v[3] * w3;
+        v[4] = v[4] * w4;
+        v[5] = v[5] * (w1 * w4);
+        v[6] = v[6] * (w2 * w4);
+        v[7] = v[7] * (w3 * w4);
+    } else {
+#pragma unroll
+        for (int t = 1; t < RAD; ++t) v[t] = v[t] * twiddle<R, INV>(tw, t * e);
+    }
+}
+
 // One DIT stage of radix RAD at span m over C vectors stored at buf + c*ld.
 template <typename R, bool INV, int RAD, int LOG2L, int NT>
 __device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, const TwTab<R> &tw, int tw_shift) {
@@ -176,25 +196,7 @@ __device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, co
         cplx<R> v[RAD];
 #pragma unroll
         for (int t = 0; t < RAD; ++t) v[t] = vb[Lds<R, LOG2L>::pad(t * m)];
-        if (m > 1) {
-            const int e = j * estep;
-            if constexpr (RAD == 8) {
-                // three table reads; w^3, w^5, w^6, w^7 as products (a few ulp)
-                const cplx<R> w1 = twiddle<R, INV>(tw, e), w2 = twiddle<R, INV>(tw, 2 * e),
-                              w4 = twiddle<R, INV>(tw, 4 * e);
-                const cplx<R> w3 = w1 * w2;
-                v[1] = v[1] * w1;
-                v[2] = v[2] * w2;
-                v[3] = v[3] * w3;
-                v[4] = v[4] * w4;
-                v[5] = v[5] * (w1 * w4);
-                v[6] = v[6] * (w2 * w4);
-                v[7] = v[7] * (w3 * w4);
-            } else {
-#pragma unroll
-                for (int t = 1; t < RAD; ++t) v[t] = v[t] * twiddle<R, INV>(tw, t * e);
-            }
-        }
+        if (m > 1) stage_twiddles<R, INV, RAD>(v, tw, j * estep);
         dft_small<R, INV, RAD>(v);
 #pragma unroll
         for (int t = 0; t < RAD; ++t) vb[Lds<R, LOG2L>::pad(t * m)] = v[t];
@@ -220,5 +222,110 @@ __device__ __forceinline__ void lds_fft(cplx<R> *buf, int C, int ld, const TwTab
         __syncthreads();
     }
 }
+
+// base-8 digit reversal of q over D digits
+template <int D> __device__ __forceinline__ int rev8(int q) {
+    int r = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        r = (r << 3) | (q & 7);
+        q >>= 3;
+    }
+    return r;
+}
+
+// FFT of C vectors of length 2^LOG2L (2^5 .. 2^14) whose first stage reads its
+// inputs through load(c, n) (natural order n) and, with STORE_REGS, whose last
+// stage hands its outputs to store(c, k, value) (natural order k) instead of
+// writing them to LDS; without STORE_REGS the result is in LDS at
+// Lds::pad(k) after a final barrier.  The first stage (radix R0, span 1) takes
+// inputs t Q + q (Q = L / R0, t < R0): its outputs belong at DIT positions
+// rev8(q) R0 + t, which replaces the digit-reversed scatter and one LDS pass.
+template <typename R, bool INV, int LOG2L, int NT, bool STORE_REGS, class Load, class Store>
+__device__ __forceinline__ void lds_fft_io(cplx<R> *buf, int C, int ld, const TwTab<R> &tw, int tw_shift, Load load,
+                                           Store store) {
+    using P = FftPlan<LOG2L>;
+    constexpr int L = 1 << LOG2L;
+    constexpr int S = P::NSTAGE;
+    constexpr int R0 = P::radix(0);
+    constexpr int Q = L / R0;
+    static_assert(S >= 2, "at least two stages");
+    // G = 8 / R0 butterflies per thread and iteration keep eight loads in flight
+    constexpr int G = 8 / R0;
+    for (int id0 = threadIdx.x; id0 < C * Q; id0 += G * NT) {
+        cplx<R> v[G][R0];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int id = id0 + u * NT;
+            if (id < C * Q) {
+                const int c = id / Q, q = id - c * Q;
+#pragma unroll
+                for (int t = 0; t < R0; ++t) v[u][t] = load(c, t * Q + q);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int id = id0 + u * NT;
+            if (id < C * Q) {
+                const int c = id / Q, q = id - c * Q;
+                dft_small<R, INV, R0>(v[u]);
+                cplx<R> *vb = buf + c * ld + Lds<R, LOG2L>::pad(rev8<S - 1>(q) * R0);
+#pragma unroll
+                for (int t = 0; t < R0; ++t) vb[Lds<R, LOG2L>::pad(t)] = v[u][t];
+            }
+        }
+    }
+    __syncthreads();
+    int m = R0;
+    constexpr int LAST = STORE_REGS ? S - 1 : S;
+#pragma unroll
+    for (int st = 1; st < LAST; ++st) {
+        dit_stage<R, INV, 8, LOG2L, NT>(buf, C, ld, m, tw, tw_shift);
+        m *= 8;
+        __syncthreads();
+    }
+    if constexpr (STORE_REGS) {
+        // last stage: span m = L / 8; butterfly j holds outputs j + t m
+        constexpr int M = L / 8;
+        for (int id = threadIdx.x; id < C * M; id += NT) {
+            const int c = id / M, j = id - c * M;
+            const cplx<R> *vb = buf + c * ld + Lds<R, LOG2L>::pad(j);
+            cplx<R> v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = vb[Lds<R, LOG2L>::pad(t * M)];
+            stage_twiddles<R, INV, 8>(v, tw, j << tw_shift);
+            dft_small<R, INV, 8>(v);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) store(c, j + t * M, v[t]);
+        }
+    }
+}
+
+// lds_fft_io when FUSE, else the same interface over the plain sequence: every
+// input scattered to its DIT position, lds_fft, and (STORE_REGS) store of every
+// output read back from LDS.  The fused first stage measured slower where it
+// starts with radix 2 or 4 (fewer loads in flight, for most kernels).
+template <typename R, bool INV, int LOG2L, int NT, bool STORE_REGS, bool FUSE, class Load, class Store>
+__device__ __forceinline__ void row_fft(cplx<R> *buf, int C, int ld, const TwTab<R> &tw, int tw_shift, Load load,
+                                        Store store) {
+    if constexpr (FUSE) {
+        lds_fft_io<R, INV, LOG2L, NT, STORE_REGS>(buf, C, ld, tw, tw_shift, load, store);
+    } else {
+        constexpr int L = 1 << LOG2L;
+        for (int id = threadIdx.x; id < C * L; id += NT) {
+            const int c = id / L, r = id - c * L;
+            buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = load(c, r);
+        }
+        __syncthreads();
+        lds_fft<R, INV, LOG2L, NT>(buf, C, ld, tw, tw_shift);
+        if constexpr (STORE_REGS)
+            for (int id = threadIdx.x; id < C * L; id += NT) {
+                const int c = id / L, k = id - c * L;
+                store(c, k, buf[c * ld + Lds<R, LOG2L>::pad(k)]);
+            }
+    }
+}
+// the fused form for lengths whose plan starts with radix 8
+template <int LOG2L> constexpr bool fuse_first8() { return FftPlan<LOG2L>::REM == 0; }
 
 }  // namespace pfb

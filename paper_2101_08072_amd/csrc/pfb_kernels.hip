@@ -1453,18 +1453,16 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformA
             for (int id = threadIdx.x; id < C * ny; id += row_threads<LOG2L>()) dst[id] = cplx<R>{R(0), R(0)};
         return;
     }
-    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
-        const int c = id / L, r = id - c * L;
-        const bool live = occ[((row0 + c) >> lgT) * nty + (r >> lgT)] != 0;
-        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = live ? src[(size_t)c * L + r] : cplx<R>{R(0), R(0)};
-    }
-    __syncthreads();
-    lds_fft<R, true, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
-    for (int id = threadIdx.x; id < C * ny; id += row_threads<LOG2L>()) {
-        const int c = id / ny, iy = id - c * ny;
-        const int k = wrapi(iy - ny / 2, L);
-        dst[(size_t)c * ny + iy] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
-    }
+    // output k of the row DFT is cropped column iy = k + ny / 2 (mod L), kept if iy < ny
+    row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>()>(
+        buf, C, ld, tt, a.log2_lmax - LOG2L,
+        [&](int c, int r) -> cplx<R> {
+            return occ[((row0 + c) >> lgT) * nty + (r >> lgT)] ? src[(size_t)c * L + r] : cplx<R>{R(0), R(0)};
+        },
+        [&](int c, int k, const cplx<R> &v) {
+            const int iy = (k + ny / 2) & (L - 1);
+            if (iy < ny) dst[(size_t)c * ny + iy] = v;
+        });
 }
 
 // Column group width for column passes (contiguous complex values per row).
@@ -1705,17 +1703,16 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformA
         any |= need[((row0 + c) >> lgT) * nty + tv] != 0;
     }
     if (!__syncthreads_or(any)) return;
-    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
-        const int c = id / L, r = id - c * L;
-        const int iy = wrapi(r + ny / 2, L);
-        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = iy < ny ? src[(size_t)c * ny + iy] : cplx<R>{R(0), R(0)};
-    }
-    __syncthreads();
-    lds_fft<R, false, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
-    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
-        const int c = id / L, k = id - c * L;
-        if (need[((row0 + c) >> lgT) * nty + (k >> lgT)]) dst[(size_t)c * L + k] = buf[c * ld + Lds<R, LOG2L>::pad(k)];
-    }
+    // input r of the row DFT is cropped column iy = r + ny / 2 (mod L), zero if iy >= ny
+    row_fft<R, false, LOG2L, row_threads<LOG2L>(), true, true>(
+        buf, C, ld, tt, a.log2_lmax - LOG2L,
+        [&](int c, int r) -> cplx<R> {
+            const int iy = (r + ny / 2) & (L - 1);
+            return iy < ny ? src[(size_t)c * ny + iy] : cplx<R>{R(0), R(0)};
+        },
+        [&](int c, int k, const cplx<R> &v) {
+            if (need[((row0 + c) >> lgT) * nty + (k >> lgT)]) dst[(size_t)c * L + k] = v;
+        });
 }
 
 template <typename R>
@@ -1848,13 +1845,13 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a,
         }
         return v;
     };
-    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
-        const int c = id / L, r = id - c * L;
-        const int i = ig * 2 * C + 2 * c;
-        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = cplx<R>{load(i, r), load(i + 1, r)};
-    }
-    __syncthreads();
-    lds_fft<R, false, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
+    row_fft<R, false, LOG2L, row_threads<LOG2L>(), false, fuse_first8<LOG2L>()>(
+        buf, C, ld, tt, a.log2_lmax - LOG2L,
+        [&](int c, int r) -> cplx<R> {
+            const int i = ig * 2 * C + 2 * c;
+            return cplx<R>{load(i, r), load(i + 1, r)};
+        },
+        [](int, int, const cplx<R> &) {});
     cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * 2 * C) * a.ldh;
     for (int id = threadIdx.x; id < C * (ny + 1); id += row_threads<LOG2L>()) {
         const int c = id / (ny + 1), k = id - c * (ny + 1);
@@ -2080,32 +2077,33 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a,
     const int ig = blockIdx.x % ngrp;
     const int b = blockIdx.x / ngrp;
     const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * 2 * C) * a.ldh;
-    for (int id = threadIdx.x; id < C * L; id += row_threads<LOG2L>()) {
-        const int c = id / L, k = id - c * L;
-        const cplx<R> *ra = t1 + (size_t)(2 * c) * a.ldh, *rb = ra + a.ldh;
-        const cplx<R> xa = k <= ny ? ra[k] : conj(ra[L - k]);
-        const cplx<R> xb = k <= ny ? rb[k] : conj(rb[L - k]);
-        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(k))] = cplx<R>{xa.re - xb.im, xa.im + xb.re};
-    }
-    __syncthreads();
-    lds_fft<R, true, LOG2L, row_threads<LOG2L>()>(buf, C, ld, tt, a.log2_lmax - LOG2L);
     const R scale = R(1) / (R(4) * R(nx) * R(ny));
     double part = 0.0;
-    for (int id = threadIdx.x; id < 2 * C * ny; id += row_threads<LOG2L>()) {
-        const int c2 = id / ny, j = id - c2 * ny;   // output row 2C ig + c2: vector c2 / 2, part c2 % 2
-        const size_t pix = ((size_t)b * nx + ig * 2 * C + c2) * ny + j;
-        const cplx<R> z = buf[(c2 >> 1) * ld + Lds<R, LOG2L>::pad(j)];
-        R v = ((c2 & 1) ? z.im : z.re) * scale;
-        if (OUT == CONV_OUT_SUB) v -= aux[pix];
-        if (OUT == CONV_OUT_CG) {
-            const R pv = aux[pix];
-            v += sigma * pv;
-            part += (double)pv * (double)v;
-        }
-        if (OUT == CONV_OUT_NORM) part += (double)v * (double)v;
-        if (OUT == CONV_OUT_DOT) part += (double)aux[pix] * (double)v;
-        y[pix] = v;
-    }
+    row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>()>(
+        buf, C, ld, tt, a.log2_lmax - LOG2L,
+        [&](int c, int k) -> cplx<R> {
+            const cplx<R> *ra = t1 + (size_t)(2 * c) * a.ldh, *rb = ra + a.ldh;
+            const cplx<R> xa = k <= ny ? ra[k] : conj(ra[L - k]);
+            const cplx<R> xb = k <= ny ? rb[k] : conj(rb[L - k]);
+            return cplx<R>{xa.re - xb.im, xa.im + xb.re};
+        },
+        [&](int c, int j, const cplx<R> &z) {
+            if (j >= ny) return;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {   // rows 2c (real part) and 2c + 1 (imaginary part)
+                const size_t pix = ((size_t)b * nx + ig * 2 * C + 2 * c + h) * ny + j;
+                R v = (h ? z.im : z.re) * scale;
+                if (OUT == CONV_OUT_SUB) v -= aux[pix];
+                if (OUT == CONV_OUT_CG) {
+                    const R pv = aux[pix];
+                    v += sigma * pv;
+                    part += (double)pv * (double)v;
+                }
+                if (OUT == CONV_OUT_NORM) part += (double)v * (double)v;
+                if (OUT == CONV_OUT_DOT) part += (double)aux[pix] * (double)v;
+                y[pix] = v;
+            }
+        });
     if (OUT == CONV_OUT_CG || OUT == CONV_OUT_NORM || OUT == CONV_OUT_DOT) {
         const double t = block_sum<row_threads<LOG2L>()>(part, red);
         if (threadIdx.x == 0) a.partials[(size_t)b * a.max_partials + ig] = t;
