@@ -804,14 +804,16 @@ template <int A, int B> __device__ __forceinline__ float row_half_bcast(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x150 + B, 0xf, 0xc, false));
 }
 
-template <int W, int VMODE>
+// TC: the tile side as a compile-time constant (LDS offsets become immediates), or
+// 0 to take it from the launch arguments
+template <int W, int VMODE, int TC>
 __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch a) {
     using R_ = float;
     using A = unsigned long long;
     constexpr int RB = MfmaWin<W>::RB, CB = MfmaWin<W>::CB, NT = MfmaWin<W>::NT;
     constexpr int NWAVE = kMfmaThreads / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int T = a.g.T, TT = T * T, TS = run_slot_stride(T, false);
+    const int T = TC ? TC : a.g.T, TT = T * T, TS = run_slot_stride(T, false);
     A *sre = reinterpret_cast<A *>(smem_raw);
     A *sim = sre + W * TS;
     const GridWork wk = a.work[blockIdx.x];
@@ -1113,9 +1115,15 @@ static hipError_t spread_run_w(const SpreadLaunch &a, hipStream_t s) {
     const bool flat = a.g.flat;
     if (!flat && a.phase) {
         const size_t lds = 2 * (size_t)W * run_slot_stride(a.g.T, false) * sizeof(unsigned long long);
-        if (a.vmode == 0) PFB_LAUNCH_NT((spread_mfma_kernel<W, 0>), a.n_work, kMfmaThreads, lds, s, a);
-        else if (a.vmode == 1) PFB_LAUNCH_NT((spread_mfma_kernel<W, 1>), a.n_work, kMfmaThreads, lds, s, a);
-        else PFB_LAUNCH_NT((spread_mfma_kernel<W, 2>), a.n_work, kMfmaThreads, lds, s, a);
+        if (a.g.T == 32) {   // the default tile
+            if (a.vmode == 0) PFB_LAUNCH_NT((spread_mfma_kernel<W, 0, 32>), a.n_work, kMfmaThreads, lds, s, a);
+            else if (a.vmode == 1) PFB_LAUNCH_NT((spread_mfma_kernel<W, 1, 32>), a.n_work, kMfmaThreads, lds, s, a);
+            else PFB_LAUNCH_NT((spread_mfma_kernel<W, 2, 32>), a.n_work, kMfmaThreads, lds, s, a);
+        } else {
+            if (a.vmode == 0) PFB_LAUNCH_NT((spread_mfma_kernel<W, 0, 0>), a.n_work, kMfmaThreads, lds, s, a);
+            else if (a.vmode == 1) PFB_LAUNCH_NT((spread_mfma_kernel<W, 1, 0>), a.n_work, kMfmaThreads, lds, s, a);
+            else PFB_LAUNCH_NT((spread_mfma_kernel<W, 2, 0>), a.n_work, kMfmaThreads, lds, s, a);
+        }
         return hipSuccess;
     }
     const size_t lds = 2 * (size_t)(flat ? 1 : W) * run_slot_stride(a.g.T, flat) * sizeof(unsigned long long);

@@ -153,6 +153,17 @@ def test_fused_hessian_matches_grid_of_degrid(tiny, tiny_plan):
     assert rel(h, gd) < (1e-13 if prec == "fp64" else 1e-6)
 
 
+def test_fp32_tile16(tiny):
+    """FP32 path with 16-cell tiles (the kernels' runtime tile side, not the
+    specialised default of 32): dirty image, degrid and Hessian against the oracle."""
+    import torch
+    plan = make_plan(tiny["prob"], "fp32", tile=16)
+    assert plan.info()["tile"] == 16
+    assert rel(host(plan.grid(to_dev(tiny["vis"], torch.complex64))), tiny["dirty"]) < TOL["fp32"]
+    assert rel(host(plan.degrid(to_dev(tiny["xd"], torch.float32))), tiny["degrid"]) < TOL["fp32"]
+    assert rel(host(plan.hessian(to_dev(tiny["xd"], torch.float32))), tiny["hess"]) < TOL["fp32"]
+
+
 def test_independent_plans_are_bitwise_identical(tiny):
     """The plan-time entry order depends on the inputs only (radix sort on a
     total key), so two plans of one problem grid, degrid and apply the Hessian
