@@ -804,6 +804,13 @@ template <int A, int B> __device__ __forceinline__ float row_half_bcast(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x150 + B, 0xf, 0xc, false));
 }
 
+// a 64-bit value that is the same in every lane, moved to scalar registers
+__device__ __forceinline__ int64_t rfl64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // TC: the tile side as a compile-time constant (LDS offsets become immediates), or
 // 0 to take it from the launch arguments
 template <int W, int VMODE, int TC>
@@ -834,22 +841,78 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
             finv = am / kMfmaScale;
         }
     }
+    const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
+    const int qstart = max(0, wk.p0 - W + 1);
+    const int qlast = min(wk.p1, bd.nj0);        // base planes qstart .. qlast - 1 can hold entries
+    // bucket offsets of those base planes: entries of base plane q are
+    // soff[q - qstart] .. soff[q - qstart + 1] - 1
+    int64_t *soff = reinterpret_cast<int64_t *>(sim + W * TS);
     for (int k = threadIdx.x; k < 2 * W * TS; k += kMfmaThreads) sre[k] = A(0);
+    for (int k = threadIdx.x; k <= qlast - qstart; k += kMfmaThreads) soff[k] = a.offsets[keybase + qstart + k];
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sg = lane >> 4, r = lane & 15;    // K slot (visibility of a group of 4); row / column
     const R_ beta2 = (R_)(a.g.beta * 1.4426950408889634), inv_hw = R_(2) / R_(W), hw = R_(0.5) * R_(W);
-    const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
-    const int qstart = max(0, wk.p0 - W + 1);
     const size_t plane_sz = (size_t)a.g.gx * a.g.gy;
+    auto soff_at = [&](int k) { return rfl64(soff[k]); };   // same address in every lane
+
+    // The entries of a wave form one stream of batches of up to 64: its share of
+    // base plane q (1/16 of the bucket), then of the next base plane in which it
+    // has a share.  A batch is (q, e, end): entries e .. min(e + 64, end) - 1.
+    // Loads run two batches ahead across plane boundaries, so the records and
+    // visibilities of the next plane are in flight during this plane's barriers
+    // and write-out.
+    constexpr int kDone = INT_MAX;
+    auto next_batch = [&](int &bq, int64_t &be, int64_t &bend) {
+        if (bq == kDone) return;
+        be += 64;
+        if (be < bend) return;
+        for (++bq; bq < qlast; ++bq) {
+            const int64_t b0 = soff_at(bq - qstart), n = soff_at(bq - qstart + 1) - b0;
+            const int64_t per = (n + NWAVE - 1) / NWAVE;
+            be = b0 + min(n, wv * per);
+            bend = b0 + min(n, (wv + 1) * per);
+            if (be < bend) return;
+        }
+        bq = kDone;
+        be = bend = 0;
+    };
+    auto load_rec = [&](int64_t ei, int64_t bend) {
+        Rec<R_> rr{R_(0), R_(0), R_(0), 0u};
+        if (ei < bend) rr = recs[ei];
+        return rr;
+    };
+    auto load_val = [&](int64_t ei, int64_t bend, const Rec<R_> &rr) {
+        cplx<R_> v{R_(0), R_(0)};
+        if (ei < bend) {
+            if (VMODE == 0) {
+                v = vis[rr.idx & ~kHomeBit] * phase[ei] * (omega[ei] * fscale);
+            } else if (VMODE == 1) {
+                v = cplx<R_>{omega[ei] * fscale, R_(0)};
+            } else {
+                v = vis[a.home_pos[ei]] * fscale;
+            }
+        }
+        return v;
+    };
+    // batch a: records and values loaded; batch b: records loaded
+    int qa = qstart - 1, qb;
+    int64_t ea = 0, enda = 0, eb, endb;
+    next_batch(qa, ea, enda);
+    qb = qa;
+    eb = ea;
+    endb = enda;
+    next_batch(qb, eb, endb);
+    Rec<R_> rec_c = load_rec(ea + lane, enda);
+    cplx<R_> val_c = load_val(ea + lane, enda, rec_c);
+    Rec<R_> rec_n = load_rec(eb + lane, endb);
+    unsigned live = 0;    // bit k: base plane q - k has entries in this bucket (planes q - W + 1 .. q)
 
     for (int q = qstart; q < wk.p1; ++q) {
-        if (q < bd.nj0) {
-            const int64_t b0 = a.offsets[keybase + q], n = a.offsets[keybase + q + 1] - b0;
-            const int64_t per = (n + NWAVE - 1) / NWAVE;
-            const int64_t e_beg = b0 + min(n, wv * per), e_end = b0 + min(n, (wv + 1) * per);
+        const bool has = q < qlast && soff_at(q - qstart + 1) != soff_at(q - qstart);   // block-uniform
+        if (qa == q) {
             mfma_v4f cre[NT], cim[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) cre[t] = cim[t] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
@@ -900,39 +963,20 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                     cre[t] = cim[t] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
                 }
             };
-            // Entries are loaded 64 at a time, lane l holding entry e + l (records
-            // coalesced, visibility gathers issued together); the loads of the
-            // next two batches are in flight while a batch is processed in 16
-            // groups of 4.  The owner lane of an entry derives its window and
-            // offsets once; each 16-lane slot fetches them with ds_bpermute.
-            auto load_rec = [&](int64_t eb) {
-                Rec<R_> rr{R_(0), R_(0), R_(0), 0u};
-                if (eb < e_end) rr = recs[eb];
-                return rr;
-            };
-            auto load_val = [&](int64_t eb, const Rec<R_> &rr) {
-                cplx<R_> v{R_(0), R_(0)};
-                if (eb < e_end) {
-                    if (VMODE == 0) {
-                        v = vis[rr.idx & ~kHomeBit] * phase[eb] * (omega[eb] * fscale);
-                    } else if (VMODE == 1) {
-                        v = cplx<R_>{omega[eb] * fscale, R_(0)};
-                    } else {
-                        v = vis[a.home_pos[eb]] * fscale;
-                    }
-                }
-                return v;
-            };
+            // Lane l of a batch holds entry e + l (records coalesced, visibility
+            // gathers issued together); a batch is processed in 16 groups of 4.  The
+            // owner lane of an entry derives its window and offsets once; each 16-lane
+            // slot fetches them with ds_bpermute.
             auto bperm_f = [](int addr, R_ x) {
                 return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
             };
-            Rec<R_> rec_c = load_rec(e_beg + lane);
-            cplx<R_> val_c = load_val(e_beg + lane, rec_c);
-            Rec<R_> rec_n = load_rec(e_beg + 64 + lane);
-            for (int64_t e = e_beg; e < e_end; e += 64) {
-                const cplx<R_> val_n = load_val(e + 64 + lane, rec_n);
-                const Rec<R_> rec_nn = load_rec(e + 128 + lane);
-                const int nbatch = (int)min((int64_t)64, e_end - e);
+            while (qa == q) {
+                int qc = qb;
+                int64_t ec = eb, endc = endb;
+                next_batch(qc, ec, endc);
+                const cplx<R_> val_n = load_val(eb + lane, endb, rec_n);
+                const Rec<R_> rec_nn = load_rec(ec + lane, endc);
+                const int nbatch = (int)min((int64_t)64, enda - ea);
                 // owner lane: window of its entry and the offsets of the window origin
                 int okey;
                 R_ odu, odv, odq;
@@ -966,7 +1010,11 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                     if constexpr (NT > 2) At[2] = U * row_half_bcast<12, 13>(E);
                     if constexpr (NT > 3) At[3] = U * row_half_bcast<14, 15>(E);
                     const R_ Bre = V * zr, Bim = V * zi;
-                    // windows present in this group (wave-uniform); usually one
+                    // windows present in this group (wave-uniform); usually one, the
+                    // current one: every lane holds the window of its slot
+                    const int key0 = rdlane(key, 0);
+                    const bool one = nb == 4 && key0 == cur && run + 4 <= kMfmaRunMax &&
+                                     __builtin_amdgcn_ballot_w64(key == key0) == ~0ull;
                     int keys[4];
 #pragma unroll
                     for (int g = 0; g < 4; ++g) keys[g] = rdlane(key, 16 * g);
@@ -982,15 +1030,18 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                     }
                     unsigned rem = (1u << nb) - 1u;
                     while (rem) {
-                        const int f = __builtin_ctz(rem);
-                        int w = keys[0];
+                        int w = key0;
+                        unsigned sel = 0xfu;    // four entries of the current window
+                        if (!one) {
+                            const int f = __builtin_ctz(rem);
 #pragma unroll
-                        for (int g = 1; g < 4; ++g)
-                            if (f == g) w = keys[g];
-                        unsigned sel = 0;
+                            for (int g = 1; g < 4; ++g)
+                                if (f == g) w = keys[g];
+                            sel = 0;
 #pragma unroll
-                        for (int g = 0; g < 4; ++g)
-                            if (((rem >> g) & 1u) && keys[g] == w) sel |= 1u << g;
+                            for (int g = 0; g < 4; ++g)
+                                if (((rem >> g) & 1u) && keys[g] == w) sel |= 1u << g;
+                        }
                         const int cnt = __builtin_popcount(sel);
                         if (w != cur || run + cnt > kMfmaRunMax) {
                             if (cur != kNoRun) flush(cur);
@@ -1012,10 +1063,21 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                 rec_c = rec_n;
                 val_c = val_n;
                 rec_n = rec_nn;
+                qa = qb;
+                ea = eb;
+                enda = endb;
+                qb = qc;
+                eb = ec;
+                endb = endc;
             }
             if (cur != kNoRun) flush(cur);
         }
-        __syncthreads();
+        // planes without any entry of base planes q - W + 1 .. q are zero: not
+        // written (the transforms read only occupied tiles), and their LDS slot
+        // stays zero; a plane without atomics needs no barrier before its write-out
+        if (has) __syncthreads();
+        live = ((live << 1) | (has ? 1u : 0u)) & ((1u << W) - 1u);
+        if (!live) continue;
         const int slot = q % W;
         if (q >= wk.p0) {
             cplx<R_> *dst = planes + ((size_t)bb * a.g.nwmax + q) * plane_sz + (size_t)tu * T * a.g.gy + (size_t)tv * T;
@@ -1114,7 +1176,9 @@ template <int W>
 static hipError_t spread_run_w(const SpreadLaunch &a, hipStream_t s) {
     const bool flat = a.g.flat;
     if (!flat && a.phase) {
-        const size_t lds = 2 * (size_t)W * run_slot_stride(a.g.T, false) * sizeof(unsigned long long);
+        // plane ring + bucket offsets of the base planes of one work item
+        const size_t lds = 2 * (size_t)W * run_slot_stride(a.g.T, false) * sizeof(unsigned long long) +
+                           ((size_t)a.g.nj0max + 1) * sizeof(int64_t);
         if (a.g.T == 32) {   // the default tile
             if (a.vmode == 0) PFB_LAUNCH_NT((spread_mfma_kernel<W, 0, 32>), a.n_work, kMfmaThreads, lds, s, a);
             else if (a.vmode == 1) PFB_LAUNCH_NT((spread_mfma_kernel<W, 1, 32>), a.n_work, kMfmaThreads, lds, s, a);
