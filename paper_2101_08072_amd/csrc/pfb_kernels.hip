@@ -1015,9 +1015,7 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                     const int key0 = rdlane(key, 0);
                     const bool one = nb == 4 && key0 == cur && run + 4 <= kMfmaRunMax &&
                                      __builtin_amdgcn_ballot_w64(key == key0) == ~0ull;
-                    int keys[4];
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) keys[g] = rdlane(key, 16 * g);
+                    const int keyv = key;
                     {
                         // next group (after the last group of the batch: unused)
                         const int own = ((g4 + 4 + sg) & 63) * 4;
@@ -1033,6 +1031,9 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                         int w = key0;
                         unsigned sel = 0xfu;    // four entries of the current window
                         if (!one) {
+                            int keys[4];
+#pragma unroll
+                            for (int g = 0; g < 4; ++g) keys[g] = rdlane(keyv, 16 * g);
                             const int f = __builtin_ctz(rem);
 #pragma unroll
                             for (int g = 1; g < 4; ++g)
