@@ -195,6 +195,43 @@ pfb_status pfb_power_iteration(pfb_plan *plan, int op, const void *v0, int iters
 pfb_status pfb_fb_step(pfb_plan *plan, const void *dirty, void *x, double sigma, double gamma,
                        double lambda, int cg_iters, hipStream_t stream);
 
+/* ---- Backward step of the paper: eq. (7) with the regulariser of eq. (9) ----
+ * r(x) = lambda ||Psi^dagger x||_{2,1} + positivity.  Psi is the dictionary of the
+ * Dirac basis and the first nbasis - 1 Daubechies wavelet bases (db1, db2, ...;
+ * the paper uses nbasis = 7), each a periodic orthonormal 2-D transform of
+ * `levels` levels (Mallat layout), scaled by 1/sqrt(nbasis) so that
+ * Psi Psi^dagger = Id.  The l2 norm runs over the bands of one basis coefficient,
+ * the l1 sum over bases and coefficients.  Daubechies filters are computed from
+ * their defining polynomial (minimum phase, coefficients summing to sqrt 2).
+ * Coefficient arrays are DEVICE real [nbasis][n_band][nx][ny] in the plan's
+ * precision; nx and ny must be multiples of 2^levels, 1 <= nbasis <= 7,
+ * 1 <= levels <= 16.  ws is a DEVICE buffer of at least pfb_prox_workspace_size
+ * bytes owned by the caller; it holds the dual variable between calls. */
+pfb_status pfb_prox_workspace_size(const pfb_plan *plan, int nbasis, size_t *bytes);
+
+/* coeffs = Psi^dagger x.  x DEVICE real [n_band][nx][ny]. */
+pfb_status pfb_wavelet_analysis(pfb_plan *plan, const void *x, void *coeffs, void *ws, size_t ws_bytes,
+                                int nbasis, int levels, hipStream_t stream);
+
+/* x = Psi coeffs (the adjoint of pfb_wavelet_analysis and, for a tight frame, its
+ * left inverse). */
+pfb_status pfb_wavelet_synthesis(pfb_plan *plan, const void *coeffs, void *x, void *ws, size_t ws_bytes,
+                                 int nbasis, int levels, hipStream_t stream);
+
+/* x = prox^U_{gamma r}(z) of eq. (7), U = I^psf * + sigma Id, by `iters` iterations of
+ * the primal-dual algorithm of Condat (2013) named after eq. (8):
+ *   x~ = max(x - tau (U (x - z) / gamma + Psi v), 0)
+ *   v  = P_lambda(v + sigma_d Psi^dagger (2 x~ - x)),  x = x~
+ * where P_lambda scales every band vector of v onto the l2 ball of radius lambda,
+ * beta = (unorm + sigma) / gamma, sigma_d = beta, tau = 0.99 / (beta / 2 + sigma_d).
+ * unorm >= ||I^psf *|| (e.g. pfb_power_iteration with a margin).  warm = 0 starts
+ * from x = max(z, 0), v = 0; warm != 0 continues from the x passed in and the v
+ * left in ws by the previous call.  z, x DEVICE real [n_band][nx][ny], z != x;
+ * the plan's PSF spectrum must exist. */
+pfb_status pfb_prox_solve(pfb_plan *plan, const void *z, void *x, void *ws, size_t ws_bytes, int nbasis,
+                          int levels, double lambda, double gamma, double sigma, double unorm, int iters,
+                          int warm, hipStream_t stream);
+
 /* hipGraph capture of forward-backward iterations (for launch-bound loops).
  * Captures `n_steps` consecutive pfb_fb_step(plan, dirty, x, sigma, gamma, lambda,
  * cg_iters) calls into one instantiated HIP graph.  `stream` must be a

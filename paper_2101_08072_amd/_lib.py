@@ -19,7 +19,8 @@ EXPORTS = ["pfb_plan_create", "pfb_plan_workspace_size", "pfb_plan_set_workspace
            "pfb_plan_get_info", "pfb_plan_destroy", "pfb_grid", "pfb_degrid", "pfb_hessian",
            "pfb_psf_conv", "pfb_precond_solve", "pfb_power_iteration", "pfb_fb_step",
            "pfb_fb_graph_create", "pfb_graph_launch", "pfb_graph_destroy",
-           "pfb_profile_enable", "pfb_profile_report", "pfb_last_error", "pfb_version"]
+           "pfb_profile_enable", "pfb_profile_report", "pfb_last_error", "pfb_version",
+           "pfb_prox_workspace_size", "pfb_wavelet_analysis", "pfb_wavelet_synthesis", "pfb_prox_solve"]
 
 
 class PfbProblem(ctypes.Structure):
@@ -81,6 +82,10 @@ def load():
         "pfb_graph_destroy": [vp],
         "pfb_profile_enable": [vp, i32],
         "pfb_profile_report": [vp, ctypes.c_char_p, sz],
+        "pfb_prox_workspace_size": [vp, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "pfb_wavelet_analysis": [vp, vp, vp, vp, sz, i32, i32, vp],
+        "pfb_wavelet_synthesis": [vp, vp, vp, vp, sz, i32, i32, vp],
+        "pfb_prox_solve": [vp, vp, vp, vp, sz, i32, i32, f64, f64, f64, f64, i32, i32, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -1306,6 +1307,237 @@ pfb_status pfb_fb_step(pfb_plan *P, const void *dirty, void *x, double sigma, do
     const int64_t Pn = (int64_t)P->prob.nx * P->prob.ny;
     LAUNCH_OK(launch_vec(d, VEC_FB_PROX, P->prob.n_band, Pn, ca.partials, ca.max_partials, ca.scal, x, y, nullptr,
                          nullptr, nullptr, gamma, lambda, s));
+    return PFB_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// backward step (eq. 7 with the regulariser of eq. 9)
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxBases = 7;   // Dirac + db1 .. db6
+
+// Low-pass filter of the Daubechies wavelet with n vanishing moments (length 2n):
+// |m0|^2 = cos^(2n)(xi/2) P(sin^2(xi/2)), P(y) = sum_{k<n} C(n-1+k, k) y^k.  The
+// roots of P (Durand-Kerner iteration) map to z-plane pairs z + 1/z = 2 - 4y; the
+// filter polynomial (z + 1)^n prod (z - z_i) takes the root inside the unit circle
+// (minimum phase); h lists its coefficients in descending powers, scaled to sum
+// sqrt(2).
+void daubechies_filter(int n, double *h) {
+    using C = std::complex<double>;
+    const int deg = n - 1;
+    std::vector<double> a(n);
+    for (int k = 0; k < n; ++k) {
+        double c = 1.0;
+        for (int i = 1; i <= k; ++i) c = c * (double)(n - 1 + i) / (double)i;
+        a[k] = c;
+    }
+    std::vector<C> y(deg);
+    for (int i = 0; i < deg; ++i) y[i] = std::pow(C(0.4, 0.9), i);
+    auto poly_at = [&](C t) {
+        C r = a[deg];
+        for (int k = deg - 1; k >= 0; --k) r = r * t + a[k];
+        return r;
+    };
+    for (int it = 0; it < 1000 && deg > 0; ++it) {
+        double moved = 0.0;
+        for (int i = 0; i < deg; ++i) {
+            C den = a[deg];
+            for (int j = 0; j < deg; ++j)
+                if (j != i) den *= (y[i] - y[j]);
+            const C step = poly_at(y[i]) / den;
+            y[i] -= step;
+            moved = std::max(moved, std::abs(step));
+        }
+        if (moved < 1e-17) break;
+    }
+    std::vector<C> roots(n, C(-1.0, 0.0));
+    for (const C &yy : y) {
+        const C b = 1.0 - 2.0 * yy;
+        const C sq = std::sqrt(b * b - 1.0);
+        const C z1 = b + sq, z2 = b - sq;
+        roots.push_back(std::abs(z1) < 1.0 ? z1 : z2);
+    }
+    std::vector<C> poly{C(1.0, 0.0)};
+    for (const C &r : roots) {
+        std::vector<C> next(poly.size() + 1, C(0.0, 0.0));
+        for (size_t i = 0; i < poly.size(); ++i) {
+            next[i] += poly[i];
+            next[i + 1] -= r * poly[i];
+        }
+        poly.swap(next);
+    }
+    double sum = 0.0;
+    for (int i = 0; i < 2 * n; ++i) {
+        h[i] = poly[i].real();
+        sum += h[i];
+    }
+    for (int i = 0; i < 2 * n; ++i) h[i] *= std::sqrt(2.0) / sum;
+}
+
+WaveletFilter db_filter(int n) {
+    WaveletFilter f{};
+    f.len = 2 * n;
+    daubechies_filter(n, f.h);
+    return f;
+}
+
+// element offsets (in reals) of the prox workspace: v, coef, then six image buffers
+struct ProxLayout {
+    int64_t NP;          // n_band * nx * ny
+    size_t v, coef, d, c, u, sv, a, b, total;   // bytes
+};
+ProxLayout prox_layout(const pfb_plan *P, int nbasis) {
+    ProxLayout L{};
+    L.NP = (int64_t)P->prob.n_band * P->prob.nx * P->prob.ny;
+    const size_t img = (size_t)L.NP * P->rsz;
+    L.v = 0;
+    L.coef = L.v + (size_t)nbasis * img;
+    L.d = L.coef + (size_t)(nbasis - 1) * img;
+    L.c = L.d + img;
+    L.u = L.c + img;
+    L.sv = L.u + img;
+    L.a = L.sv + img;
+    L.b = L.a + img;
+    L.total = L.b + img;
+    return L;
+}
+
+pfb_status wavelet_args_ok(const pfb_plan *P, int nbasis, int levels) {
+    if (nbasis < 1 || nbasis > kMaxBases) return fail(PFB_EINVAL, "nbasis must be 1 .. %d", kMaxBases);
+    if (levels < 1 || levels > 16) return fail(PFB_EINVAL, "levels must be 1 .. 16");
+    const int m = (1 << levels) - 1;
+    if ((P->prob.nx & m) || (P->prob.ny & m))
+        return fail(PFB_EINVAL, "nx = %d and ny = %d must be multiples of 2^levels = %d", P->prob.nx, P->prob.ny,
+                    1 << levels);
+    return PFB_OK;
+}
+
+// coef_k (k >= 1) = W_k^dagger src for every band, unscaled; uses buffer a
+pfb_status analysis_bases(const pfb_plan *P, const void *src, char *coef, void *a, int nbasis, int levels,
+                          hipStream_t s) {
+    const bool d = P->dbl;
+    const int nx = P->prob.nx, ny = P->prob.ny, nb = P->prob.n_band;
+    const int64_t Pn = (int64_t)nx * ny;
+    const size_t img = (size_t)nb * Pn * P->rsz;
+    for (int k = 1; k < nbasis; ++k) {
+        const WaveletFilter f = db_filter(k);
+        void *ck = coef + (size_t)(k - 1) * img;
+        for (int l = 0; l < levels; ++l) {
+            const int bx = nx >> l, by = ny >> l;
+            LAUNCH_OK(launch_wavelet_pass(d, false, 1, false, l == 0 ? src : ck, a, f, by, bx, ny, Pn, nb, s));
+            LAUNCH_OK(launch_wavelet_pass(d, false, 0, false, a, ck, f, bx, by, ny, Pn, nb, s));
+        }
+    }
+    return PFB_OK;
+}
+
+// out = v_0 + sum_{k >= 1} W_k v_k (unscaled); uses buffers a and b
+pfb_status synthesis_bases(const pfb_plan *P, const char *v, void *out, void *a, void *b, int nbasis, int levels,
+                           hipStream_t s) {
+    const bool d = P->dbl;
+    const int nx = P->prob.nx, ny = P->prob.ny, nb = P->prob.n_band;
+    const int64_t Pn = (int64_t)nx * ny;
+    const size_t img = (size_t)nb * Pn * P->rsz;
+    LAUNCH_OK(launch_wave_copy(d, v, out, (int64_t)nb * Pn, 1.0, s));
+    for (int k = 1; k < nbasis; ++k) {
+        const WaveletFilter f = db_filter(k);
+        LAUNCH_OK(launch_wave_copy(d, v + (size_t)k * img, a, (int64_t)nb * Pn, 1.0, s));
+        for (int l = levels - 1; l >= 0; --l) {
+            const int bx = nx >> l, by = ny >> l;
+            LAUNCH_OK(launch_wavelet_pass(d, true, 0, false, a, b, f, bx, by, ny, Pn, nb, s));
+            LAUNCH_OK(launch_wavelet_pass(d, true, 1, l == 0, b, l == 0 ? out : a, f, by, bx, ny, Pn, nb, s));
+        }
+    }
+    return PFB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pfb_status pfb_prox_workspace_size(const pfb_plan *P, int nbasis, size_t *bytes) {
+    if (!P || !bytes) return fail(PFB_EINVAL, "plan and bytes must be non-NULL");
+    if (nbasis < 1 || nbasis > kMaxBases) return fail(PFB_EINVAL, "nbasis must be 1 .. %d", kMaxBases);
+    *bytes = prox_layout(P, nbasis).total;
+    return PFB_OK;
+}
+
+pfb_status pfb_wavelet_analysis(pfb_plan *P, const void *x, void *coeffs, void *ws, size_t ws_bytes, int nbasis,
+                                int levels, hipStream_t s) {
+    ProfScope prof_scope(P);
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!x || !coeffs || !ws) return fail(PFB_EINVAL, "x, coeffs and ws must be non-NULL");
+    if ((st = wavelet_args_ok(P, nbasis, levels))) return st;
+    const ProxLayout L = prox_layout(P, nbasis);
+    if (ws_bytes < L.total) return fail(PFB_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    const bool d = P->dbl;
+    const double scale = 1.0 / std::sqrt((double)nbasis);
+    char *c = reinterpret_cast<char *>(coeffs);
+    char *w = reinterpret_cast<char *>(ws);
+    const size_t img = (size_t)L.NP * P->rsz;
+    LAUNCH_OK(launch_wave_copy(d, x, c, L.NP, scale, s));
+    if ((st = analysis_bases(P, x, c + img, w + L.a, nbasis, levels, s))) return st;
+    if (nbasis > 1) LAUNCH_OK(launch_wave_copy(d, c + img, c + img, (int64_t)(nbasis - 1) * L.NP, scale, s));
+    return PFB_OK;
+}
+
+pfb_status pfb_wavelet_synthesis(pfb_plan *P, const void *coeffs, void *x, void *ws, size_t ws_bytes, int nbasis,
+                                 int levels, hipStream_t s) {
+    ProfScope prof_scope(P);
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!x || !coeffs || !ws) return fail(PFB_EINVAL, "coeffs, x and ws must be non-NULL");
+    if ((st = wavelet_args_ok(P, nbasis, levels))) return st;
+    const ProxLayout L = prox_layout(P, nbasis);
+    if (ws_bytes < L.total) return fail(PFB_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    char *w = reinterpret_cast<char *>(ws);
+    if ((st = synthesis_bases(P, reinterpret_cast<const char *>(coeffs), x, w + L.a, w + L.b, nbasis, levels, s)))
+        return st;
+    LAUNCH_OK(launch_wave_copy(P->dbl, x, x, L.NP, 1.0 / std::sqrt((double)nbasis), s));
+    return PFB_OK;
+}
+
+pfb_status pfb_prox_solve(pfb_plan *P, const void *z, void *x, void *ws, size_t ws_bytes, int nbasis, int levels,
+                          double lambda, double gamma, double sigma, double unorm, int iters, int warm,
+                          hipStream_t s) {
+    ProfScope prof_scope(P);
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!z || !x || !ws) return fail(PFB_EINVAL, "z, x and ws must be non-NULL");
+    if (z == x) return fail(PFB_EINVAL, "z and x must differ");
+    if (!P->psf_ready) return fail(PFB_ESTATE, "no PSF spectrum: call pfb_grid with PFB_GRID_PSF first");
+    if ((st = wavelet_args_ok(P, nbasis, levels))) return st;
+    if (!(lambda >= 0) || !(gamma > 0) || !(sigma >= 0) || !(unorm > 0) || !std::isfinite(lambda) ||
+        !std::isfinite(gamma) || !std::isfinite(sigma) || !std::isfinite(unorm) || iters < 0)
+        return fail(PFB_EINVAL, "need lambda >= 0, gamma > 0, sigma >= 0, unorm > 0 (finite), iters >= 0");
+    const ProxLayout L = prox_layout(P, nbasis);
+    if (ws_bytes < L.total) return fail(PFB_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    const bool d = P->dbl;
+    char *w = reinterpret_cast<char *>(ws);
+    void *v = w + L.v, *coef = w + L.coef, *dd = w + L.d, *c = w + L.c, *u = w + L.u, *sv = w + L.sv;
+    // Condat's iteration: F(x) = (x - z)^T U (x - z) / (2 gamma) with U = I^psf * + sigma Id,
+    // G = positivity, H = lambda ||.||_{2,1} of L x = Psi^dagger x (||Psi^dagger|| = 1)
+    const double beta = (unorm + sigma) / gamma;
+    const double sigma_d = beta, tau = 0.99 / (0.5 * beta + sigma_d);
+    const double psi_scale = 1.0 / std::sqrt((double)nbasis);
+    const ConvArgs ca = conv_args(P);
+    if (!warm) LAUNCH_OK(launch_pd_dual(d, true, v, nullptr, nullptr, nbasis, P->prob.n_band,
+                                         (int64_t)P->prob.nx * P->prob.ny, 0.0, 0.0, 0.0, s));
+    LAUNCH_OK(launch_pd_primal(d, true, z, x, dd, nullptr, nullptr, nullptr, L.NP, 0.0, 1.0, 0.0, 0.0, warm, s));
+    for (int it = 0; it < iters; ++it) {
+        LAUNCH_OK(launch_psf_conv(d, ca, dd, nullptr, c, nullptr, 0.0, CONV_IN_X, CONV_OUT_Y, s));
+        if ((st = synthesis_bases(P, reinterpret_cast<const char *>(v), sv, w + L.a, w + L.b, nbasis, levels, s)))
+            return st;
+        LAUNCH_OK(launch_pd_primal(d, false, z, x, dd, c, sv, u, L.NP, tau, gamma, sigma, psi_scale, warm, s));
+        if ((st = analysis_bases(P, u, reinterpret_cast<char *>(coef), w + L.a, nbasis, levels, s))) return st;
+        LAUNCH_OK(launch_pd_dual(d, false, v, u, coef, nbasis, P->prob.n_band, (int64_t)P->prob.nx * P->prob.ny,
+                                 sigma_d, psi_scale, lambda, s));
+    }
     return PFB_OK;
 }
 

@@ -183,4 +183,25 @@ hipError_t launch_reduce(int op, int n_band, const double *partials, int n_part,
                          double *scal, hipStream_t s);
 hipError_t launch_copy_scalar(int n_band, const double *scal, int slot, double *dst, hipStream_t s);
 
+
+// Backward step (eq. 7, regulariser of eq. 9).  A periodic orthonormal wavelet
+// filter: low-pass taps h[0 .. len), len <= kMaxWaveletTaps (db6 has 12).
+constexpr int kMaxWaveletTaps = 12;
+struct WaveletFilter {
+    double h[kMaxWaveletTaps];
+    int len;
+};
+// One wavelet level along `axis` (1: contiguous, 0: strided) of the top-left
+// n x other (axis 1: other x n) block of n_img images `img` elements apart, rows
+// `ld` apart; inv: synthesis (the adjoint), acc: add into dst.
+hipError_t launch_wavelet_pass(bool dbl, bool inv, int axis, bool acc, const void *src, void *dst,
+                               const WaveletFilter &f, int n, int other, int ld, int64_t img, int n_img,
+                               hipStream_t s);
+hipError_t launch_wave_copy(bool dbl, const void *src, void *dst, int64_t n, double scale, hipStream_t s);
+hipError_t launch_pd_primal(bool dbl, bool init, const void *z, void *x, void *d, const void *c, const void *sv,
+                            void *u, int64_t n, double tau, double gamma, double sigma_u, double psi_scale, int warm,
+                            hipStream_t s);
+hipError_t launch_pd_dual(bool dbl, bool zero, void *v, const void *u, const void *coef, int nbasis, int n_band,
+                          int64_t P, double sigma_d, double psi_scale, double lam, hipStream_t s);
+
 }  // namespace pfb

@@ -2433,4 +2433,207 @@ hipError_t launch_copy_scalar(int n_band, const double *scal, int slot, double *
     return hipSuccess;
 }
 
+
+// ---------------------------------------------------------------------------
+// backward step (eq. 7 with the regulariser of eq. 9): wavelet dictionary and
+// primal-dual updates
+// ---------------------------------------------------------------------------
+// One periodic wavelet level along one axis of a block of images.  The block is
+// rows x n (AXIS 1: along the contiguous axis) or n x cols (AXIS 0: along the
+// strided axis) at the top-left of every image; images are `img` elements apart,
+// rows `ld` apart.  Analysis (INV false): low[k] = sum_j h[j] x[(2k + j) mod n],
+// high[k] = sum_j g[j] x[(2k + j) mod n] with g[j] = (-1)^j h[len-1-j], stored as
+// [low | high].  Synthesis (INV true): the adjoint, x[m] = sum over taps j with
+// m - j even of h[j] low[k] + g[j] high[k], k = ((m - j) mod n) / 2; ACC adds the
+// result to dst instead of storing it.
+template <typename R, bool INV, int AXIS, bool ACC>
+__global__ __launch_bounds__(kThreads) void wavelet_pass_kernel(const R *src, R *dst, WaveletFilter f, int n,
+                                                                int other, int ld, int64_t img, int n_img) {
+    const int64_t per = (int64_t)n * other;
+    const int64_t total = per * n_img;
+    const int len = f.len;
+    const int half = n >> 1;
+    for (int64_t id = (int64_t)blockIdx.x * kThreads + threadIdx.x; id < total;
+         id += (int64_t)gridDim.x * kThreads) {
+        const int64_t im = id / per;
+        const int64_t rem = id - im * per;
+        // AXIS 1: consecutive threads along the axis; AXIS 0: along the other (contiguous) axis
+        int o, m;
+        if (AXIS == 1) {
+            o = (int)(rem / n);
+            m = (int)(rem - (int64_t)o * n);
+        } else {
+            m = (int)(rem / other);
+            o = (int)(rem - (int64_t)m * other);
+        }
+        const R *sp = src + im * img;
+        auto at = [&](int i) -> R { return AXIS == 1 ? sp[(size_t)o * ld + i] : sp[(size_t)i * ld + o]; };
+        R acc = R(0);
+        if (!INV) {
+            // output m: low (m < half) or high (m >= half) coefficient k
+            const bool hi = m >= half;
+            const int k = hi ? m - half : m;
+            for (int j = 0; j < len; ++j) {
+                const R w = hi ? ((j & 1) ? -f.h[len - 1 - j] : f.h[len - 1 - j]) : f.h[j];
+                int i = 2 * k + j;
+                i -= (i / n) * n;
+                acc += (R)w * at(i);
+            }
+        } else {
+            for (int j = (m & 1); j < len; j += 2) {    // taps with m - j even
+                int t = m - j;
+                t %= n;
+                if (t < 0) t += n;
+                const int k = t >> 1;
+                const R hw = (R)f.h[j];
+                const R gw = (R)((j & 1) ? -f.h[len - 1 - j] : f.h[len - 1 - j]);
+                acc += hw * at(k) + gw * at(half + k);
+            }
+        }
+        R *dp = dst + im * img + (AXIS == 1 ? (size_t)o * ld + m : (size_t)m * ld + o);
+        if (ACC) *dp += acc;
+        else *dp = acc;
+    }
+}
+
+static int64_t wave_blocks(int64_t total) {
+    int64_t nb = (total + kThreads - 1) / kThreads;
+    return nb < 1 ? 1 : (nb > 65536 ? 65536 : nb);
+}
+
+template <typename R>
+static hipError_t wavelet_pass_t(bool inv, int axis, bool acc, const void *src, void *dst, const WaveletFilter &f,
+                                 int n, int other, int ld, int64_t img, int n_img, hipStream_t s) {
+    const int64_t nb = wave_blocks((int64_t)n * other * n_img);
+    const R *sp = reinterpret_cast<const R *>(src);
+    R *dp = reinterpret_cast<R *>(dst);
+#define WPASS(I, X, C)                                                                        \
+    if (inv == I && axis == X && acc == C) {                                                  \
+        PFB_LAUNCH((wavelet_pass_kernel<R, I, X, C>), nb, 0, s, sp, dp, f, n, other, ld, img, n_img); \
+        return hipSuccess;                                                                    \
+    }
+    WPASS(false, 1, false)
+    WPASS(false, 0, false)
+    WPASS(true, 0, false)
+    WPASS(true, 1, false)
+    WPASS(true, 1, true)
+#undef WPASS
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_wavelet_pass(bool dbl, bool inv, int axis, bool acc, const void *src, void *dst,
+                               const WaveletFilter &f, int n, int other, int ld, int64_t img, int n_img,
+                               hipStream_t s) {
+    if (dbl) return wavelet_pass_t<double>(inv, axis, acc, src, dst, f, n, other, ld, img, n_img, s);
+    return wavelet_pass_t<float>(inv, axis, acc, src, dst, f, n, other, ld, img, n_img, s);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void wave_copy_kernel(const R *src, R *dst, int64_t n, R scale) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        dst[i] = src[i] * scale;
+}
+hipError_t launch_wave_copy(bool dbl, const void *src, void *dst, int64_t n, double scale, hipStream_t s) {
+    const int64_t nb = wave_blocks(n);
+    if (dbl)
+        PFB_LAUNCH(wave_copy_kernel<double>, nb, 0, s, (const double *)src, (double *)dst, n, scale);
+    else
+        PFB_LAUNCH(wave_copy_kernel<float>, nb, 0, s, (const float *)src, (float *)dst, n, (float)scale);
+    return hipSuccess;
+}
+
+// Primal update of the primal-dual iteration, per pixel:
+//   x~ = max(x - tau ((c + sigma_u d) / gamma + psi_scale * s), 0),   d = x - z, c = I^psf * d
+//   u  = 2 x~ - x;  x = x~;  d = x~ - z
+// INIT (before the first iteration): x = max(z, 0) unless warm, d = x - z.
+template <typename R, bool INIT>
+__global__ __launch_bounds__(kThreads) void pd_primal_kernel(const R *z, R *x, R *d, const R *c, const R *sv, R *u,
+                                                             int64_t n, R tau, R inv_gamma, R sigma_u, R psi_scale,
+                                                             int warm) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        if (INIT) {
+            const R xi = warm ? x[i] : max(z[i], R(0));
+            x[i] = xi;
+            d[i] = xi - z[i];
+        } else {
+            const R xi = x[i], di = d[i];
+            const R grad = (c[i] + sigma_u * di) * inv_gamma;
+            const R xt = max(xi - tau * (grad + psi_scale * sv[i]), R(0));
+            u[i] = R(2) * xt - xi;
+            x[i] = xt;
+            d[i] = xt - z[i];
+        }
+    }
+}
+
+// Dual update per (basis, coefficient): t_b = v_b + sigma_d psi_scale a_b over the
+// bands b, v = t min(1, lam / ||t||_2); basis 0 reads the image u (Dirac), basis
+// k >= 1 its analysis coefficients.  ZERO: v = 0.
+template <typename R, bool ZERO>
+__global__ __launch_bounds__(kThreads) void pd_dual_kernel(R *v, const R *u, const R *coef, int nbasis, int n_band,
+                                                           int64_t P, R sigma_d, R psi_scale, R lam) {
+    const int64_t total = (int64_t)nbasis * P;
+    for (int64_t id = (int64_t)blockIdx.x * kThreads + threadIdx.x; id < total;
+         id += (int64_t)gridDim.x * kThreads) {
+        const int k = (int)(id / P);
+        const int64_t p = id - (int64_t)k * P;
+        R *vk = v + (size_t)k * n_band * P + p;
+        if (ZERO) {
+            for (int b = 0; b < n_band; ++b) vk[(size_t)b * P] = R(0);
+            continue;
+        }
+        const R *ak = k == 0 ? u + p : coef + (size_t)(k - 1) * n_band * P + p;
+        double nrm2 = 0.0;
+        for (int b = 0; b < n_band; ++b) {
+            const R t = vk[(size_t)b * P] + sigma_d * psi_scale * ak[(size_t)b * P];
+            nrm2 += (double)t * (double)t;
+        }
+        const double nrm = sqrt(nrm2);
+        const R sc = nrm > (double)lam ? (R)((double)lam / nrm) : R(1);
+        for (int b = 0; b < n_band; ++b) {
+            const R t = vk[(size_t)b * P] + sigma_d * psi_scale * ak[(size_t)b * P];
+            vk[(size_t)b * P] = t * sc;
+        }
+    }
+}
+
+hipError_t launch_pd_primal(bool dbl, bool init, const void *z, void *x, void *d, const void *c, const void *sv,
+                            void *u, int64_t n, double tau, double gamma, double sigma_u, double psi_scale, int warm,
+                            hipStream_t s) {
+    const int64_t nb = wave_blocks(n);
+#define PDP(T)                                                                                                    \
+    if (init)                                                                                                     \
+        PFB_LAUNCH((pd_primal_kernel<T, true>), nb, 0, s, (const T *)z, (T *)x, (T *)d, (const T *)c,           \
+                   (const T *)sv, (T *)u, n, (T)tau, (T)(1.0 / gamma), (T)sigma_u, (T)psi_scale, warm);          \
+    else                                                                                                          \
+        PFB_LAUNCH((pd_primal_kernel<T, false>), nb, 0, s, (const T *)z, (T *)x, (T *)d, (const T *)c,          \
+                   (const T *)sv, (T *)u, n, (T)tau, (T)(1.0 / gamma), (T)sigma_u, (T)psi_scale, warm);
+    if (dbl) {
+        PDP(double)
+    } else {
+        PDP(float)
+    }
+#undef PDP
+    return hipSuccess;
+}
+
+hipError_t launch_pd_dual(bool dbl, bool zero, void *v, const void *u, const void *coef, int nbasis, int n_band,
+                          int64_t P, double sigma_d, double psi_scale, double lam, hipStream_t s) {
+    const int64_t nb = wave_blocks((int64_t)nbasis * P);
+#define PDD(T)                                                                                                  \
+    if (zero)                                                                                                   \
+        PFB_LAUNCH((pd_dual_kernel<T, true>), nb, 0, s, (T *)v, (const T *)u, (const T *)coef, nbasis, n_band, \
+                   P, (T)sigma_d, (T)psi_scale, (T)lam);                                                        \
+    else                                                                                                        \
+        PFB_LAUNCH((pd_dual_kernel<T, false>), nb, 0, s, (T *)v, (const T *)u, (const T *)coef, nbasis, n_band,\
+                   P, (T)sigma_d, (T)psi_scale, (T)lam);
+    if (dbl) {
+        PDD(double)
+    } else {
+        PDD(float)
+    }
+#undef PDD
+    return hipSuccess;
+}
+
 }  // namespace pfb

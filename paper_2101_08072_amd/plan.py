@@ -229,6 +229,46 @@ class Plan:
                                         float(lam), int(cg_iters), _stream()))
         return x
 
+    # -- backward step: eq. (7) with the regulariser of eq. (9) -------------------------
+    def prox_workspace(self, nbasis: int = 7) -> torch.Tensor:
+        """Device workspace of the wavelet and prox calls (holds the dual variable)."""
+        n = ctypes.c_size_t(0)
+        _lib.check(self.lib.pfb_prox_workspace_size(self.handle, int(nbasis), ctypes.byref(n)))
+        return torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=self.uvw.device)
+
+    def coeffs(self, nbasis: int = 7) -> torch.Tensor:
+        return torch.empty((nbasis, self.n_band, self.nx, self.ny), dtype=self.real, device=self.uvw.device)
+
+    def wavelet_analysis(self, x: torch.Tensor, ws: torch.Tensor, nbasis: int = 7, levels: int = 3,
+                         out: torch.Tensor | None = None) -> torch.Tensor:
+        """Psi^dagger x: Dirac + db1 .. db(nbasis-1), periodic, ``levels`` levels."""
+        self._chk(x, (self.n_band, self.nx, self.ny), self.real)
+        out = self.coeffs(nbasis) if out is None else out
+        self._chk(out, (nbasis, self.n_band, self.nx, self.ny), self.real)
+        _lib.check(self.lib.pfb_wavelet_analysis(self.handle, _ptr(x), _ptr(out), _ptr(ws), ws.numel(),
+                                                 int(nbasis), int(levels), _stream()))
+        return out
+
+    def wavelet_synthesis(self, c: torch.Tensor, ws: torch.Tensor, nbasis: int = 7, levels: int = 3,
+                          out: torch.Tensor | None = None) -> torch.Tensor:
+        """Psi c (the adjoint of wavelet_analysis)."""
+        self._chk(c, (nbasis, self.n_band, self.nx, self.ny), self.real)
+        out = self.image() if out is None else out
+        self._chk(out, (self.n_band, self.nx, self.ny), self.real)
+        _lib.check(self.lib.pfb_wavelet_synthesis(self.handle, _ptr(c), _ptr(out), _ptr(ws), ws.numel(),
+                                                  int(nbasis), int(levels), _stream()))
+        return out
+
+    def prox(self, z: torch.Tensor, x: torch.Tensor, ws: torch.Tensor, lam: float, gamma: float, sigma: float,
+             unorm: float, iters: int, nbasis: int = 7, levels: int = 3, warm: bool = False) -> torch.Tensor:
+        """x = prox^U_{gamma r}(z), U = I^psf * + sigma Id, by ``iters`` primal-dual steps; x in place."""
+        self._chk(z, (self.n_band, self.nx, self.ny), self.real)
+        self._chk(x, (self.n_band, self.nx, self.ny), self.real)
+        _lib.check(self.lib.pfb_prox_solve(self.handle, _ptr(z), _ptr(x), _ptr(ws), ws.numel(), int(nbasis),
+                                           int(levels), float(lam), float(gamma), float(sigma), float(unorm),
+                                           int(iters), 1 if warm else 0, _stream()))
+        return x
+
 
 class FbGraph:
     """An instantiated HIP graph of FB iterations (keeps its plan and buffers alive)."""

@@ -47,6 +47,11 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.pfb_plan_workspace_size(None, None) == -1
     assert lib.pfb_grid(None, None, None, 0, None) == -1
     assert lib.pfb_psf_conv(None, None, None, None) == -1
+    n = ctypes.c_size_t(0)
+    assert lib.pfb_prox_workspace_size(None, 7, ctypes.byref(n)) == -1
+    assert lib.pfb_wavelet_analysis(None, None, None, None, 0, 7, 3, None) == -1
+    assert lib.pfb_wavelet_synthesis(None, None, None, None, 0, 7, 3, None) == -1
+    assert lib.pfb_prox_solve(None, None, None, None, 0, 7, 3, 1.0, 1.0, 1.0, 1.0, 1, 0, None) == -1
     assert lib.pfb_plan_destroy(None) == 0
 
 

@@ -1,0 +1,95 @@
+"""GPU parity of the backward step (eq. 7 with the regulariser of eq. 9) through the
+C ABI: the wavelet dictionary Psi^dagger / Psi and the primal-dual prox against
+the FP64 oracle, on a two-band, non-square problem."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import wavelets as wv
+from gpu_helpers import TOL, host, make_plan, rel, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = ["fp32", "fp64"]
+
+
+def _real(prec):
+    import torch
+    return torch.float64 if prec == "fp64" else torch.float32
+
+
+@pytest.fixture(scope="module")
+def mb():
+    prob = synth.tiny_problem(seed=91, nx=64, ny=32, n_row=700, freqs=(1.0e9, 1.1e9, 1.3e9, 1.4e9),
+                              cell_arcsec=120.0, w_frac=1.5, n_band=2, flag_frac=0.2)
+    say("oracle: PSF of the two-band problem")
+    psf = oracle.psf(prob)
+    unorm, _ = oracle.power_iteration(lambda v: oracle.psf_conv(psf, v), np.ones((2, 64, 32)), 60)
+    return dict(prob=prob, psf=psf, unorm=1.05 * unorm)
+
+
+@pytest.fixture(scope="module", params=PRECISIONS)
+def mb_plan(request, mb):
+    say(f"plan: two-band 64x32 {request.param}")
+    plan = make_plan(mb["prob"], request.param)
+    plan.make_psf(want_image=False)
+    return request.param, plan
+
+
+@pytest.mark.parametrize("nbasis,levels", [(7, 3), (3, 1), (1, 2)])
+def test_wavelet_analysis_and_synthesis(mb_plan, nbasis, levels):
+    prec, plan = mb_plan
+    R = _real(prec)
+    rng = np.random.default_rng(5 + nbasis + levels)
+    x = rng.normal(size=(2, 64, 32))
+    c = rng.normal(size=(nbasis, 2, 64, 32))
+    ws = plan.prox_workspace(nbasis)
+    say(f"wavelets {prec} nbasis {nbasis} levels {levels}")
+    a = host(plan.wavelet_analysis(to_dev(x, R), ws, nbasis, levels))
+    assert rel(a, wv.psi_adj(x, levels, nbasis)) < TOL[prec]
+    s = host(plan.wavelet_synthesis(to_dev(c, R), ws, nbasis, levels))
+    assert rel(s, wv.psi(c, levels, nbasis)) < TOL[prec]
+    # tight frame on the GPU: Psi Psi^dagger x = x
+    back = host(plan.wavelet_synthesis(to_dev(a, R), ws, nbasis, levels))
+    assert rel(back, x) < TOL[prec]
+
+
+def test_prox_matches_oracle_and_warm_start(mb, mb_plan):
+    prec, plan = mb_plan
+    R = _real(prec)
+    rng = np.random.default_rng(17)
+    z = rng.normal(size=(2, 64, 32)) + 0.3
+    unorm = mb["unorm"]
+    sigma, gamma, lam, levels, iters = 0.1 * unorm, 1.0, 0.1, 2, 30
+    ws = plan.prox_workspace(7)
+    zg = to_dev(z, R)
+    say(f"prox {prec}: {iters} primal-dual iterations")
+    x = plan.prox(zg, to_dev(np.zeros_like(z), R), ws, lam, gamma, sigma, unorm, iters, 7, levels)
+    xh = host(x)
+    x_ref, v_ref = wv.prox_pd(lambda v: oracle.psf_conv(mb["psf"], v), z, sigma, gamma, lam, unorm, levels, iters)
+    tol = 5e-5 if prec == "fp32" else 1e-9
+    assert rel(xh, x_ref) < tol
+    assert (xh >= 0).all()
+    # the dual variable left in the workspace: |v| <= lam per band vector
+    v = host(ws[: 7 * 2 * 64 * 32 * (8 if prec == "fp64" else 4)].view(R)).reshape(7, 2, 64, 32)
+    assert rel(v, v_ref) < 10 * tol
+    assert (np.sqrt((v.astype(np.float64) ** 2).sum(axis=1)) <= lam * (1 + 1e-5)).all()
+    # 15 + 15 warm-started iterations equal 30 in one call, bit for bit
+    x2 = plan.prox(zg, to_dev(np.zeros_like(z), R), ws, lam, gamma, sigma, unorm, 15, 7, levels)
+    x2 = plan.prox(zg, x2, ws, lam, gamma, sigma, unorm, 15, 7, levels, warm=True)
+    assert np.array_equal(host(x2), xh)
+
+
+def test_prox_zero_iterations_and_bad_arguments(mb_plan):
+    prec, plan = mb_plan
+    R = _real(prec)
+    from paper_2101_08072_amd import _lib
+    z = np.random.default_rng(2).normal(size=(2, 64, 32))
+    ws = plan.prox_workspace(7)
+    x = host(plan.prox(to_dev(z, R), to_dev(np.zeros_like(z), R), ws, 0.1, 1.0, 0.0, 1.0, 0))
+    assert np.array_equal(x, np.maximum(z, 0).astype(x.dtype))
+    with pytest.raises(_lib.PfbError):
+        plan.prox(to_dev(z, R), to_dev(z, R), ws, 0.1, 1.0, 0.0, 1.0, 3, levels=7)   # 32 is not a multiple of 2^7
+    with pytest.raises(_lib.PfbError):
+        plan.prox(to_dev(z, R), to_dev(z, R), ws[:16], 0.1, 1.0, 0.0, 1.0, 3)        # workspace too small
