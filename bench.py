@@ -361,6 +361,23 @@ def main():
         "cg_solve": timed(lambda: plan.precond_solve(dirty, sigma, args.cg_iters, out=hx)),
     }
     breakdown["fb_step"] = ms_step - breakdown["grid"] - breakdown["degrid"] - breakdown["hessian"]
+
+    # backward step of eq. 7 with the regulariser of eq. 9 (outside the step above, which
+    # keeps the Euclidean l1 prox): primal-dual iterations with the Dirac + db1-6
+    # dictionary at 3 levels and the PSF metric; per-kernel times from the same profiler
+    prox_levels, prox_iters = 3, 10
+    prox_ws = plan.prox_workspace(7)
+    xp = plan.image()
+    lam_prox = 1e-3 * float(dirty.abs().max().item())
+    plan.prox(dirty, xp, prox_ws, lam_prox, gamma, sigma, 1.05 * lam_max, 1, 7, prox_levels)
+    breakdown["prox_iteration"] = timed(lambda: plan.prox(dirty, xp, prox_ws, lam_prox, gamma, sigma, 1.05 * lam_max,
+                                                          prox_iters, 7, prox_levels), n=2) / prox_iters
+    plan.profile(True)
+    plan.prox(dirty, xp, prox_ws, lam_prox, gamma, sigma, 1.05 * lam_max, prox_iters, 7, prox_levels)
+    torch.cuda.synchronize()
+    prox_prof = plan.profile_report()
+    plan.profile(False)
+    del prox_ws
     grid_degrid_vis_s = M / ((breakdown["grid"] + breakdown["degrid"]) * 1e-3)
     hess_apps = 1e3 / breakdown["hessian"]
 
@@ -401,6 +418,22 @@ def main():
                 peak = PEAK["fp32_matrix_TFLOPs"] if bound == "mfma" else PEAK["fp32_vector_TFLOPs"]
                 kernels[k].update(bound=bound, achieved_TFLOPs=round(ach, 3), frac=round(ach / peak, 4))
     log("kernels:", json.dumps(kernels))
+
+    # backward step: per-kernel ms per primal-dual iteration; the wavelet passes against
+    # HBM with algorithmic bytes = one read and one write of every level block, two passes
+    # (rows, columns) per level, six wavelet bases, analysis and synthesis
+    rsz = 4
+    blk = sum(prob.n_band * (prob.nx >> l) * (prob.ny >> l) for l in range(prox_levels))
+    wave_bytes = 2 * 6 * 2 * 2 * blk * rsz
+    prox_k = {k: {"launches_per_iteration": n / prox_iters, "ms_per_iteration": round(t / prox_iters, 4)}
+              for k, (n, t) in sorted(prox_prof.items(), key=lambda kv: -kv[1][1])}
+    if "wavelet_pass_kernel" in prox_k:
+        ach = wave_bytes / (prox_k["wavelet_pass_kernel"]["ms_per_iteration"] * 1e-3) / 1e9
+        prox_k["wavelet_pass_kernel"].update(bound="hbm", achieved_GBps=round(ach, 1),
+                                             frac=round(ach / PEAK["hbm_GBps"], 4))
+    prox_out = {"ms_per_iteration": round(breakdown["prox_iteration"], 4), "nbasis": 7, "levels": prox_levels,
+                "kernels": prox_k}
+    log("prox:", json.dumps(prox_out))
 
     # plain per-band FP64 path on the same GPU (Hessian applications/s)
     plain = None
@@ -487,6 +520,7 @@ def main():
         "one_band_per_launch": per_band,
         "breakdown_ms": {k: round(v, 4) for k, v in breakdown.items()},
         "kernels": kernels,
+        "prox": prox_out,
         "parity_rel_l2": parity,
         "setup_s": {"plan": round(plan_s, 3), "psf": round(psf_s, 3)},
         "lambda_max": lam_max,

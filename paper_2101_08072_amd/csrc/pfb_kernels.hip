@@ -2441,58 +2441,57 @@ hipError_t launch_copy_scalar(int n_band, const double *scal, int slot, double *
 // One periodic wavelet level along one axis of a block of images.  The block is
 // rows x n (AXIS 1: along the contiguous axis) or n x cols (AXIS 0: along the
 // strided axis) at the top-left of every image; images are `img` elements apart,
-// rows `ld` apart.  Analysis (INV false): low[k] = sum_j h[j] x[(2k + j) mod n],
-// high[k] = sum_j g[j] x[(2k + j) mod n] with g[j] = (-1)^j h[len-1-j], stored as
-// [low | high].  Synthesis (INV true): the adjoint, x[m] = sum over taps j with
-// m - j even of h[j] low[k] + g[j] high[k], k = ((m - j) mod n) / 2; ACC adds the
+// rows `ld` apart.  N: vanishing moments (2N taps).  A thread owns coefficient
+// pair k < n/2.  Analysis (INV false): low[k] = sum_j h[j] x[(2k + j) mod n],
+// high[k] = sum_j g[j] x[(2k + j) mod n], g[j] = (-1)^j h[2N-1-j], stored as
+// [low | high].  Synthesis (INV true): the adjoint, x[2k + e] = sum_i h[2i + e]
+// low[(k - i) mod n/2] + g[2i + e] high[(k - i) mod n/2] for e = 0, 1; ACC adds the
 // result to dst instead of storing it.
-template <typename R, bool INV, int AXIS, bool ACC>
-__global__ __launch_bounds__(kThreads) void wavelet_pass_kernel(const R *src, R *dst, WaveletFilter f, int n,
-                                                                int other, int ld, int64_t img, int n_img) {
-    const int64_t per = (int64_t)n * other;
-    const int64_t total = per * n_img;
-    const int len = f.len;
+template <typename R> struct WaveletTaps {
+    R h[kMaxWaveletTaps], g[kMaxWaveletTaps];
+};
+template <typename R, int N, bool INV, int AXIS, bool ACC>
+__global__ __launch_bounds__(kThreads) void wavelet_pass_kernel(const R *src, R *dst, WaveletTaps<R> f, int n,
+                                                                int other, int ld, int64_t img) {
+    // grid: x over the contiguous index (k for AXIS 1, o for AXIS 0), y over the
+    // other index, z over the images
     const int half = n >> 1;
-    for (int64_t id = (int64_t)blockIdx.x * kThreads + threadIdx.x; id < total;
-         id += (int64_t)gridDim.x * kThreads) {
-        const int64_t im = id / per;
-        const int64_t rem = id - im * per;
-        // AXIS 1: consecutive threads along the axis; AXIS 0: along the other (contiguous) axis
-        int o, m;
-        if (AXIS == 1) {
-            o = (int)(rem / n);
-            m = (int)(rem - (int64_t)o * n);
-        } else {
-            m = (int)(rem / other);
-            o = (int)(rem - (int64_t)m * other);
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    const int k = AXIS == 1 ? c : (int)blockIdx.y;
+    const int o = AXIS == 1 ? (int)blockIdx.y : c;
+    if (c >= (AXIS == 1 ? half : other)) return;
+    const R *sp = src + (size_t)blockIdx.z * img;
+    R *dp = dst + (size_t)blockIdx.z * img;
+    auto idx = [&](int i) -> size_t { return AXIS == 1 ? (size_t)o * ld + i : (size_t)i * ld + o; };
+    if (!INV) {
+        R lo = R(0), hi = R(0);
+        int i = 2 * k;
+#pragma unroll
+        for (int j = 0; j < 2 * N; ++j) {
+            const R x = sp[idx(i)];
+            lo += f.h[j] * x;
+            hi += f.g[j] * x;
+            if (++i == n) i = 0;
         }
-        const R *sp = src + im * img;
-        auto at = [&](int i) -> R { return AXIS == 1 ? sp[(size_t)o * ld + i] : sp[(size_t)i * ld + o]; };
-        R acc = R(0);
-        if (!INV) {
-            // output m: low (m < half) or high (m >= half) coefficient k
-            const bool hi = m >= half;
-            const int k = hi ? m - half : m;
-            for (int j = 0; j < len; ++j) {
-                const R w = hi ? ((j & 1) ? -f.h[len - 1 - j] : f.h[len - 1 - j]) : f.h[j];
-                int i = 2 * k + j;
-                i -= (i / n) * n;
-                acc += (R)w * at(i);
-            }
-        } else {
-            for (int j = (m & 1); j < len; j += 2) {    // taps with m - j even
-                int t = m - j;
-                t %= n;
-                if (t < 0) t += n;
-                const int k = t >> 1;
-                const R hw = (R)f.h[j];
-                const R gw = (R)((j & 1) ? -f.h[len - 1 - j] : f.h[len - 1 - j]);
-                acc += hw * at(k) + gw * at(half + k);
-            }
+        dp[idx(k)] = lo;
+        dp[idx(half + k)] = hi;
+    } else {
+        R x0 = R(0), x1 = R(0);
+        int t = k;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const R a = sp[idx(t)], d = sp[idx(half + t)];
+            x0 += f.h[2 * i] * a + f.g[2 * i] * d;
+            x1 += f.h[2 * i + 1] * a + f.g[2 * i + 1] * d;
+            if (--t < 0) t += half;
         }
-        R *dp = dst + im * img + (AXIS == 1 ? (size_t)o * ld + m : (size_t)m * ld + o);
-        if (ACC) *dp += acc;
-        else *dp = acc;
+        if (ACC) {
+            dp[idx(2 * k)] += x0;
+            dp[idx(2 * k + 1)] += x1;
+        } else {
+            dp[idx(2 * k)] = x0;
+            dp[idx(2 * k + 1)] = x1;
+        }
     }
 }
 
@@ -2501,16 +2500,16 @@ static int64_t wave_blocks(int64_t total) {
     return nb < 1 ? 1 : (nb > 65536 ? 65536 : nb);
 }
 
-template <typename R>
-static hipError_t wavelet_pass_t(bool inv, int axis, bool acc, const void *src, void *dst, const WaveletFilter &f,
-                                 int n, int other, int ld, int64_t img, int n_img, hipStream_t s) {
-    const int64_t nb = wave_blocks((int64_t)n * other * n_img);
-    const R *sp = reinterpret_cast<const R *>(src);
-    R *dp = reinterpret_cast<R *>(dst);
-#define WPASS(I, X, C)                                                                        \
-    if (inv == I && axis == X && acc == C) {                                                  \
-        PFB_LAUNCH((wavelet_pass_kernel<R, I, X, C>), nb, 0, s, sp, dp, f, n, other, ld, img, n_img); \
-        return hipSuccess;                                                                    \
+template <typename R, int N>
+static hipError_t wavelet_pass_n(bool inv, int axis, bool acc, const R *sp, R *dp, const WaveletTaps<R> &f, int n,
+                                 int other, int ld, int64_t img, int n_img, hipStream_t s) {
+    const int contig = axis == 1 ? n / 2 : other, strided = axis == 1 ? other : n / 2;
+    if (strided > 65535 || n_img > 65535 || n < 2 || (n & 1)) return hipErrorInvalidValue;
+    const dim3 grid((contig + kThreads - 1) / kThreads, strided, n_img);
+#define WPASS(I, X, C)                                                                           \
+    if (inv == I && axis == X && acc == C) {                                                     \
+        PFB_LAUNCH((wavelet_pass_kernel<R, N, I, X, C>), grid, 0, s, sp, dp, f, n, other, ld, img); \
+        return hipSuccess;                                                                       \
     }
     WPASS(false, 1, false)
     WPASS(false, 0, false)
@@ -2519,6 +2518,23 @@ static hipError_t wavelet_pass_t(bool inv, int axis, bool acc, const void *src, 
     WPASS(true, 1, true)
 #undef WPASS
     return hipErrorInvalidValue;
+}
+
+template <typename R>
+static hipError_t wavelet_pass_t(bool inv, int axis, bool acc, const void *src, void *dst, const WaveletFilter &f,
+                                 int n, int other, int ld, int64_t img, int n_img, hipStream_t s) {
+    WaveletTaps<R> t{};
+    const int L = f.len;
+    if (L < 2 || L > kMaxWaveletTaps || (L & 1)) return hipErrorInvalidValue;
+    for (int j = 0; j < L; ++j) {
+        t.h[j] = (R)f.h[j];
+        t.g[j] = (R)((j & 1) ? -f.h[L - 1 - j] : f.h[L - 1 - j]);
+    }
+    const R *sp = reinterpret_cast<const R *>(src);
+    R *dp = reinterpret_cast<R *>(dst);
+    return dispatch_int<1, 6>(L / 2, [&](auto Nc) {
+        return wavelet_pass_n<R, decltype(Nc)::value>(inv, axis, acc, sp, dp, t, n, other, ld, img, n_img, s);
+    });
 }
 
 hipError_t launch_wavelet_pass(bool dbl, bool inv, int axis, bool acc, const void *src, void *dst,
