@@ -232,6 +232,16 @@ pfb_status pfb_prox_solve(pfb_plan *plan, const void *z, void *x, void *ws, size
                           int levels, double lambda, double gamma, double sigma, double unorm, int iters,
                           int warm, hipStream_t stream);
 
+/* One forward-backward step of the paper (eqs. 6-7 with the regulariser of eq. 9):
+ *   z = x - gamma U^-1 (I^psf * x - I^d), U^-1 by `cg_iters` CG steps (as pfb_fb_step);
+ *   x = prox^U_{gamma r}(z) by `pd_iters` iterations of pfb_prox_solve (warm as there:
+ *   warm != 0 starts the primal-dual iteration from the x passed in and the dual
+ *   variable kept in ws).  ws as for pfb_prox_solve (the same size query); dirty, x
+ *   DEVICE real [n_band][nx][ny]; x is updated in place. */
+pfb_status pfb_fb_step_wavelet(pfb_plan *plan, const void *dirty, void *x, void *ws, size_t ws_bytes, int nbasis,
+                               int levels, double sigma, double gamma, double lambda, double unorm, int cg_iters,
+                               int pd_iters, int warm, hipStream_t stream);
+
 /* hipGraph capture of forward-backward iterations (for launch-bound loops).
  * Captures `n_steps` consecutive pfb_fb_step(plan, dirty, x, sigma, gamma, lambda,
  * cg_iters) calls into one instantiated HIP graph.  `stream` must be a

@@ -249,8 +249,22 @@ def cg(apply_A, g, iters, y0=None):
 
 
 def precond_solve(psf_img, g, sigma, iters):
-    """y ~= (I^psf * + sigma Id)^-1 g by ``iters`` CG steps (eq. 8 and the text after it)."""
-    return cg(lambda v: psf_conv(psf_img, v) + sigma * v, g, iters)
+    """y ~= (I^psf * + sigma Id)^-1 g by ``iters`` CG steps (eq. 8 and the text after it).
+
+    U acts on every band with that band's PSF (eq. 4), so the system is
+    block-diagonal over bands; each band's system gets its own CG (its own step
+    lengths).  Returns (y, residual norms^2 with shape (n_band, iterations + 1))."""
+    g = np.asarray(g, dtype=np.float64)
+    psf_img = np.asarray(psf_img, dtype=np.float64)
+    ys, traces = [], []
+    for b in range(g.shape[0]):
+        pb = psf_img[b:b + 1]
+        yb, tb = cg(lambda v: psf_conv(pb, v[None])[0] + sigma * v, g[b], iters)
+        ys.append(yb)
+        traces.append(tb)
+    n = max(len(t) for t in traces)
+    trace = np.array([np.pad(t, (0, n - len(t)), mode="edge") for t in traces])
+    return np.stack(ys), trace
 
 
 def power_iteration(apply_A, v0, iters):

@@ -181,3 +181,16 @@ def prox_pd(apply_psf, z, sigma_u, gamma, lam, unorm, levels, iters, nbasis=7, x
         v = l21_dual_project(v + sigma_d * psi_adj(2.0 * xt - x, levels, nbasis), lam)
         x = xt
     return x, v
+
+
+def fb_step_wavelet(psf_img, dirty, x, sigma, gamma, lam, unorm, cg_iters, pd_iters, levels, nbasis=7,
+                    v0=None, warm=False):
+    """One forward-backward step of eqs. 6-7 with the regulariser of eq. 9:
+    z = x - gamma U^-1 (I^psf * x - I^d) by CG, then x = prox^U_{gamma r}(z) by
+    ``prox_pd`` (warm: from the given x and dual v0).  Returns (x, v)."""
+    import oracle
+    grad = oracle.psf_conv(psf_img, x) - dirty
+    y, _ = oracle.precond_solve(psf_img, grad, sigma, cg_iters)
+    z = np.asarray(x, dtype=np.float64) - gamma * y
+    return prox_pd(lambda v: oracle.psf_conv(psf_img, v), z, sigma, gamma, lam, unorm, levels, pd_iters, nbasis,
+                   x0=x if warm else None, v0=v0 if warm else None)

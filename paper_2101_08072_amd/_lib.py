@@ -20,7 +20,8 @@ EXPORTS = ["pfb_plan_create", "pfb_plan_workspace_size", "pfb_plan_set_workspace
            "pfb_psf_conv", "pfb_precond_solve", "pfb_power_iteration", "pfb_fb_step",
            "pfb_fb_graph_create", "pfb_graph_launch", "pfb_graph_destroy",
            "pfb_profile_enable", "pfb_profile_report", "pfb_last_error", "pfb_version",
-           "pfb_prox_workspace_size", "pfb_wavelet_analysis", "pfb_wavelet_synthesis", "pfb_prox_solve"]
+           "pfb_prox_workspace_size", "pfb_wavelet_analysis", "pfb_wavelet_synthesis", "pfb_prox_solve",
+           "pfb_fb_step_wavelet"]
 
 
 class PfbProblem(ctypes.Structure):
@@ -86,6 +87,7 @@ def load():
         "pfb_wavelet_analysis": [vp, vp, vp, vp, sz, i32, i32, vp],
         "pfb_wavelet_synthesis": [vp, vp, vp, vp, sz, i32, i32, vp],
         "pfb_prox_solve": [vp, vp, vp, vp, sz, i32, i32, f64, f64, f64, f64, i32, i32, vp],
+        "pfb_fb_step_wavelet": [vp, vp, vp, vp, sz, i32, i32, f64, f64, f64, f64, i32, i32, i32, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -1388,7 +1388,7 @@ WaveletFilter db_filter(int n) {
 // element offsets (in reals) of the prox workspace: v, coef, then six image buffers
 struct ProxLayout {
     int64_t NP;          // n_band * nx * ny
-    size_t v, coef, d, c, u, sv, a, b, total;   // bytes
+    size_t v, coef, d, c, u, sv, a, b, z, total;   // bytes
 };
 ProxLayout prox_layout(const pfb_plan *P, int nbasis) {
     ProxLayout L{};
@@ -1402,7 +1402,8 @@ ProxLayout prox_layout(const pfb_plan *P, int nbasis) {
     L.sv = L.u + img;
     L.a = L.sv + img;
     L.b = L.a + img;
-    L.total = L.b + img;
+    L.z = L.b + img;      // forward-step result of pfb_fb_step_wavelet
+    L.total = L.z + img;
     return L;
 }
 
@@ -1539,6 +1540,32 @@ pfb_status pfb_prox_solve(pfb_plan *P, const void *z, void *x, void *ws, size_t 
                                  sigma_d, psi_scale, lambda, s));
     }
     return PFB_OK;
+}
+
+pfb_status pfb_fb_step_wavelet(pfb_plan *P, const void *dirty, void *x, void *ws, size_t ws_bytes, int nbasis,
+                               int levels, double sigma, double gamma, double lambda, double unorm, int cg_iters,
+                               int pd_iters, int warm, hipStream_t s) {
+    ProfScope prof_scope(P);
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!dirty || !x || !ws) return fail(PFB_EINVAL, "dirty, x and ws must be non-NULL");
+    if (!P->psf_ready) return fail(PFB_ESTATE, "no PSF spectrum: call pfb_grid with PFB_GRID_PSF first");
+    if ((st = wavelet_args_ok(P, nbasis, levels))) return st;
+    if (!(sigma >= 0) || !(gamma > 0) || cg_iters < 0) return fail(PFB_EINVAL, "need sigma >= 0, gamma > 0, cg_iters >= 0");
+    const ProxLayout L = prox_layout(P, nbasis);
+    if (ws_bytes < L.total) return fail(PFB_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    const bool d = P->dbl;
+    ConvArgs ca = conv_args(P);
+    char *v = reinterpret_cast<char *>(P->p(P->o_vec));
+    void *g = v + 3 * P->vec_bytes, *y = v + 4 * P->vec_bytes;
+    void *z = reinterpret_cast<char *>(ws) + L.z;
+    // forward step (eq. 6): z = x - gamma U^-1 (I^psf * x - I^d)
+    LAUNCH_OK(launch_psf_conv(d, ca, x, nullptr, g, dirty, 0.0, CONV_IN_X, CONV_OUT_SUB, s));
+    st = cg_solve(P, g, y, sigma, cg_iters, s);
+    if (st) return st;
+    LAUNCH_OK(launch_wave_axpy(d, x, y, z, L.NP, -gamma, s));
+    // backward step (eq. 7 with the regulariser of eq. 9)
+    return pfb_prox_solve(P, z, x, ws, ws_bytes, nbasis, levels, lambda, gamma, sigma, unorm, pd_iters, warm, s);
 }
 
 }  // extern "C"

@@ -198,6 +198,7 @@ hipError_t launch_wavelet_pass(bool dbl, bool inv, int axis, bool acc, const voi
                                const WaveletFilter &f, int n, int other, int ld, int64_t img, int n_img,
                                hipStream_t s);
 hipError_t launch_wave_copy(bool dbl, const void *src, void *dst, int64_t n, double scale, hipStream_t s);
+hipError_t launch_wave_axpy(bool dbl, const void *x, const void *y, void *z, int64_t n, double a, hipStream_t s);   // z = x + a y
 hipError_t launch_pd_primal(bool dbl, bool init, const void *z, void *x, void *d, const void *c, const void *sv,
                             void *u, int64_t n, double tau, double gamma, double sigma_u, double psi_scale, int warm,
                             hipStream_t s);

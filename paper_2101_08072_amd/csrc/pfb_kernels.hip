@@ -2549,6 +2549,20 @@ __global__ __launch_bounds__(kThreads) void wave_copy_kernel(const R *src, R *ds
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
         dst[i] = src[i] * scale;
 }
+template <typename R>
+__global__ __launch_bounds__(kThreads) void wave_axpy_kernel(const R *x, const R *y, R *z, int64_t n, R a) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        z[i] = x[i] + a * y[i];
+}
+hipError_t launch_wave_axpy(bool dbl, const void *x, const void *y, void *z, int64_t n, double a, hipStream_t s) {
+    const int64_t nb = wave_blocks(n);
+    if (dbl)
+        PFB_LAUNCH(wave_axpy_kernel<double>, nb, 0, s, (const double *)x, (const double *)y, (double *)z, n, a);
+    else
+        PFB_LAUNCH(wave_axpy_kernel<float>, nb, 0, s, (const float *)x, (const float *)y, (float *)z, n, (float)a);
+    return hipSuccess;
+}
+
 hipError_t launch_wave_copy(bool dbl, const void *src, void *dst, int64_t n, double scale, hipStream_t s) {
     const int64_t nb = wave_blocks(n);
     if (dbl)

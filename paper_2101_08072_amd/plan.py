@@ -269,6 +269,18 @@ class Plan:
                                            int(iters), 1 if warm else 0, _stream()))
         return x
 
+    def fb_step_wavelet(self, dirty: torch.Tensor, x: torch.Tensor, ws: torch.Tensor, sigma: float, gamma: float,
+                        lam: float, unorm: float, cg_iters: int, pd_iters: int, nbasis: int = 7, levels: int = 3,
+                        warm: bool = False) -> torch.Tensor:
+        """One forward-backward step of eqs. 6-7 with the l2,1 wavelet prior of eq. 9; x in place."""
+        self._chk(dirty, (self.n_band, self.nx, self.ny), self.real)
+        self._chk(x, (self.n_band, self.nx, self.ny), self.real)
+        _lib.check(self.lib.pfb_fb_step_wavelet(self.handle, _ptr(dirty), _ptr(x), _ptr(ws), ws.numel(),
+                                                int(nbasis), int(levels), float(sigma), float(gamma), float(lam),
+                                                float(unorm), int(cg_iters), int(pd_iters), 1 if warm else 0,
+                                                _stream()))
+        return x
+
 
 class FbGraph:
     """An instantiated HIP graph of FB iterations (keeps its plan and buffers alive)."""

@@ -108,7 +108,7 @@ def test_precond_solve_and_fb_step(tiny, tiny_plan):
     y = host(plan.precond_solve(to_dev(g, R), sigma, iters, resid=resid))
     y_ref, trace = oracle.precond_solve(psf, g, sigma, iters)
     assert rel(y, y_ref) < 10 * TOL[prec]
-    assert abs(host(resid)[0] - trace[-1]) < 1e-3 * trace[0]
+    assert abs(host(resid)[0] - trace[0][-1]) < 1e-3 * trace[0][0]
     say(f"fb_step {prec}")
     dirty = tiny["dirty"]
     x0 = np.abs(tiny["xd"]) * 1e-3

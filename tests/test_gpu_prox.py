@@ -93,3 +93,30 @@ def test_prox_zero_iterations_and_bad_arguments(mb_plan):
         plan.prox(to_dev(z, R), to_dev(z, R), ws, 0.1, 1.0, 0.0, 1.0, 3, levels=7)   # 32 is not a multiple of 2^7
     with pytest.raises(_lib.PfbError):
         plan.prox(to_dev(z, R), to_dev(z, R), ws[:16], 0.1, 1.0, 0.0, 1.0, 3)        # workspace too small
+
+
+def test_fb_step_wavelet_two_steps(mb, mb_plan):
+    """Two forward-backward steps (eqs. 6-7, prior of eq. 9), the second warm-started
+    from the first step's primal and dual variables."""
+    prec, plan = mb_plan
+    R = _real(prec)
+    rng = np.random.default_rng(23)
+    dirty = oracle.psf_conv(mb["psf"], np.abs(rng.normal(size=(2, 64, 32))))
+    x0 = np.zeros((2, 64, 32))
+    unorm = mb["unorm"]
+    sigma, gamma, lam, levels, cg_iters, pd_iters = 0.1 * unorm, 1.0, 0.02 * np.abs(dirty).max(), 2, 8, 10
+    ws = plan.prox_workspace(7)
+    xg = to_dev(x0, R)
+    dg = to_dev(dirty, R)
+    say(f"fb_step_wavelet {prec}")
+    plan.fb_step_wavelet(dg, xg, ws, sigma, gamma, lam, unorm, cg_iters, pd_iters, 7, levels)
+    x1 = host(xg).copy()
+    plan.fb_step_wavelet(dg, xg, ws, sigma, gamma, lam, unorm, cg_iters, pd_iters, 7, levels, warm=True)
+    x2 = host(xg)
+    r1, v1 = wv.fb_step_wavelet(mb["psf"], dirty, x0, sigma, gamma, lam, unorm, cg_iters, pd_iters, levels)
+    r2, _ = wv.fb_step_wavelet(mb["psf"], dirty, r1, sigma, gamma, lam, unorm, cg_iters, pd_iters, levels,
+                               v0=v1, warm=True)
+    tol = 1e-4 if prec == "fp32" else 1e-9
+    assert rel(x1, r1) < tol
+    assert rel(x2, r2) < tol
+    assert (x2 >= 0).all() and np.linalg.norm(x2) > 0

@@ -262,11 +262,18 @@ def test_cg_against_dense_solve_and_scaled_delta(oracle_mod):
     y, trace = oracle_mod.precond_solve(P, g, sigma, 64)
     ref = np.linalg.solve(M + sigma * np.eye(64), g.ravel())
     assert np.abs(y.ravel() - ref).max() < 1e-9 * np.abs(ref).max()
-    assert trace[-1] < 1e-16 * trace[0]
+    assert trace[0][-1] < 1e-16 * trace[0][0]
     D = np.zeros((1, 16, 16))
     D[0, 8, 8] = 3.0
     y1, _ = oracle_mod.precond_solve(D, g, 0.5, 1)
     assert np.allclose(y1, g / 3.5, rtol=1e-14)
+    # bands are independent systems: with PSFs 3 delta and 5 delta one step gives
+    # g_b / (c_b + sigma) in each band (one step length shared by both bands would not)
+    D2 = np.zeros((2, 16, 16))
+    D2[0, 8, 8], D2[1, 8, 8] = 3.0, 5.0
+    g2 = np.random.default_rng(20).normal(size=(2, 8, 8))
+    y2, _ = oracle_mod.precond_solve(D2, g2, 0.5, 1)
+    assert np.allclose(y2[0], g2[0] / 3.5, rtol=1e-14) and np.allclose(y2[1], g2[1] / 5.5, rtol=1e-14)
 
 
 def test_power_iteration_matches_eigvalsh(oracle_mod):
