@@ -242,6 +242,16 @@ pfb_status pfb_fb_step_wavelet(pfb_plan *plan, const void *dirty, void *x, void 
                                int levels, double sigma, double gamma, double lambda, double unorm, int cg_iters,
                                int pd_iters, int warm, hipStream_t stream);
 
+/* pfb-clean iterations (Sec. 2): `n_major` preconditioned forward-backward steps with
+ * the exact gradient, each one Hessian application (eq. 3):
+ *   g = R^dagger Sigma^-1 R x - I^d;  z = x - gamma U^-1 g (`cg_iters` CG steps, eq. 6,
+ *   U = I^psf * + sigma Id, eq. 8);  x = prox^U_{gamma r}(z) (eq. 7, prior of eq. 9,
+ *   `pd_iters` primal-dual steps, warm-started from the previous step after the first).
+ * Arguments as for pfb_fb_step_wavelet; x DEVICE real [n_band][nx][ny] in/out. */
+pfb_status pfb_clean(pfb_plan *plan, const void *dirty, void *x, void *ws, size_t ws_bytes, int nbasis, int levels,
+                     double sigma, double gamma, double lambda, double unorm, int cg_iters, int pd_iters,
+                     int n_major, hipStream_t stream);
+
 /* hipGraph capture of forward-backward iterations (for launch-bound loops).
  * Captures `n_steps` consecutive pfb_fb_step(plan, dirty, x, sigma, gamma, lambda,
  * cg_iters) calls into one instantiated HIP graph.  `stream` must be a

@@ -194,3 +194,19 @@ def fb_step_wavelet(psf_img, dirty, x, sigma, gamma, lam, unorm, cg_iters, pd_it
     z = np.asarray(x, dtype=np.float64) - gamma * y
     return prox_pd(lambda v: oracle.psf_conv(psf_img, v), z, sigma, gamma, lam, unorm, levels, pd_iters, nbasis,
                    x0=x if warm else None, v0=v0 if warm else None)
+
+
+def clean(prob, psf_img, dirty, x0, sigma, gamma, lam, unorm, cg_iters, pd_iters, n_major, levels, nbasis=7):
+    """``n_major`` forward-backward steps of eqs. 6-7 with the exact gradient
+    R^dagger Sigma^-1 R x - I^d (eq. 3, the FP64 direct-sum Hessian) and the prior of
+    eq. 9; the prox is warm-started from the previous step after the first."""
+    import oracle
+    x = np.array(x0, dtype=np.float64)
+    v = None
+    for k in range(n_major):
+        grad = oracle.hessian(prob, x) - dirty
+        y, _ = oracle.precond_solve(psf_img, grad, sigma, cg_iters)
+        z = x - gamma * y
+        x, v = prox_pd(lambda t: oracle.psf_conv(psf_img, t), z, sigma, gamma, lam, unorm, levels, pd_iters, nbasis,
+                       x0=x if k > 0 else None, v0=v if k > 0 else None)
+    return x, v

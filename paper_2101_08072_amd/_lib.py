@@ -21,7 +21,7 @@ EXPORTS = ["pfb_plan_create", "pfb_plan_workspace_size", "pfb_plan_set_workspace
            "pfb_fb_graph_create", "pfb_graph_launch", "pfb_graph_destroy",
            "pfb_profile_enable", "pfb_profile_report", "pfb_last_error", "pfb_version",
            "pfb_prox_workspace_size", "pfb_wavelet_analysis", "pfb_wavelet_synthesis", "pfb_prox_solve",
-           "pfb_fb_step_wavelet"]
+           "pfb_fb_step_wavelet", "pfb_clean"]
 
 
 class PfbProblem(ctypes.Structure):
@@ -88,6 +88,7 @@ def load():
         "pfb_wavelet_synthesis": [vp, vp, vp, vp, sz, i32, i32, vp],
         "pfb_prox_solve": [vp, vp, vp, vp, sz, i32, i32, f64, f64, f64, f64, i32, i32, vp],
         "pfb_fb_step_wavelet": [vp, vp, vp, vp, sz, i32, i32, f64, f64, f64, f64, i32, i32, i32, vp],
+        "pfb_clean": [vp, vp, vp, vp, sz, i32, i32, f64, f64, f64, f64, i32, i32, i32, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

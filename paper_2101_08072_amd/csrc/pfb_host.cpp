@@ -1568,4 +1568,35 @@ pfb_status pfb_fb_step_wavelet(pfb_plan *P, const void *dirty, void *x, void *ws
     return pfb_prox_solve(P, z, x, ws, ws_bytes, nbasis, levels, lambda, gamma, sigma, unorm, pd_iters, warm, s);
 }
 
+pfb_status pfb_clean(pfb_plan *P, const void *dirty, void *x, void *ws, size_t ws_bytes, int nbasis, int levels,
+                     double sigma, double gamma, double lambda, double unorm, int cg_iters, int pd_iters, int n_major,
+                     hipStream_t s) {
+    ProfScope prof_scope(P);
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!dirty || !x || !ws) return fail(PFB_EINVAL, "dirty, x and ws must be non-NULL");
+    if (!P->psf_ready) return fail(PFB_ESTATE, "no PSF spectrum: call pfb_grid with PFB_GRID_PSF first");
+    if ((st = wavelet_args_ok(P, nbasis, levels))) return st;
+    if (!(sigma >= 0) || !(gamma > 0) || cg_iters < 0 || n_major < 0)
+        return fail(PFB_EINVAL, "need sigma >= 0, gamma > 0, cg_iters >= 0, n_major >= 0");
+    const ProxLayout L = prox_layout(P, nbasis);
+    if (ws_bytes < L.total) return fail(PFB_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    const bool d = P->dbl;
+    char *v = reinterpret_cast<char *>(P->p(P->o_vec));
+    void *g = v + 3 * P->vec_bytes, *y = v + 4 * P->vec_bytes;
+    void *z = reinterpret_cast<char *>(ws) + L.z;
+    for (int k = 0; k < n_major; ++k) {
+        // exact gradient (eq. 3): R^dagger Sigma^-1 R x - I^d, one Hessian application
+        if ((st = hessian_impl(P, x, g, s))) return st;
+        LAUNCH_OK(launch_wave_axpy(d, g, dirty, g, L.NP, -1.0, s));
+        // forward step (eq. 6) preconditioned by U = I^psf * + sigma Id, backward step (eq. 7)
+        if ((st = cg_solve(P, g, y, sigma, cg_iters, s))) return st;
+        LAUNCH_OK(launch_wave_axpy(d, x, y, z, L.NP, -gamma, s));
+        if ((st = pfb_prox_solve(P, z, x, ws, ws_bytes, nbasis, levels, lambda, gamma, sigma, unorm, pd_iters, k > 0,
+                                 s)))
+            return st;
+    }
+    return PFB_OK;
+}
+
 }  // extern "C"

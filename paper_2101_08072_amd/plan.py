@@ -281,6 +281,17 @@ class Plan:
                                                 _stream()))
         return x
 
+    def clean(self, dirty: torch.Tensor, x: torch.Tensor, ws: torch.Tensor, sigma: float, gamma: float, lam: float,
+              unorm: float, cg_iters: int, pd_iters: int, n_major: int, nbasis: int = 7,
+              levels: int = 3) -> torch.Tensor:
+        """``n_major`` forward-backward steps with the exact gradient (one Hessian each); x in place."""
+        self._chk(dirty, (self.n_band, self.nx, self.ny), self.real)
+        self._chk(x, (self.n_band, self.nx, self.ny), self.real)
+        _lib.check(self.lib.pfb_clean(self.handle, _ptr(dirty), _ptr(x), _ptr(ws), ws.numel(), int(nbasis),
+                                      int(levels), float(sigma), float(gamma), float(lam), float(unorm),
+                                      int(cg_iters), int(pd_iters), int(n_major), _stream()))
+        return x
+
 
 class FbGraph:
     """An instantiated HIP graph of FB iterations (keeps its plan and buffers alive)."""
