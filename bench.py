@@ -87,7 +87,8 @@ def kernel_models(info, prob, M, W, csz, rsz):
         "spread_run_kernel": ("alu", spread_flops),
         # same algorithmic work, computed as FP32 matrix products on the matrix cores
         "spread_mfma_kernel": ("mfma", spread_flops),
-        "interp_kernel": ("alu", spread_flops),
+        "interp_kernel": ("alu", spread_flops),     # FP64 mode
+        "interp4_kernel": ("alu", spread_flops),    # FP32
         # row inverse DFT of every w-plane: read its occupied tiles (the rest of the
         # plane is zero), write the cropped rows
         "g1_rows_kernel": ("hbm", (info["occ_tiles"] * T * T + nwt * gx * ny) * csz),

@@ -1207,11 +1207,15 @@ static hipError_t spread_run_w(const SpreadLaunch &a, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+// cplx<float> after the LDS ring of the FP32 interpolation (reads of zero-weight columns)
+constexpr int kInterp4Pad = 8;
+
 size_t gridder_lds_bytes(bool dbl, int W, int T, bool flat) {
     const size_t ww = flat ? 1 : (size_t)W;
     const size_t spread = dbl ? 2 * ww * T * T * sizeof(double)
                               : 2 * ww * run_slot_stride(T, flat) * sizeof(unsigned long long);
-    const size_t interp = ww * (size_t)(T + W) * (T + W) * (dbl ? sizeof(cplx<double>) : sizeof(cplx<float>));
+    const size_t interp = (ww * (size_t)(T + W) * (T + W) + (dbl ? 0 : kInterp4Pad)) *
+                          (dbl ? sizeof(cplx<double>) : sizeof(cplx<float>));
     return spread > interp ? spread : interp;
 }
 
@@ -1230,30 +1234,8 @@ hipError_t launch_spread(bool dbl, const SpreadLaunch &a, hipStream_t s) {
 // slides one plane at a time.  Each visibility is computed once, from its home
 // tile; lanes of a group own footprint columns and the partial sums are
 // reduced across the group with lane shuffles.
-// Lane exchange inside groups of 8 lanes (FP32 interpolation) with DPP instead
-// of the LDS crossbar, which the tap reads keep busy; all 8 lanes of a group must
-// be active.  Value of lane I of the group: row_newbcast of lane I (lanes 0-7 of
-// the 16-lane row, banks 0-1; lanes 8-15 left undefined) and of lane 8 + I
-// (lanes 8-15, banks 2-3).
-template <int I> __device__ __forceinline__ float grp8_bcast(float v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + I, 0xf, 0x3, false);
-    return __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x158 + I, 0xf, 0xc, false));
-}
-template <int N, int I = 0> __device__ __forceinline__ void grp8_bcast_all(float v, float *out) {
-    if constexpr (I < N) {
-        out[I] = grp8_bcast<I>(v);
-        grp8_bcast_all<N, I + 1>(v, out);
-    }
-}
-// sum over the group, valid in its lane 0: quad_perm [1,0,3,2], [2,3,0,1], then
-// row_half_mirror (lane i of the 8 takes lane 7 - i) adds the other quad
-__device__ __forceinline__ float grp8_sum(float v) {
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, false));
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4e, 0xf, 0xf, false));
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xf, 0xf, false));
-    return v;
-}
-
+// FP64 mode: `interp_kernel` (LPV lanes per visibility, lane shuffles); FP32:
+// `interp4_kernel` below.
 template <typename R, int W, int LPV, bool FLAT, int OMODE>
 __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
     constexpr int WW = FLAT ? 1 : W;
@@ -1292,74 +1274,36 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
     const int lane = threadIdx.x % LPV;
     const int grp = threadIdx.x / LPV;
     const R beta = (R)a.g.beta, inv_hw = R(2) / R(W), hw = R(0.5) * R(W);
-    const float beta2 = (float)(a.g.beta * 1.4426950408889634);
     const R w0 = (R)bd.w0, dw = (R)bd.dw, sc = (R)bd.sc;
     const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
 
-    R vmax2 = R(0);   // OMODE 1: largest |value|^2 written (scale of the FP32 spread that follows)
     for (int q = wk.q0; q <= wk.q1; ++q) {
         const int64_t lo = max((int64_t)wk.e0, a.hoffsets[keybase + q]);
         const int64_t hi = min((int64_t)wk.e1, a.hoffsets[keybase + q + 1]);
-        // group grp takes entries lo + grp, lo + grp + NGRP, ...: the 8 groups of a
-        // wave read neighbouring footprints (same window), so their LDS reads share
-        // banks and addresses instead of colliding
+        // group grp takes entries lo + grp, lo + grp + NGRP, ...: the groups of a
+        // wave read neighbouring footprints (same window)
         const int64_t n = max(hi - lo, (int64_t)0);
         const int64_t e_end = lo + n;
-        // FP32: the entry index (home list) and record of the next visibility are
-        // loaded while the current one is interpolated (FP64 has no registers to spare)
-        constexpr bool kPrefetch = sizeof(R) == 4;
-        int64_t h = lo + grp;
-        int64_t e_n = 0, e_nn = 0;
-        Rec<R> rec_n{R(0), R(0), R(0), 0u};
-        if constexpr (kPrefetch) {
-            if (h < e_end) {
-                e_n = a.hidx[h];
-                rec_n = recs[e_n];
-            }
-            if (h + NGRP < e_end) e_nn = a.hidx[h + NGRP];
-        }
-        for (; h < e_end; h += NGRP) {
-            int64_t e;                        // entry listed under its own tile
-            Rec<R> rec;
-            if constexpr (kPrefetch) {
-                e = e_n;
-                rec = rec_n;
-                e_n = e_nn;
-                if (h + NGRP < e_end) rec_n = recs[e_n];
-                e_nn = h + 2 * NGRP < e_end ? (int64_t)a.hidx[h + 2 * NGRP] : 0;
-            } else {
-                e = a.hidx[h];
-                rec = recs[e];
-            }
+        for (int64_t h = lo + grp; h < e_end; h += NGRP) {
+            const int64_t e = a.hidx[h];        // entry listed under its own tile
+            const Rec<R> rec = recs[e];
             const int i0 = (int)dev_floor(rec.fu - hw) + 1;
             const int j0 = (int)dev_floor(rec.fv - hw) + 1;
             R pu = R(0), pv = R(0), pw = R(1);
             if (lane < W) {
-                if constexpr (sizeof(R) == 4) {   // hardware exp2 / sqrt
-                    pu = es_kernel_fast(R(i0 + lane) - rec.fu, beta2, inv_hw);
-                    pv = es_kernel_fast(R(j0 + lane) - rec.fv, beta2, inv_hw);
-                    if (!FLAT) pw = es_kernel_fast(R(q + lane) - rec.fw, beta2, inv_hw);
-                } else {
-                    pu = es_kernel<R>(R(i0 + lane) - rec.fu, beta, inv_hw);
-                    pv = es_kernel<R>(R(j0 + lane) - rec.fv, beta, inv_hw);
-                    if (!FLAT) pw = es_kernel<R>(R(q + lane) - rec.fw, beta, inv_hw);
-                }
+                pu = es_kernel<R>(R(i0 + lane) - rec.fu, beta, inv_hw);
+                pv = es_kernel<R>(R(j0 + lane) - rec.fv, beta, inv_hw);
+                if (!FLAT) pw = es_kernel<R>(R(q + lane) - rec.fw, beta, inv_hw);
             }
             R wu[W];
             R ww[WW];
-            if constexpr (sizeof(R) == 4 && LPV == 8) {
-                grp8_bcast_all<W>(pu, wu);
-                if constexpr (FLAT) ww[0] = R(1);
-                else grp8_bcast_all<WW>(pw, ww);
+#pragma unroll
+            for (int i = 0; i < W; ++i) wu[i] = __shfl(pu, i, LPV);
+            if (FLAT) {
+                ww[0] = R(1);
             } else {
 #pragma unroll
-                for (int i = 0; i < W; ++i) wu[i] = __shfl(pu, i, LPV);
-                if (FLAT) {
-                    ww[0] = R(1);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < WW; ++k) ww[k] = __shfl(pw, k, LPV);
-                }
+                for (int k = 0; k < WW; ++k) ww[k] = __shfl(pw, k, LPV);
             }
             cplx<R> acc{R(0), R(0)};
             if (lane < W) {
@@ -1380,17 +1324,157 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
                 acc.re *= pv;
                 acc.im *= pv;
             }
-            if constexpr (sizeof(R) == 4 && LPV == 8) {
-                acc.re = grp8_sum(acc.re);
-                acc.im = grp8_sum(acc.im);
-            } else {
 #pragma unroll
-                for (int off = LPV / 2; off >= 1; off >>= 1) {
-                    acc.re += __shfl_xor(acc.re, off, LPV);
-                    acc.im += __shfl_xor(acc.im, off, LPV);
-                }
+            for (int off = LPV / 2; off >= 1; off >>= 1) {
+                acc.re += __shfl_xor(acc.re, off, LPV);
+                acc.im += __shfl_xor(acc.im, off, LPV);
             }
             if (lane == 0) {
+                const uint32_t vid = rec.idx & ~kHomeBit;
+                if (OMODE == 0) {
+                    cplx<R> out = FLAT ? acc : acc * conj(cis_cycles<R>((w0 + rec.fw * dw) * sc));
+                    reinterpret_cast<cplx<R> *>(a.out)[vid] = out;
+                } else {
+                    const cplx<R> o = acc * omega[e];
+                    reinterpret_cast<cplx<R> *>(a.out)[h] = o;   // home-list order
+                }
+            }
+        }
+        __syncthreads();
+        if (!FLAT && q < wk.q1 && q + W < bd.nw) {
+            load_plane(q + W, q % W);
+        }
+        __syncthreads();
+    }
+}
+
+// FP32 interpolation with 4 lanes per visibility (W <= 8): lane q of a quad owns
+// footprint columns q and q + 4 (the two 8-byte LDS reads merge into one
+// ds_read2_b64; each half reads 32 contiguous bytes per quad, as the 8-lane
+// version reads 64), evaluates those two column weights and its share of the row and
+// plane weights (indices q and q + 4), which quad_perm DPP broadcasts to the quad;
+// a wave interpolates 16 visibilities at a time.  Columns at or beyond W have zero
+// weight; their reads stay inside the ring (the next row, or the zeroed pad after
+// the last one).
+template <int I> __device__ __forceinline__ float quad_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), I * 0x55, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float quad_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4e, 0xf, 0xf, false));
+    return v;
+}
+template <int W, int I = 0> __device__ __forceinline__ void quad_bcast_w(float a, float b, float *out) {
+    if constexpr (I < W) {
+        out[I] = I < 4 ? quad_bcast<I & 3>(a) : quad_bcast<I & 3>(b);
+        quad_bcast_w<W, I + 1>(a, b, out);
+    }
+}
+
+template <int W, bool FLAT, int OMODE>
+__global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
+    using R = float;
+    static_assert(W <= 8, "two columns per lane, four lanes");
+    constexpr int WW = FLAT ? 1 : W;
+    constexpr int NT = kTileThreads;
+    constexpr int NGRP = NT / 4;
+    constexpr int H = (W - 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *ring = reinterpret_cast<cplx<R> *>(smem_raw);
+    const int T = a.g.T, S = T + W, SS = S * S;
+    const InterpWork wk = a.work[blockIdx.x];
+    const BandDev bd = a.bands[wk.band];
+    const int ntiles = a.g.ntx * a.g.nty;
+    const int tu = wk.tile / a.g.nty, tv = wk.tile - tu * a.g.nty;
+    const int bb = wk.band - a.band0;
+    const Rec<R> *recs = reinterpret_cast<const Rec<R> *>(a.recs);
+    const R *omega = reinterpret_cast<const R *>(a.omega);
+    const size_t plane_sz = (size_t)a.g.gx * a.g.gy;
+    const cplx<R> *pbase = reinterpret_cast<const cplx<R> *>(a.planes) + (size_t)bb * a.g.nwmax * plane_sz;
+    const int gx = a.g.gx, gy = a.g.gy;
+    const int ox = tu * T - H, oy = tv * T - H;
+
+    auto load_plane = [&](int p, int slot) {
+        const cplx<R> *P = pbase + (size_t)p * plane_sz;
+        cplx<R> *dst = ring + slot * SS;
+        for (int k = threadIdx.x; k < SS; k += NT) {
+            const int aa = k / S, cc = k - aa * S;
+            const int gi = wrapi(ox + aa, gx), gj = wrapi(oy + cc, gy);
+            dst[k] = P[(size_t)gi * gy + gj];
+        }
+    };
+    if (threadIdx.x < kInterp4Pad) ring[WW * SS + threadIdx.x] = cplx<R>{R(0), R(0)};
+    for (int k = 0; k < WW; ++k)
+        if (wk.q0 + k < (FLAT ? 1 : bd.nw)) load_plane(wk.q0 + k, (wk.q0 + k) % WW);
+    __syncthreads();
+
+    const int lq = threadIdx.x & 3;
+    const int grp = threadIdx.x >> 2;
+    const R inv_hw = R(2) / R(W), hw = R(0.5) * R(W);
+    const float beta2 = (float)(a.g.beta * 1.4426950408889634);
+    const R w0 = (R)bd.w0, dw = (R)bd.dw, sc = (R)bd.sc;
+    const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
+
+    R vmax2 = R(0);   // OMODE 1: largest |value|^2 written (scale of the FP32 spread that follows)
+    for (int q = wk.q0; q <= wk.q1; ++q) {
+        const int64_t lo = max((int64_t)wk.e0, a.hoffsets[keybase + q]);
+        const int64_t hi = min((int64_t)wk.e1, a.hoffsets[keybase + q + 1]);
+        const int64_t n = max(hi - lo, (int64_t)0);
+        const int64_t e_end = lo + n;
+        int64_t h = lo + grp;
+        int64_t e_n = 0, e_nn = 0;
+        Rec<R> rec_n{R(0), R(0), R(0), 0u};
+        if (h < e_end) {
+            e_n = a.hidx[h];
+            rec_n = recs[e_n];
+        }
+        if (h + NGRP < e_end) e_nn = a.hidx[h + NGRP];
+        for (; h < e_end; h += NGRP) {
+            const int64_t e = e_n;
+            const Rec<R> rec = rec_n;
+            e_n = e_nn;
+            if (h + NGRP < e_end) rec_n = recs[e_n];
+            e_nn = h + 2 * NGRP < e_end ? (int64_t)a.hidx[h + 2 * NGRP] : 0;
+            const int i0 = (int)dev_floor(rec.fu - hw) + 1;
+            const int j0 = (int)dev_floor(rec.fv - hw) + 1;
+            const R pv0 = es_kernel_fast(R(j0 + lq) - rec.fv, beta2, inv_hw);
+            const R pv1 = es_kernel_fast(R(j0 + lq + 4) - rec.fv, beta2, inv_hw);
+            const R pua = es_kernel_fast(R(i0 + lq) - rec.fu, beta2, inv_hw);
+            const R pub = es_kernel_fast(R(i0 + lq + 4) - rec.fu, beta2, inv_hw);
+            R wu[W];
+            quad_bcast_w<W>(pua, pub, wu);
+            R ww[WW];
+            if constexpr (FLAT) {
+                ww[0] = R(1);
+            } else {
+                const R pwa = es_kernel_fast(R(q + lq) - rec.fw, beta2, inv_hw);
+                const R pwb = es_kernel_fast(R(q + lq + 4) - rec.fw, beta2, inv_hw);
+                quad_bcast_w<WW>(pwa, pwb, ww);
+            }
+            const int col = j0 + lq + H;
+            cplx<R> A0{R(0), R(0)}, A1{R(0), R(0)};
+#pragma unroll
+            for (int k = 0; k < WW; ++k) {
+                const cplx<R> *base = ring + ((q + k) % WW) * SS + col;
+                cplx<R> a0{R(0), R(0)}, a1{R(0), R(0)};
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    const cplx<R> *row = base + (i0 + i + H) * S;
+                    const cplx<R> g0 = row[0], g1 = row[4];
+                    a0.re += wu[i] * g0.re;
+                    a0.im += wu[i] * g0.im;
+                    a1.re += wu[i] * g1.re;
+                    a1.im += wu[i] * g1.im;
+                }
+                A0.re += ww[k] * a0.re;
+                A0.im += ww[k] * a0.im;
+                A1.re += ww[k] * a1.re;
+                A1.im += ww[k] * a1.im;
+            }
+            cplx<R> acc{pv0 * A0.re + pv1 * A1.re, pv0 * A0.im + pv1 * A1.im};
+            acc.re = quad_sum(acc.re);
+            acc.im = quad_sum(acc.im);
+            if (lq == 0) {
                 const uint32_t vid = rec.idx & ~kHomeBit;
                 if (OMODE == 0) {
                     cplx<R> out = FLAT ? acc : acc * conj(cis_cycles<R>((w0 + rec.fw * dw) * sc));
@@ -1408,7 +1492,7 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
         }
         __syncthreads();
     }
-    if constexpr (sizeof(R) == 4 && OMODE == 1) {
+    if constexpr (OMODE == 1) {
         if (a.absmax) {
             float m = (float)vmax2;
             for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
@@ -1441,7 +1525,23 @@ hipError_t launch_interp(bool dbl, const InterpLaunch &a, hipStream_t s) {
     if (a.n_work <= 0) return hipSuccess;
     if (dbl)
         return dispatch_int<9, 16>(a.g.W, [&](auto Wc) { return interp_w<double, decltype(Wc)::value, 16>(a, s); });
-    return dispatch_int<4, 8>(a.g.W, [&](auto Wc) { return interp_w<float, decltype(Wc)::value, 8>(a, s); });
+    return dispatch_int<4, 8>(a.g.W, [&](auto Wc) {
+        constexpr int W = decltype(Wc)::value;
+        const bool flat = a.g.flat;
+        const int S = a.g.T + W;
+        const size_t lds = ((size_t)(flat ? 1 : W) * S * S + kInterp4Pad) * sizeof(cplx<float>);
+#define INTERP4_CASE(FL, OM)                                                              \
+        if (flat == FL && a.omode == OM) {                                                \
+            PFB_LAUNCH_NT((interp4_kernel<W, FL, OM>), a.n_work, kTileThreads, lds, s, a); \
+            return hipSuccess;                                                            \
+        }
+        INTERP4_CASE(false, 0)
+        INTERP4_CASE(false, 1)
+        INTERP4_CASE(true, 0)
+        INTERP4_CASE(true, 1)
+#undef INTERP4_CASE
+        return hipErrorInvalidValue;
+    });
 }
 
 template <typename R>
