@@ -164,6 +164,20 @@ def test_fp32_tile16(tiny):
     assert rel(host(plan.hessian(to_dev(tiny["xd"], torch.float32))), tiny["hess"]) < TOL["fp32"]
 
 
+@pytest.mark.parametrize("support,tol", [(5, 5e-4), (8, 1e-5)])
+def test_fp32_other_supports(tiny, support, tol):
+    """FP32 path at kernel supports other than the default 7: the interpolation's
+    zero-weight columns (W = 5) and a full eight-column footprint (W = 8).  The
+    tolerance is the ES kernel's own error at that support (about 3x the 1-D
+    figure for the 3-D product), not a kernel error."""
+    import torch
+    plan = make_plan(tiny["prob"], "fp32", support=support)
+    assert plan.info()["support"] == support
+    assert rel(host(plan.degrid(to_dev(tiny["xd"], torch.float32))), tiny["degrid"]) < tol
+    assert rel(host(plan.grid(to_dev(tiny["vis"], torch.complex64))), tiny["dirty"]) < tol
+    assert rel(host(plan.hessian(to_dev(tiny["xd"], torch.float32))), tiny["hess"]) < tol
+
+
 def test_independent_plans_are_bitwise_identical(tiny):
     """The plan-time entry order depends on the inputs only (radix sort on a
     total key), so two plans of one problem grid, degrid and apply the Hessian
