@@ -1417,40 +1417,44 @@ pfb_status wavelet_args_ok(const pfb_plan *P, int nbasis, int levels) {
     return PFB_OK;
 }
 
-// coef_k (k >= 1) = W_k^dagger src for every band, unscaled; uses buffer a
-pfb_status analysis_bases(const pfb_plan *P, const void *src, char *coef, void *a, int nbasis, int levels,
+// coef_k (k >= 1) = W_k^dagger src for every band, unscaled; the low-pass block
+// of every level but the last goes to buffer a or b (alternately)
+pfb_status analysis_bases(const pfb_plan *P, const void *src, char *coef, void *a, void *b, int nbasis, int levels,
                           hipStream_t s) {
     const bool d = P->dbl;
     const int nx = P->prob.nx, ny = P->prob.ny, nb = P->prob.n_band;
     const int64_t Pn = (int64_t)nx * ny;
     const size_t img = (size_t)nb * Pn * P->rsz;
+    void *pp[2] = {a, b};
     for (int k = 1; k < nbasis; ++k) {
         const WaveletFilter f = db_filter(k);
         void *ck = coef + (size_t)(k - 1) * img;
         for (int l = 0; l < levels; ++l) {
-            const int bx = nx >> l, by = ny >> l;
-            LAUNCH_OK(launch_wavelet_pass(d, false, 1, false, l == 0 ? src : ck, a, f, by, bx, ny, Pn, nb, s));
-            LAUNCH_OK(launch_wavelet_pass(d, false, 0, false, a, ck, f, bx, by, ny, Pn, nb, s));
+            const void *in = l == 0 ? src : pp[(l - 1) & 1];
+            void *ll = l == levels - 1 ? ck : pp[l & 1];
+            LAUNCH_OK(launch_wavelet_analysis_level(d, in, ck, ll, f, nx >> l, ny >> l, ny, Pn, nb, s));
         }
     }
     return PFB_OK;
 }
 
-// out = v_0 + sum_{k >= 1} W_k v_k (unscaled); uses buffers a and b
+// out = v_0 + sum_{k >= 1} W_k v_k (unscaled); the low-pass block of every level
+// but the finest goes to buffer a or b (alternately)
 pfb_status synthesis_bases(const pfb_plan *P, const char *v, void *out, void *a, void *b, int nbasis, int levels,
                            hipStream_t s) {
     const bool d = P->dbl;
     const int nx = P->prob.nx, ny = P->prob.ny, nb = P->prob.n_band;
     const int64_t Pn = (int64_t)nx * ny;
     const size_t img = (size_t)nb * Pn * P->rsz;
+    void *pp[2] = {a, b};
     LAUNCH_OK(launch_wave_copy(d, v, out, (int64_t)nb * Pn, 1.0, s));
     for (int k = 1; k < nbasis; ++k) {
         const WaveletFilter f = db_filter(k);
-        LAUNCH_OK(launch_wave_copy(d, v + (size_t)k * img, a, (int64_t)nb * Pn, 1.0, s));
+        const void *vk = v + (size_t)k * img;
         for (int l = levels - 1; l >= 0; --l) {
-            const int bx = nx >> l, by = ny >> l;
-            LAUNCH_OK(launch_wavelet_pass(d, true, 0, false, a, b, f, bx, by, ny, Pn, nb, s));
-            LAUNCH_OK(launch_wavelet_pass(d, true, 1, l == 0, b, l == 0 ? out : a, f, by, bx, ny, Pn, nb, s));
+            const void *ll = l == levels - 1 ? vk : pp[(l + 1) & 1];
+            void *dst = l == 0 ? out : pp[l & 1];
+            LAUNCH_OK(launch_wavelet_synthesis_level(d, l == 0, ll, vk, dst, f, nx >> l, ny >> l, ny, Pn, nb, s));
         }
     }
     return PFB_OK;
@@ -1482,7 +1486,7 @@ pfb_status pfb_wavelet_analysis(pfb_plan *P, const void *x, void *coeffs, void *
     char *w = reinterpret_cast<char *>(ws);
     const size_t img = (size_t)L.NP * P->rsz;
     LAUNCH_OK(launch_wave_copy(d, x, c, L.NP, scale, s));
-    if ((st = analysis_bases(P, x, c + img, w + L.a, nbasis, levels, s))) return st;
+    if ((st = analysis_bases(P, x, c + img, w + L.a, w + L.b, nbasis, levels, s))) return st;
     if (nbasis > 1) LAUNCH_OK(launch_wave_copy(d, c + img, c + img, (int64_t)(nbasis - 1) * L.NP, scale, s));
     return PFB_OK;
 }
@@ -1535,7 +1539,7 @@ pfb_status pfb_prox_solve(pfb_plan *P, const void *z, void *x, void *ws, size_t 
         if ((st = synthesis_bases(P, reinterpret_cast<const char *>(v), sv, w + L.a, w + L.b, nbasis, levels, s)))
             return st;
         LAUNCH_OK(launch_pd_primal(d, false, z, x, dd, c, sv, u, L.NP, tau, gamma, sigma, psi_scale, warm, s));
-        if ((st = analysis_bases(P, u, reinterpret_cast<char *>(coef), w + L.a, nbasis, levels, s))) return st;
+        if ((st = analysis_bases(P, u, reinterpret_cast<char *>(coef), w + L.a, w + L.b, nbasis, levels, s))) return st;
         LAUNCH_OK(launch_pd_dual(d, false, v, u, coef, nbasis, P->prob.n_band, (int64_t)P->prob.nx * P->prob.ny,
                                  sigma_d, psi_scale, lambda, s));
     }

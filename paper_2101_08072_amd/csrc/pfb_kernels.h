@@ -191,12 +191,16 @@ struct WaveletFilter {
     double h[kMaxWaveletTaps];
     int len;
 };
-// One wavelet level along `axis` (1: contiguous, 0: strided) of the top-left
-// n x other (axis 1: other x n) block of n_img images `img` elements apart, rows
-// `ld` apart; inv: synthesis (the adjoint), acc: add into dst.
-hipError_t launch_wavelet_pass(bool dbl, bool inv, int axis, bool acc, const void *src, void *dst,
-                               const WaveletFilter &f, int n, int other, int ld, int64_t img, int n_img,
-                               hipStream_t s);
+// One 2-D wavelet level (rows then columns) of the top-left nr x nc block in LDS
+// tiles: analysis writes LL to dst_ll and the three detail quadrants to
+// dst_detail; synthesis reads LL from src_ll and the details from src_detail
+// (acc: add into dst).  Source and destinations must not overlap.
+hipError_t launch_wavelet_analysis_level(bool dbl, const void *src, void *dst_detail, void *dst_ll,
+                                         const WaveletFilter &f, int nr, int nc, int ld, int64_t img, int n_img,
+                                         hipStream_t s);
+hipError_t launch_wavelet_synthesis_level(bool dbl, bool acc, const void *src_ll, const void *src_detail, void *dst,
+                                          const WaveletFilter &f, int nr, int nc, int ld, int64_t img, int n_img,
+                                          hipStream_t s);
 hipError_t launch_wave_copy(bool dbl, const void *src, void *dst, int64_t n, double scale, hipStream_t s);
 hipError_t launch_wave_axpy(bool dbl, const void *x, const void *y, void *z, int64_t n, double a, hipStream_t s);   // z = x + a y
 hipError_t launch_pd_primal(bool dbl, bool init, const void *z, void *x, void *d, const void *c, const void *sv,

@@ -1207,14 +1207,16 @@ static hipError_t spread_run_w(const SpreadLaunch &a, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-// cplx<float> after the LDS ring of the FP32 interpolation (reads of zero-weight columns)
+// cplx<float> after the LDS ring of the FP32 interpolation (reads of zero-weight
+// columns), and zero columns after each ring row (row stride T + W + kInterp4ColPad)
 constexpr int kInterp4Pad = 8;
+constexpr int kInterp4ColPad = 1;
 
 size_t gridder_lds_bytes(bool dbl, int W, int T, bool flat) {
     const size_t ww = flat ? 1 : (size_t)W;
     const size_t spread = dbl ? 2 * ww * T * T * sizeof(double)
                               : 2 * ww * run_slot_stride(T, flat) * sizeof(unsigned long long);
-    const size_t interp = (ww * (size_t)(T + W) * (T + W) + (dbl ? 0 : kInterp4Pad)) *
+    const size_t interp = (ww * (size_t)(T + W) * (T + W + (dbl ? 0 : kInterp4ColPad)) + (dbl ? 0 : kInterp4Pad)) *
                           (dbl ? sizeof(cplx<double>) : sizeof(cplx<float>));
     return spread > interp ? spread : interp;
 }
@@ -1381,7 +1383,8 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
     constexpr int H = (W - 1) / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *ring = reinterpret_cast<cplx<R> *>(smem_raw);
-    const int T = a.g.T, S = T + W, SS = S * S;
+    // ring rows hold the E = T + W halo columns, kInterp4ColPad zero columns after them
+    const int T = a.g.T, E = T + W, S = E + kInterp4ColPad, SS = E * S;
     const InterpWork wk = a.work[blockIdx.x];
     const BandDev bd = a.bands[wk.band];
     const int ntiles = a.g.ntx * a.g.nty;
@@ -1397,13 +1400,18 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
     auto load_plane = [&](int p, int slot) {
         const cplx<R> *P = pbase + (size_t)p * plane_sz;
         cplx<R> *dst = ring + slot * SS;
-        for (int k = threadIdx.x; k < SS; k += NT) {
-            const int aa = k / S, cc = k - aa * S;
+        for (int k = threadIdx.x; k < E * E; k += NT) {
+            const int aa = k / E, cc = k - aa * E;
             const int gi = wrapi(ox + aa, gx), gj = wrapi(oy + cc, gy);
-            dst[k] = P[(size_t)gi * gy + gj];
+            dst[aa * S + cc] = P[(size_t)gi * gy + gj];
         }
     };
     if (threadIdx.x < kInterp4Pad) ring[WW * SS + threadIdx.x] = cplx<R>{R(0), R(0)};
+    if constexpr (kInterp4ColPad > 0)
+        for (int k = threadIdx.x; k < WW * E * kInterp4ColPad; k += NT) {
+            const int r = k / kInterp4ColPad, c = k - r * kInterp4ColPad;
+            ring[r * S + E + c] = cplx<R>{R(0), R(0)};
+        }
     for (int k = 0; k < WW; ++k)
         if (wk.q0 + k < (FLAT ? 1 : bd.nw)) load_plane(wk.q0 + k, (wk.q0 + k) % WW);
     __syncthreads();
@@ -1529,7 +1537,7 @@ hipError_t launch_interp(bool dbl, const InterpLaunch &a, hipStream_t s) {
         constexpr int W = decltype(Wc)::value;
         const bool flat = a.g.flat;
         const int S = a.g.T + W;
-        const size_t lds = ((size_t)(flat ? 1 : W) * S * S + kInterp4Pad) * sizeof(cplx<float>);
+        const size_t lds = ((size_t)(flat ? 1 : W) * S * (S + kInterp4ColPad) + kInterp4Pad) * sizeof(cplx<float>);
 #define INTERP4_CASE(FL, OM)                                                              \
         if (flat == FL && a.omode == OM) {                                                \
             PFB_LAUNCH_NT((interp4_kernel<W, FL, OM>), a.n_work, kTileThreads, lds, s, a); \
@@ -2538,110 +2546,172 @@ hipError_t launch_copy_scalar(int n_band, const double *scal, int slot, double *
 // backward step (eq. 7 with the regulariser of eq. 9): wavelet dictionary and
 // primal-dual updates
 // ---------------------------------------------------------------------------
-// One periodic wavelet level along one axis of a block of images.  The block is
-// rows x n (AXIS 1: along the contiguous axis) or n x cols (AXIS 0: along the
-// strided axis) at the top-left of every image; images are `img` elements apart,
-// rows `ld` apart.  N: vanishing moments (2N taps).  A thread owns coefficient
-// pair k < n/2.  Analysis (INV false): low[k] = sum_j h[j] x[(2k + j) mod n],
-// high[k] = sum_j g[j] x[(2k + j) mod n], g[j] = (-1)^j h[2N-1-j], stored as
-// [low | high].  Synthesis (INV true): the adjoint, x[2k + e] = sum_i h[2i + e]
-// low[(k - i) mod n/2] + g[2i + e] high[(k - i) mod n/2] for e = 0, 1; ACC adds the
-// result to dst instead of storing it.
+// Taps of one wavelet filter pair in the kernel's precision: low-pass h and
+// wavelet g[j] = (-1)^j h[2N-1-j].
 template <typename R> struct WaveletTaps {
     R h[kMaxWaveletTaps], g[kMaxWaveletTaps];
 };
-template <typename R, int N, bool INV, int AXIS, bool ACC>
-__global__ __launch_bounds__(kThreads) void wavelet_pass_kernel(const R *src, R *dst, WaveletTaps<R> f, int n,
-                                                                int other, int ld, int64_t img) {
-    // grid: x over the contiguous index (k for AXIS 1, o for AXIS 0), y over the
-    // other index, z over the images
-    const int half = n >> 1;
-    const int c = blockIdx.x * kThreads + threadIdx.x;
-    const int k = AXIS == 1 ? c : (int)blockIdx.y;
-    const int o = AXIS == 1 ? (int)blockIdx.y : c;
-    if (c >= (AXIS == 1 ? half : other)) return;
-    const R *sp = src + (size_t)blockIdx.z * img;
-    R *dp = dst + (size_t)blockIdx.z * img;
-    auto idx = [&](int i) -> size_t { return AXIS == 1 ? (size_t)o * ld + i : (size_t)i * ld + o; };
-    if (!INV) {
-        R lo = R(0), hi = R(0);
-        int i = 2 * k;
-#pragma unroll
-        for (int j = 0; j < 2 * N; ++j) {
-            const R x = sp[idx(i)];
-            lo += f.h[j] * x;
-            hi += f.g[j] * x;
-            if (++i == n) i = 0;
-        }
-        dp[idx(k)] = lo;
-        dp[idx(half + k)] = hi;
-    } else {
-        R x0 = R(0), x1 = R(0);
-        int t = k;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const R a = sp[idx(t)], d = sp[idx(half + t)];
-            x0 += f.h[2 * i] * a + f.g[2 * i] * d;
-            x1 += f.h[2 * i + 1] * a + f.g[2 * i + 1] * d;
-            if (--t < 0) t += half;
-        }
-        if (ACC) {
-            dp[idx(2 * k)] += x0;
-            dp[idx(2 * k + 1)] += x1;
-        } else {
-            dp[idx(2 * k)] = x0;
-            dp[idx(2 * k + 1)] = x1;
-        }
-    }
-}
-
 static int64_t wave_blocks(int64_t total) {
     int64_t nb = (total + kThreads - 1) / kThreads;
     return nb < 1 ? 1 : (nb > 65536 ? 65536 : nb);
 }
 
+// One whole 2-D level per launch, in LDS tiles (rows pass, then columns pass,
+// the order of the level's definition), so a level reads its block once (plus a
+// halo of 2N - 2) and writes it once.  Analysis: a workgroup makes the four
+// coefficients (LL, LH, HL, HH) of kWaveTileR x kWaveTileC coefficient positions; LL goes
+// to dst_ll (the next level's input, or the coefficient array after the last
+// level), the details to dst_d at the level's quadrant positions.  Synthesis: a
+// workgroup makes 2 kWaveTileR x 2 kWaveTileC samples from the LL block (src_ll) and the
+// three detail quadrants (src_d), columns pass then rows pass (the adjoint order);
+// ACC adds into dst.  Rows `ld` apart, images `img` apart, periodic boundaries.
+constexpr int kWaveTileR = 16, kWaveTileC = 32;
 template <typename R, int N>
-static hipError_t wavelet_pass_n(bool inv, int axis, bool acc, const R *sp, R *dp, const WaveletTaps<R> &f, int n,
-                                 int other, int ld, int64_t img, int n_img, hipStream_t s) {
-    const int contig = axis == 1 ? n / 2 : other, strided = axis == 1 ? other : n / 2;
-    if (strided > 65535 || n_img > 65535 || n < 2 || (n & 1)) return hipErrorInvalidValue;
-    const dim3 grid((contig + kThreads - 1) / kThreads, strided, n_img);
-#define WPASS(I, X, C)                                                                           \
-    if (inv == I && axis == X && acc == C) {                                                     \
-        PFB_LAUNCH((wavelet_pass_kernel<R, N, I, X, C>), grid, 0, s, sp, dp, f, n, other, ld, img); \
-        return hipSuccess;                                                                       \
+__global__ __launch_bounds__(kThreads) void wavelet_ana2_kernel(const R *src, R *dst_d, R *dst_ll, WaveletTaps<R> f,
+                                                                int nr, int nc, int ld, int64_t img) {
+    constexpr int TR = kWaveTileR, TC = kWaveTileC;
+    constexpr int IR = 2 * TR + 2 * N - 2, IC = 2 * TC + 2 * N - 2;
+    __shared__ R xin[IR][IC + 1];
+    __shared__ R trow[IR][2 * TC + 1];
+    const int hr = nr >> 1, hc = nc >> 1;
+    const int kr0 = blockIdx.y * TR, kc0 = blockIdx.x * TC;
+    const R *sp = src + (size_t)blockIdx.z * img;
+    for (int id = threadIdx.x; id < IR * IC; id += kThreads) {
+        const int r = id / IC, c = id - r * IC;
+        const int gr = (2 * kr0 + r) % nr, gc = (2 * kc0 + c) % nc;
+        xin[r][c] = sp[(size_t)gr * ld + gc];
     }
-    WPASS(false, 1, false)
-    WPASS(false, 0, false)
-    WPASS(true, 0, false)
-    WPASS(true, 1, false)
-    WPASS(true, 1, true)
-#undef WPASS
-    return hipErrorInvalidValue;
+    __syncthreads();
+    for (int id = threadIdx.x; id < IR * TC; id += kThreads) {
+        const int r = id / TC, k = id - r * TC;
+        R lo = R(0), hi = R(0);
+#pragma unroll
+        for (int j = 0; j < 2 * N; ++j) {
+            const R x = xin[r][2 * k + j];
+            lo += f.h[j] * x;
+            hi += f.g[j] * x;
+        }
+        trow[r][k] = lo;
+        trow[r][TC + k] = hi;
+    }
+    __syncthreads();
+    R *dd = dst_d + (size_t)blockIdx.z * img;
+    R *dl = dst_ll + (size_t)blockIdx.z * img;
+    for (int id = threadIdx.x; id < TR * 2 * TC; id += kThreads) {
+        const int kr = id / (2 * TC), c = id - kr * (2 * TC);
+        const bool chi = c >= TC;
+        const int kc = chi ? c - TC : c;
+        if (kr0 + kr >= hr || kc0 + kc >= hc) continue;
+        R lo = R(0), hi = R(0);
+#pragma unroll
+        for (int j = 0; j < 2 * N; ++j) {
+            const R t = trow[2 * kr + j][c];
+            lo += f.h[j] * t;
+            hi += f.g[j] * t;
+        }
+        const int col = (chi ? hc : 0) + kc0 + kc;
+        if (chi) dd[(size_t)(kr0 + kr) * ld + col] = lo;
+        else dl[(size_t)(kr0 + kr) * ld + col] = lo;
+        dd[(size_t)(hr + kr0 + kr) * ld + col] = hi;
+    }
+}
+
+template <typename R, int N, bool ACC>
+__global__ __launch_bounds__(kThreads) void wavelet_syn2_kernel(const R *src_ll, const R *src_d, R *dst,
+                                                                WaveletTaps<R> f, int nr, int nc, int ld, int64_t img) {
+    constexpr int TR = kWaveTileR, TC = kWaveTileC;
+    constexpr int YR = TR + N - 1, YC = TC + N - 1;   // coefficient rows / columns per half
+    __shared__ R yin[2 * YR][2 * YC + 1];
+    __shared__ R tcol[2 * TR][2 * YC + 1];
+    const int hr = nr >> 1, hc = nc >> 1;
+    const int kr0 = blockIdx.y * TR, kc0 = blockIdx.x * TC;
+    const R *sl = src_ll + (size_t)blockIdx.z * img;
+    const R *sd = src_d + (size_t)blockIdx.z * img;
+    for (int id = threadIdx.x; id < 4 * YR * YC; id += kThreads) {
+        const int a = id / (2 * YC), b = id - a * (2 * YC);
+        const bool rhi = a >= YR, chi = b >= YC;
+        int pr = (rhi ? a - YR : a) + kr0 - (N - 1), pc = (chi ? b - YC : b) + kc0 - (N - 1);
+        while (pr < 0) pr += hr;
+        while (pc < 0) pc += hc;
+        pr %= hr;
+        pc %= hc;
+        const size_t off = (size_t)((rhi ? hr : 0) + pr) * ld + (chi ? hc : 0) + pc;
+        yin[a][b] = (!rhi && !chi) ? sl[off] : sd[off];
+    }
+    __syncthreads();
+    // columns: sample rows 2p + e of the tile from coefficient rows p - i, i < N
+    for (int id = threadIdx.x; id < 2 * TR * 2 * YC; id += kThreads) {
+        const int mr = id / (2 * YC), b = id - mr * (2 * YC);
+        const int p = mr >> 1, e = mr & 1;
+        R acc = R(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc += f.h[2 * i + e] * yin[p + N - 1 - i][b] + f.g[2 * i + e] * yin[YR + p + N - 1 - i][b];
+        tcol[mr][b] = acc;
+    }
+    __syncthreads();
+    R *dp = dst + (size_t)blockIdx.z * img;
+    for (int id = threadIdx.x; id < 2 * TR * 2 * TC; id += kThreads) {
+        const int mr = id / (2 * TC), mc = id - mr * (2 * TC);
+        const int q = mc >> 1, e = mc & 1;
+        if (kr0 + (mr >> 1) >= hr || kc0 + q >= hc) continue;
+        R acc = R(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc += f.h[2 * i + e] * tcol[mr][q + N - 1 - i] + f.g[2 * i + e] * tcol[mr][YC + q + N - 1 - i];
+        R *o = dp + (size_t)(2 * kr0 + mr) * ld + 2 * kc0 + mc;
+        if (ACC) *o += acc;
+        else *o = acc;
+    }
 }
 
 template <typename R>
-static hipError_t wavelet_pass_t(bool inv, int axis, bool acc, const void *src, void *dst, const WaveletFilter &f,
-                                 int n, int other, int ld, int64_t img, int n_img, hipStream_t s) {
+static WaveletTaps<R> make_taps(const WaveletFilter &f) {
     WaveletTaps<R> t{};
     const int L = f.len;
-    if (L < 2 || L > kMaxWaveletTaps || (L & 1)) return hipErrorInvalidValue;
     for (int j = 0; j < L; ++j) {
         t.h[j] = (R)f.h[j];
         t.g[j] = (R)((j & 1) ? -f.h[L - 1 - j] : f.h[L - 1 - j]);
     }
-    const R *sp = reinterpret_cast<const R *>(src);
-    R *dp = reinterpret_cast<R *>(dst);
-    return dispatch_int<1, 6>(L / 2, [&](auto Nc) {
-        return wavelet_pass_n<R, decltype(Nc)::value>(inv, axis, acc, sp, dp, t, n, other, ld, img, n_img, s);
+    return t;
+}
+
+template <typename R>
+static hipError_t wavelet_level_t(bool inv, bool acc, const void *a_src, const void *b_src, void *a_dst, void *b_dst,
+                                  const WaveletFilter &f, int nr, int nc, int ld, int64_t img, int n_img,
+                                  hipStream_t s) {
+    const int L = f.len;
+    if (L < 2 || L > kMaxWaveletTaps || (L & 1) || nr < 2 || nc < 2 || (nr & 1) || (nc & 1) || n_img > 65535)
+        return hipErrorInvalidValue;
+    const WaveletTaps<R> t = make_taps<R>(f);
+    const dim3 grid((nc / 2 + kWaveTileC - 1) / kWaveTileC, (nr / 2 + kWaveTileR - 1) / kWaveTileR, n_img);
+    if (grid.y > 65535) return hipErrorInvalidValue;
+    return dispatch_int<1, 6>(L / 2, [&](auto Nc) -> hipError_t {
+        constexpr int N = decltype(Nc)::value;
+        if (!inv) {
+            PFB_LAUNCH((wavelet_ana2_kernel<R, N>), grid, 0, s, (const R *)a_src, (R *)a_dst, (R *)b_dst, t, nr, nc,
+                       ld, img);
+        } else if (acc) {
+            PFB_LAUNCH((wavelet_syn2_kernel<R, N, true>), grid, 0, s, (const R *)a_src, (const R *)b_src, (R *)a_dst,
+                       t, nr, nc, ld, img);
+        } else {
+            PFB_LAUNCH((wavelet_syn2_kernel<R, N, false>), grid, 0, s, (const R *)a_src, (const R *)b_src, (R *)a_dst,
+                       t, nr, nc, ld, img);
+        }
+        return hipSuccess;
     });
 }
 
-hipError_t launch_wavelet_pass(bool dbl, bool inv, int axis, bool acc, const void *src, void *dst,
-                               const WaveletFilter &f, int n, int other, int ld, int64_t img, int n_img,
-                               hipStream_t s) {
-    if (dbl) return wavelet_pass_t<double>(inv, axis, acc, src, dst, f, n, other, ld, img, n_img, s);
-    return wavelet_pass_t<float>(inv, axis, acc, src, dst, f, n, other, ld, img, n_img, s);
+hipError_t launch_wavelet_analysis_level(bool dbl, const void *src, void *dst_detail, void *dst_ll,
+                                         const WaveletFilter &f, int nr, int nc, int ld, int64_t img, int n_img,
+                                         hipStream_t s) {
+    if (dbl) return wavelet_level_t<double>(false, false, src, nullptr, dst_detail, dst_ll, f, nr, nc, ld, img, n_img, s);
+    return wavelet_level_t<float>(false, false, src, nullptr, dst_detail, dst_ll, f, nr, nc, ld, img, n_img, s);
+}
+
+hipError_t launch_wavelet_synthesis_level(bool dbl, bool acc, const void *src_ll, const void *src_detail, void *dst,
+                                          const WaveletFilter &f, int nr, int nc, int ld, int64_t img, int n_img,
+                                          hipStream_t s) {
+    if (dbl) return wavelet_level_t<double>(true, acc, src_ll, src_detail, dst, nullptr, f, nr, nc, ld, img, n_img, s);
+    return wavelet_level_t<float>(true, acc, src_ll, src_detail, dst, nullptr, f, nr, nc, ld, img, n_img, s);
 }
 
 template <typename R>
