@@ -2576,43 +2576,66 @@ __global__ __launch_bounds__(kThreads) void wavelet_ana2_kernel(const R *src, R 
     const int hr = nr >> 1, hc = nc >> 1;
     const int kr0 = blockIdx.y * TR, kc0 = blockIdx.x * TC;
     const R *sp = src + (size_t)blockIdx.z * img;
+    // the tile wraps round the block only at its far edges (periodic boundaries)
+    const bool wrap = 2 * kr0 + IR > nr || 2 * kc0 + IC > nc;
     for (int id = threadIdx.x; id < IR * IC; id += kThreads) {
         const int r = id / IC, c = id - r * IC;
-        const int gr = (2 * kr0 + r) % nr, gc = (2 * kc0 + c) % nc;
+        int gr = 2 * kr0 + r, gc = 2 * kc0 + c;
+        if (wrap) {
+            gr %= nr;
+            gc %= nc;
+        }
         xin[r][c] = sp[(size_t)gr * ld + gc];
     }
     __syncthreads();
-    for (int id = threadIdx.x; id < IR * TC; id += kThreads) {
-        const int r = id / TC, k = id - r * TC;
-        R lo = R(0), hi = R(0);
+    // rows: a thread makes KB consecutive (low, high) pairs from one window of
+    // 2N + 2KB - 2 samples held in registers
+    constexpr int KB = 4, WIN = 2 * N + 2 * KB - 2;
+    for (int id = threadIdx.x; id < IR * (TC / KB); id += kThreads) {
+        const int r = id / (TC / KB), k0 = (id - r * (TC / KB)) * KB;
+        R x[WIN];
 #pragma unroll
-        for (int j = 0; j < 2 * N; ++j) {
-            const R x = xin[r][2 * k + j];
-            lo += f.h[j] * x;
-            hi += f.g[j] * x;
+        for (int t = 0; t < WIN; ++t) x[t] = xin[r][2 * k0 + t];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            R lo = R(0), hi = R(0);
+#pragma unroll
+            for (int j = 0; j < 2 * N; ++j) {
+                lo += f.h[j] * x[2 * u + j];
+                hi += f.g[j] * x[2 * u + j];
+            }
+            trow[r][k0 + u] = lo;
+            trow[r][TC + k0 + u] = hi;
         }
-        trow[r][k] = lo;
-        trow[r][TC + k] = hi;
     }
     __syncthreads();
     R *dd = dst_d + (size_t)blockIdx.z * img;
     R *dl = dst_ll + (size_t)blockIdx.z * img;
-    for (int id = threadIdx.x; id < TR * 2 * TC; id += kThreads) {
-        const int kr = id / (2 * TC), c = id - kr * (2 * TC);
+    // columns: KB consecutive coefficient rows per thread, as above
+    for (int id = threadIdx.x; id < (TR / KB) * 2 * TC; id += kThreads) {
+        const int kb = id / (2 * TC), c = id - kb * (2 * TC);
+        const int kr0b = kb * KB;
         const bool chi = c >= TC;
         const int kc = chi ? c - TC : c;
-        if (kr0 + kr >= hr || kc0 + kc >= hc) continue;
-        R lo = R(0), hi = R(0);
+        if (kc0 + kc >= hc) continue;
+        R t[WIN];
 #pragma unroll
-        for (int j = 0; j < 2 * N; ++j) {
-            const R t = trow[2 * kr + j][c];
-            lo += f.h[j] * t;
-            hi += f.g[j] * t;
-        }
+        for (int v = 0; v < WIN; ++v) t[v] = trow[2 * kr0b + v][c];
         const int col = (chi ? hc : 0) + kc0 + kc;
-        if (chi) dd[(size_t)(kr0 + kr) * ld + col] = lo;
-        else dl[(size_t)(kr0 + kr) * ld + col] = lo;
-        dd[(size_t)(hr + kr0 + kr) * ld + col] = hi;
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int kr = kr0b + u;
+            if (kr0 + kr >= hr) break;
+            R lo = R(0), hi = R(0);
+#pragma unroll
+            for (int j = 0; j < 2 * N; ++j) {
+                lo += f.h[j] * t[2 * u + j];
+                hi += f.g[j] * t[2 * u + j];
+            }
+            if (chi) dd[(size_t)(kr0 + kr) * ld + col] = lo;
+            else dl[(size_t)(kr0 + kr) * ld + col] = lo;
+            dd[(size_t)(hr + kr0 + kr) * ld + col] = hi;
+        }
     }
 }
 
@@ -2627,39 +2650,71 @@ __global__ __launch_bounds__(kThreads) void wavelet_syn2_kernel(const R *src_ll,
     const int kr0 = blockIdx.y * TR, kc0 = blockIdx.x * TC;
     const R *sl = src_ll + (size_t)blockIdx.z * img;
     const R *sd = src_d + (size_t)blockIdx.z * img;
+    // the coefficient window wraps only at the block's edges (periodic boundaries)
+    const bool wrap = kr0 < N - 1 || kc0 < N - 1 || kr0 + YR - (N - 1) > hr || kc0 + YC - (N - 1) > hc;
     for (int id = threadIdx.x; id < 4 * YR * YC; id += kThreads) {
         const int a = id / (2 * YC), b = id - a * (2 * YC);
         const bool rhi = a >= YR, chi = b >= YC;
         int pr = (rhi ? a - YR : a) + kr0 - (N - 1), pc = (chi ? b - YC : b) + kc0 - (N - 1);
-        while (pr < 0) pr += hr;
-        while (pc < 0) pc += hc;
-        pr %= hr;
-        pc %= hc;
+        if (wrap) {
+            while (pr < 0) pr += hr;
+            while (pc < 0) pc += hc;
+            pr %= hr;
+            pc %= hc;
+        }
         const size_t off = (size_t)((rhi ? hr : 0) + pr) * ld + (chi ? hc : 0) + pc;
         yin[a][b] = (!rhi && !chi) ? sl[off] : sd[off];
     }
     __syncthreads();
-    // columns: sample rows 2p + e of the tile from coefficient rows p - i, i < N
-    for (int id = threadIdx.x; id < 2 * TR * 2 * YC; id += kThreads) {
-        const int mr = id / (2 * YC), b = id - mr * (2 * YC);
-        const int p = mr >> 1, e = mr & 1;
-        R acc = R(0);
+    // columns: sample rows 2p + e of the tile from coefficient rows p - i, i < N;
+    // a thread makes PB consecutive p (both e) from PB + N - 1 low and high rows
+    constexpr int PB = 4, PW = PB + N - 1;
+    for (int id = threadIdx.x; id < (TR / PB) * 2 * YC; id += kThreads) {
+        const int pb = id / (2 * YC), b = id - pb * (2 * YC);
+        const int p0 = pb * PB;
+        R lo[PW], hi[PW];
 #pragma unroll
-        for (int i = 0; i < N; ++i) acc += f.h[2 * i + e] * yin[p + N - 1 - i][b] + f.g[2 * i + e] * yin[YR + p + N - 1 - i][b];
-        tcol[mr][b] = acc;
+        for (int t = 0; t < PW; ++t) {
+            lo[t] = yin[p0 + t][b];
+            hi[t] = yin[YR + p0 + t][b];
+        }
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                R acc = R(0);
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc += f.h[2 * i + e] * lo[u + N - 1 - i] + f.g[2 * i + e] * hi[u + N - 1 - i];
+                tcol[2 * (p0 + u) + e][b] = acc;
+            }
+        }
     }
     __syncthreads();
     R *dp = dst + (size_t)blockIdx.z * img;
-    for (int id = threadIdx.x; id < 2 * TR * 2 * TC; id += kThreads) {
-        const int mr = id / (2 * TC), mc = id - mr * (2 * TC);
-        const int q = mc >> 1, e = mc & 1;
-        if (kr0 + (mr >> 1) >= hr || kc0 + q >= hc) continue;
-        R acc = R(0);
+    // rows: PB consecutive q (both e) per thread, as above
+    for (int id = threadIdx.x; id < 2 * TR * (TC / PB); id += kThreads) {
+        const int mr = id / (TC / PB), q0 = (id - mr * (TC / PB)) * PB;
+        if (kr0 + (mr >> 1) >= hr) continue;
+        R lo[PW], hi[PW];
 #pragma unroll
-        for (int i = 0; i < N; ++i) acc += f.h[2 * i + e] * tcol[mr][q + N - 1 - i] + f.g[2 * i + e] * tcol[mr][YC + q + N - 1 - i];
-        R *o = dp + (size_t)(2 * kr0 + mr) * ld + 2 * kc0 + mc;
-        if (ACC) *o += acc;
-        else *o = acc;
+        for (int t = 0; t < PW; ++t) {
+            lo[t] = tcol[mr][q0 + t];
+            hi[t] = tcol[mr][YC + q0 + t];
+        }
+        R *orow = dp + (size_t)(2 * kr0 + mr) * ld + 2 * kc0;
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            if (kc0 + q0 + u >= hc) break;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                R acc = R(0);
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc += f.h[2 * i + e] * lo[u + N - 1 - i] + f.g[2 * i + e] * hi[u + N - 1 - i];
+                R *o = orow + 2 * (q0 + u) + e;
+                if (ACC) *o += acc;
+                else *o = acc;
+            }
+        }
     }
 }
 
