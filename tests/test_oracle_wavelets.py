@@ -18,6 +18,10 @@ def test_haar_and_db2_closed_forms():
     r3 = math.sqrt(3.0)
     db2 = np.array([1 + r3, 3 + r3, 3 - r3, 1 - r3]) / (4 * math.sqrt(2.0))
     assert np.allclose(wv.daubechies(2), db2, atol=1e-14)
+    # db3 as tabulated in Daubechies' Ten Lectures on Wavelets (Table 6.1, scaled to sum sqrt 2)
+    db3 = [0.3326705529500826, 0.8068915093110925, 0.4598775021184915,
+           -0.1350110200102545, -0.0854412738820267, 0.0352262918857095]
+    assert np.allclose(wv.daubechies(3), db3, atol=1e-13)
 
 
 @pytest.mark.parametrize("n", range(1, 7))
