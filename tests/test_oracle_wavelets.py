@@ -1,5 +1,6 @@
 """Pins of the FP64 backward-step reference (eqs. 7 and 9) against facts that do
-not come from its own code: the closed-form Haar and db2 filters, the defining
+not come from its own code: the closed-form Haar and db2 filters, the published
+db3 table, the defining
 properties of Daubechies filters, perfect reconstruction and Parseval of an
 orthonormal transform, a hand-computed Haar level, the tight-frame identity of
 the dictionary, the closed-form prox in the Dirac / identity-metric case and
