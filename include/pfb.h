@@ -226,8 +226,9 @@ pfb_status pfb_wavelet_synthesis(pfb_plan *plan, const void *coeffs, void *x, vo
  * beta = (unorm + sigma) / gamma, sigma_d = beta, tau = 0.99 / (beta / 2 + sigma_d).
  * unorm >= ||I^psf *|| (e.g. pfb_power_iteration with a margin).  warm = 0 starts
  * from x = max(z, 0), v = 0; warm != 0 continues from the x passed in and the v
- * left in ws by the previous call.  z, x DEVICE real [n_band][nx][ny], z != x;
- * the plan's PSF spectrum must exist. */
+ * left in ws by the previous call, which must have used the same plan, ws and
+ * nbasis (the dual is not checked).  z, x DEVICE real [n_band][nx][ny], z != x;
+ * the plan's PSF spectrum must exist.  Calls on one ws must not overlap. */
 pfb_status pfb_prox_solve(pfb_plan *plan, const void *z, void *x, void *ws, size_t ws_bytes, int nbasis,
                           int levels, double lambda, double gamma, double sigma, double unorm, int iters,
                           int warm, hipStream_t stream);
