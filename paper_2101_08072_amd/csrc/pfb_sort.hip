@@ -3,8 +3,11 @@
 // The scatter pass fills every (band, tile, w-base-plane) bucket in an order
 // set by atomic cursors.  Here each bucket is re-ordered by a total key: the
 // block of rb x cb footprint base cells the entry falls in (rb = cb = 1: the
-// base cell itself), then the visibility index, which is unique within a
-// bucket.  One 64-bit key per entry, (bucket, block, index), is radix-sorted
+// base cell itself), then the base cell within the block (row-major, when the
+// key has room: neighbouring entries then read the same LDS rows in the
+// interpolation, which costs no bank conflicts), then the visibility index,
+// which is unique within a bucket.  One 64-bit key per entry, (bucket, block,
+// cell, index), is radix-sorted
 // with its position (hipCUB, stable); a gather then writes the records and
 // weights in that order.  The result depends on the inputs only, so repeated
 // plans of the same problem give bitwise-identical gridding.  For the FP32
@@ -28,8 +31,8 @@ int bits_for(uint64_t n) {   // bits to hold values 0 .. n - 1
 
 template <typename R>
 __global__ __launch_bounds__(kSortThreads) void sort_keys_kernel(const Rec<R> *recs, const int64_t *items, int T,
-                                                                 int W, int rb, int cb, int sh_blk, int sh_bucket,
-                                                                 uint64_t *keys, uint32_t *vals) {
+                                                                 int W, int rb, int cb, int sh_cell, int sh_blk,
+                                                                 int sh_bucket, uint64_t *keys, uint32_t *vals) {
     const int64_t start = items[4 * blockIdx.x], n = items[4 * blockIdx.x + 1], bucket = items[4 * blockIdx.x + 3];
     const int KS = T + W - 1, NB = (KS + cb - 1) / cb;
     const R hw = R(0.5) * R(W);
@@ -38,7 +41,9 @@ __global__ __launch_bounds__(kSortThreads) void sort_keys_kernel(const Rec<R> *r
         const int i0 = (int)dev_floor(r.fu - hw) + 1, j0 = (int)dev_floor(r.fv - hw) + 1;
         const int a = min(max(i0 + W - 1, 0), KS - 1), b = min(max(j0 + W - 1, 0), KS - 1);
         const uint64_t blk = (uint64_t)((a / rb) * NB + b / cb);
-        keys[start + e] = ((uint64_t)bucket << sh_bucket) | (blk << sh_blk) | (uint64_t)(r.idx & ~kHomeBit);
+        const uint64_t cell = sh_blk > sh_cell ? (uint64_t)((a % rb) * cb + b % cb) : 0;
+        keys[start + e] = ((uint64_t)bucket << sh_bucket) | (blk << sh_blk) | (cell << sh_cell) |
+                          (uint64_t)(r.idx & ~kHomeBit);
         vals[start + e] = (uint32_t)(start + e);
     }
 }
@@ -102,7 +107,10 @@ hipError_t launch_sort(bool dbl, const void *src, const void *src_om, void *dst,
     if (n_items <= 0 || n_entries <= 0) return hipSuccess;
     const int KS = T + W - 1;
     const int64_t nblk = (int64_t)((KS + rb - 1) / rb) * ((KS + cb - 1) / cb);
-    const int sh_blk = bits_for((uint64_t)n_vis);
+    const int sh_cell = bits_for((uint64_t)n_vis);
+    int cell_bits = bits_for((uint64_t)rb * cb);
+    if (sh_cell + cell_bits + bits_for((uint64_t)nblk) + bits_for((uint64_t)n_buckets) > 64) cell_bits = 0;
+    const int sh_blk = sh_cell + cell_bits;
     const int sh_bucket = sh_blk + bits_for((uint64_t)nblk);
     const int end_bit = sh_bucket + bits_for((uint64_t)n_buckets);
     if (end_bit > 64) return hipErrorInvalidValue;
@@ -114,10 +122,10 @@ hipError_t launch_sort(bool dbl, const void *src, const void *src_om, void *dst,
     uint32_t *vout = reinterpret_cast<uint32_t *>(base + L.vals_out);
     if (dbl)
         hipLaunchKernelGGL(sort_keys_kernel<double>, dim3(n_items), dim3(kSortThreads), 0, s,
-                           (const Rec<double> *)src, items, T, W, rb, cb, sh_blk, sh_bucket, kin, vin);
+                           (const Rec<double> *)src, items, T, W, rb, cb, sh_cell, sh_blk, sh_bucket, kin, vin);
     else
         hipLaunchKernelGGL(sort_keys_kernel<float>, dim3(n_items), dim3(kSortThreads), 0, s,
-                           (const Rec<float> *)src, items, T, W, rb, cb, sh_blk, sh_bucket, kin, vin);
+                           (const Rec<float> *)src, items, T, W, rb, cb, sh_cell, sh_blk, sh_bucket, kin, vin);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     size_t cub_bytes = L.cub_bytes;
