@@ -1350,9 +1350,9 @@ void daubechies_filter(int n, double *h) {
                 if (j != i) den *= (y[i] - y[j]);
             const C step = poly_at(y[i]) / den;
             y[i] -= step;
-            moved = std::max(moved, std::abs(step));
+            moved = std::max(moved, std::abs(step) / std::max(1.0, std::abs(y[i])));
         }
-        if (moved < 1e-17) break;
+        if (moved < 1e-15) break;
     }
     std::vector<C> roots(n, C(-1.0, 0.0));
     for (const C &yy : y) {
@@ -1378,11 +1378,18 @@ void daubechies_filter(int n, double *h) {
     for (int i = 0; i < 2 * n; ++i) h[i] *= std::sqrt(2.0) / sum;
 }
 
+// db1 .. db6, computed once per process (the initialisation of a function-local
+// static is thread-safe)
 WaveletFilter db_filter(int n) {
-    WaveletFilter f{};
-    f.len = 2 * n;
-    daubechies_filter(n, f.h);
-    return f;
+    static const std::vector<WaveletFilter> table = [] {
+        std::vector<WaveletFilter> t(kMaxBases);
+        for (int k = 1; k < kMaxBases; ++k) {
+            t[k].len = 2 * k;
+            daubechies_filter(k, t[k].h);
+        }
+        return t;
+    }();
+    return table[n];
 }
 
 // element offsets (in reals) of the prox workspace: v, coef, then six image buffers
