@@ -1102,18 +1102,19 @@ __global__ __launch_bounds__(kThreads) void absmax_blocks_kernel(int vmode, cons
                                                                  const float *weight, const uint8_t *flag,
                                                                  int64_t n, float *partials) {
     __shared__ float red[kThreads / 64];
+    // squared magnitudes (the root is taken once, in the final kernel); every load is
+    // issued whatever the weight and flag, so that loads of later iterations overlap
     float m = 0.f;
+#pragma unroll 4
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
         const float w = weight[e];
-        if (!(w > 0.f) || (flag && flag[e])) continue;
-        float v;
-        if (vmode == 1) {
-            v = w;
-        } else {
+        const bool on = w > 0.f && !(flag && flag[e]);
+        float v = w * w;
+        if (vmode != 1) {
             const cplx<float> z = vis[e];
-            v = sqrtf(z.re * z.re + z.im * z.im) * (vmode == 0 ? w : 1.f);
+            v = (z.re * z.re + z.im * z.im) * (vmode == 0 ? w * w : 1.f);
         }
-        m = fmaxf(m, v);
+        if (on) m = fmaxf(m, v);
     }
     for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -1134,8 +1135,9 @@ __global__ __launch_bounds__(kThreads) void absmax_final_kernel(const float *par
     if (threadIdx.x == 0) {
         float t = 0.f;
         for (int k = 0; k < kThreads / 64; ++k) t = fmaxf(t, red[k]);
-        // margin so that rounding in z * phi * S never exceeds 2^31 - 1
-        out[0] = t * 1.0001f;
+        // partials hold squared magnitudes; margin so that rounding in z * phi * S
+        // never exceeds 2^31 - 1
+        out[0] = sqrtf(t) * 1.0001f;
     }
 }
 __global__ void absmax_clear_kernel(float *out) { out[0] = 0.f; }
