@@ -52,6 +52,8 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.pfb_wavelet_analysis(None, None, None, None, 0, 7, 3, None) == -1
     assert lib.pfb_wavelet_synthesis(None, None, None, None, 0, 7, 3, None) == -1
     assert lib.pfb_prox_solve(None, None, None, None, 0, 7, 3, 1.0, 1.0, 1.0, 1.0, 1, 0, None) == -1
+    assert lib.pfb_fb_step_wavelet(None, None, None, None, 0, 7, 3, 1.0, 1.0, 1.0, 1.0, 1, 1, 0, None) == -1
+    assert lib.pfb_clean(None, None, None, None, 0, 7, 3, 1.0, 1.0, 1.0, 1.0, 1, 1, 1, None) == -1
     assert lib.pfb_plan_destroy(None) == 0
 
 
