@@ -1001,6 +1001,11 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                     const bool hi = r >= 8;               // rows 8..15 of a tile: its second plane
                     // plane weights k = r - 8 >= W fall outside the support (zero) and
                     // their planes are never flushed
+                    // the VALU work of a group (weights, operands) and the flushes run at a
+                    // raised wave priority, the matrix products at the base one: waves that
+                    // compute win the issue arbitration while another wave's products keep
+                    // the matrix core busy (6.35 -> 6.01 ms)
+                    __builtin_amdgcn_s_setprio(1);
                     const R_ E = es_kernel_fast(hi ? dq + R_(r - 8) : du + R_(r), beta2, inv_hw);
                     const R_ V = es_kernel_fast(dv + R_(r), beta2, inv_hw);
                     const R_ U = row_lo_to_hi(E);         // U[r mod 8]
@@ -1026,6 +1031,7 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                         zi = bperm_f(own, val_c.im);
                         key = __builtin_amdgcn_ds_bpermute(own, okey);
                     }
+                    __builtin_amdgcn_s_setprio(0);
                     unsigned rem = (1u << nb) - 1u;
                     while (rem) {
                         int w = key0;
@@ -1045,7 +1051,9 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                         }
                         const int cnt = __builtin_popcount(sel);
                         if (w != cur || run + cnt > kMfmaRunMax) {
+                            __builtin_amdgcn_s_setprio(1);
                             if (cur != kNoRun) flush(cur);
+                            __builtin_amdgcn_s_setprio(0);
                             cur = w;
                             run = 0;
                         }
