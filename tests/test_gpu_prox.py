@@ -141,3 +141,18 @@ def test_clean_exact_gradient_major_cycles(mb, mb_plan):
     ref, _ = wv.clean(prob, mb["psf"], dirty, x0, sigma, gamma, lam, unorm, cg_iters, pd_iters, n_major, levels)
     tol = 1e-4 if prec == "fp32" else 1e-9
     assert rel(host(xg), ref) < tol
+
+
+def test_precond_solve_two_bands(mb, mb_plan):
+    """CG on U = I^psf * + sigma Id (eq. 8) with two bands: each band's system has
+    its own step lengths, as in the oracle."""
+    prec, plan = mb_plan
+    R = _real(prec)
+    g = np.random.default_rng(29).normal(size=(2, 64, 32))
+    sigma, iters = 0.1 * mb["unorm"], 8
+    say(f"precond_solve two bands {prec}")
+    y = host(plan.precond_solve(to_dev(g, R), sigma, iters))
+    y_ref, _ = oracle.precond_solve(mb["psf"], g, sigma, iters)
+    tol = 1e-4 if prec == "fp32" else 1e-9
+    for b in range(2):
+        assert rel(y[b], y_ref[b]) < tol
