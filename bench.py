@@ -247,7 +247,7 @@ def cpu_baseline(prob, vis_host, x_host, M, target_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has "
               f"no multi-GPU path: bands would be sharded across GPUs with no exchange.",
               file=sys.stderr)
         sys.exit(2)
