@@ -111,3 +111,17 @@ def test_pd_fixed_point_with_psf_metric():
     assert np.linalg.norm(v2 - v) < 1e-7 * max(np.linalg.norm(v), 1e-30)
     # the dual is feasible (l2 over bands <= lam) and the primal non-negative
     assert (np.sqrt((v * v).sum(axis=1)) <= lam * (1 + 1e-12)).all() and (x >= 0).all()
+
+
+def test_dual_projection_is_the_moreau_complement_of_the_group_soft_threshold():
+    """prox of sigma H^* for H = lam ||.||_{2,1} (over the band axis) equals
+    t - sigma prox_{H / sigma}(t / sigma) (Moreau's identity), where the prox of the
+    group norm is the group soft threshold."""
+    rng = np.random.default_rng(31)
+    t = rng.normal(size=(3, 4, 5, 6)) * 2.0
+    lam, sigma = 0.7, 2.5
+    u = t / sigma
+    nrm = np.sqrt((u * u).sum(axis=1, keepdims=True))
+    soft = u * np.maximum(0.0, 1.0 - (lam / sigma) / np.where(nrm > 0, nrm, 1.0))
+    ref = t - sigma * soft
+    assert np.allclose(wv.l21_dual_project(t, lam), ref, atol=1e-12)
