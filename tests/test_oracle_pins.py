@@ -323,3 +323,27 @@ def test_fb_steps_decrease_the_objective(oracle_mod):
     # zero image, zero dirty image: x = 0 is a fixed point
     z = oracle_mod.fb_step(P, np.zeros_like(dirty), np.zeros_like(dirty), sigma, gamma, lam, 10)
     assert np.all(z == 0)
+
+
+@pytest.mark.parametrize("gamma", [0.5, 1.7])
+def test_fb_step_scaled_delta_psf_closed_form(oracle_mod, gamma):
+    """I^psf = c_b delta in band b makes U = (c_b + sigma) Id (eq. 8), so the CG solve is
+    exact after one step and the forward-backward step (eq. 6, then the l1 + positivity
+    prox standing in for eq. 7) has the closed form
+    max(x - gamma (c_b x - I^d) / (c_b + sigma) - gamma lam, 0).  gamma != 1 separates the
+    threshold gamma lam from lam; the bands have different c_b, so one step length
+    shared by both bands would fail."""
+    rng = np.random.default_rng(41)
+    nb, nx, ny = 2, 8, 6
+    c = np.array([2.5, 4.0])
+    sigma, lam = 0.3, 0.2
+    D = np.zeros((nb, 2 * nx, 2 * ny))
+    D[:, nx, ny] = c
+    x = rng.uniform(0.0, 1.0, (nb, nx, ny))
+    dirty = rng.normal(0.0, 2.0, (nb, nx, ny))
+    out = oracle_mod.fb_step(D, dirty, x, sigma, gamma, lam, 3)
+    cb = c[:, None, None]
+    ref = np.maximum(x - gamma * (cb * x - dirty) / (cb + sigma) - gamma * lam, 0.0)
+    assert np.abs(out - ref).max() < 1e-12
+    # positivity is enforced and active; the threshold leaves some pixels positive
+    assert (out >= 0).all() and (out == 0).any() and (out > 0).any()

@@ -125,3 +125,108 @@ def test_dual_projection_is_the_moreau_complement_of_the_group_soft_threshold():
     soft = u * np.maximum(0.0, 1.0 - (lam / sigma) / np.where(nrm > 0, nrm, 1.0))
     ref = t - sigma * soft
     assert np.allclose(wv.l21_dual_project(t, lam), ref, atol=1e-12)
+
+
+def test_condat_step_rule_satisfies_the_convergence_condition():
+    """Condat (2013), Theorem 3.1: the iteration converges when
+    1 / tau - sigma_d ||L||^2 > beta / 2 for L = Psi^dagger.  ||L||^2 is measured here by
+    power iteration on Psi Psi^dagger (a tight frame gives 1), not taken from the code."""
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=(2, 16, 16))
+    for _ in range(30):
+        w = wv.psi(wv.psi_adj(v, 2), 2)
+        nrm2 = float(np.vdot(v, w) / np.vdot(v, v))
+        v = w / np.linalg.norm(w)
+    assert abs(nrm2 - 1.0) < 1e-12
+    for unorm, sigma_u, gamma in [(3.0, 0.0, 1.0), (120.0, 0.12, 0.5), (1.0, 1e-3, 1.9)]:
+        beta, sigma_d, tau = wv.pd_steps(unorm, sigma_u, gamma)
+        assert beta == pytest.approx((unorm + sigma_u) / gamma)   # Lipschitz constant of grad F
+        assert 1.0 / tau - sigma_d * nrm2 > 0.5 * beta
+
+
+def _delta_psf(nb, nx, ny, c):
+    D = np.zeros((nb, 2 * nx, 2 * ny))
+    D[:, nx, ny] = c
+    return D
+
+
+def test_fb_step_wavelet_scaled_delta_psf_closed_form():
+    """I^psf = c delta and U = (c + sigma) Id: the forward step (eq. 6) is
+    z = x - gamma (c x - I^d) / (c + sigma), and the U-metric prox of eq. 7 with the Dirac
+    basis alone is the prox of gamma / (c + sigma) (lam ||.||_{2,1} + iota_+), the group
+    soft threshold of z_+ with threshold gamma lam / (c + sigma)."""
+    rng = np.random.default_rng(13)
+    nb, nx, ny = 3, 8, 8
+    c, sigma, gamma, lam = 2.0, 0.5, 0.6, 0.3
+    D = _delta_psf(nb, nx, ny, c)
+    x = rng.uniform(0.0, 1.0, (nb, nx, ny))
+    dirty = rng.normal(0.0, 1.5, (nb, nx, ny)) + 1.0
+    xo, v = wv.fb_step_wavelet(D, dirty, x, sigma, gamma, lam, c, 3, 3000, 1, nbasis=1)
+    z = x - gamma * (c * x - dirty) / (c + sigma)
+    zp = np.maximum(z, 0.0)
+    nrm = np.sqrt((zp * zp).sum(axis=0, keepdims=True))
+    ref = zp * np.maximum(0.0, 1.0 - (gamma * lam / (c + sigma)) / np.where(nrm > 0, nrm, 1.0))
+    assert (ref == 0).any() and (ref > 0).any()
+    assert np.abs(xo - ref).max() < 1e-9
+    # zero primal-dual iterations: a cold start returns max(z, 0), a warm one its start x
+    xc, _ = wv.fb_step_wavelet(D, dirty, x, sigma, gamma, lam, c, 3, 0, 1, nbasis=1)
+    assert np.abs(xc - zp).max() < 1e-13
+    xw, _ = wv.fb_step_wavelet(D, dirty, x, sigma, gamma, lam, c, 3, 0, 1, nbasis=1,
+                               v0=np.zeros((1,) + x.shape), warm=True)
+    assert np.array_equal(xw, x)
+
+
+def _clean_problem():
+    import synth
+    p = synth.tiny_problem(seed=61, nx=16, ny=16, n_row=80, w_frac=0.5, cell_arcsec=60.0)
+    x_true = synth.point_sky(61, 1, 16, 16, n_src=5, flux=(0.2, 1.0))
+    return p, x_true
+
+
+def test_clean_fixed_point_with_exact_gradient():
+    """lam = 0, I^d = R^dagger Sigma^-1 R x_true (eq. 3, w term included) and x_true >= 0:
+    the exact gradient vanishes at x_true, so the pfb-clean iterations started there
+    return x_true unchanged."""
+    p, x_true = _clean_problem()
+    psf = oracle.psf(p)
+    dirty = oracle.hessian(p, x_true)
+    lam_max, _ = oracle.power_iteration(lambda t: oracle.psf_conv(psf, t), np.ones((1, 16, 16)), 40)
+    x, _ = wv.clean(p, psf, dirty, x_true, 1e-2 * lam_max, 1.0, 0.0, 1.05 * lam_max, 10, 20, 3, 2)
+    assert np.abs(x - x_true).max() < 1e-10 * np.abs(x_true).max()
+
+
+def test_clean_decreases_the_data_fidelity():
+    """From x = 0 with lam = 0, each exact-gradient step (eq. 3) preconditioned by
+    U = I^psf * + sigma Id (eq. 8), gamma = 1 < 2 / L_U, followed by the U-metric
+    projection onto x >= 0 (eq. 7 with lam = 0) lowers f(x) of eq. 2."""
+    p, x_true = _clean_problem()
+    vis = oracle.degrid(p, x_true)
+    psf = oracle.psf(p)
+    dirty = oracle.grid(p, vis)
+    lam_max, _ = oracle.power_iteration(lambda t: oracle.psf_conv(psf, t), np.ones((1, 16, 16)), 40)
+    sigma = 1e-1 * lam_max
+    x = np.zeros_like(x_true)
+    f = [oracle.fidelity(p, x, vis)]
+    for n in range(1, 5):
+        x, _ = wv.clean(p, psf, dirty, np.zeros_like(x_true), sigma, 1.0, 0.0, 1.05 * lam_max, 40, 300, n, 2)
+        f.append(oracle.fidelity(p, x, vis))
+    assert np.all(np.diff(f) < 0), f
+    assert f[-1] < 0.5 * f[0]
+    assert (x >= 0).all()
+
+
+def test_clean_warm_starts_from_the_previous_step():
+    """With zero primal-dual iterations the prox returns its start point: the first
+    (cold) step gives max(z, 0), and every later step is warm-started from the previous
+    iterate, so it returns that iterate unchanged."""
+    p, x_true = _clean_problem()
+    psf = oracle.psf(p)
+    dirty = oracle.hessian(p, x_true)
+    x0 = np.full_like(x_true, 0.05)
+    args = (p, psf, dirty, x0, 0.5, 1.0, 0.1, 100.0, 10, 0)
+    x1, _ = wv.clean(*args, 1, 2)
+    x3, _ = wv.clean(*args, 3, 2)
+    assert np.array_equal(x1, x3)
+    y, _ = oracle.precond_solve(psf, oracle.hessian(p, x0) - dirty, 0.5, 10)
+    assert not np.array_equal(x1, x0)
+    assert np.abs(x1 - np.maximum(x0 - y, 0.0)).max() < 1e-13
