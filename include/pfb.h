@@ -40,12 +40,16 @@
  *   - Every pointer documented as "device" is HIP device memory owned by the
  *     caller; the library borrows it.  uvw, weight and flag must stay valid
  *     and unchanged until pfb_plan_destroy.
- *   - All persistent device state of a plan (visibility buckets, correction
+ *   - The library never allocates device memory.  Plan set-up takes three
+ *     calls: pfb_plan_create (validation, uvw analysis), pfb_plan_count (the
+ *     counting pass, in a caller-provided scratch buffer whose size
+ *     pfb_plan_count_scratch_size reports) and pfb_plan_set_workspace.  All
+ *     persistent device state of a plan (visibility buckets, correction
  *     tables, twiddles, w-planes, FFT intermediates, the resident PSF
  *     spectrum, CG vectors) lives in ONE caller-provided workspace whose size
- *     pfb_plan_workspace_size reports.  The operator calls never allocate.
- *     pfb_plan_create allocates and frees a temporary device buffer for its
- *     counting pass and synchronises its stream; nothing else synchronises.
+ *     pfb_plan_workspace_size reports.  pfb_plan_create and pfb_plan_count
+ *     synchronise their stream (uvw and the bucket counts are read on the
+ *     host); so does pfb_precond_solve with tol > 0; nothing else does.
  *   - Operator calls are asynchronous on the stream they are given and contain
  *     no host synchronisation.  A plan is not thread-safe; calls on one plan
  *     must be serialised on one stream.  Distinct plans are independent.
@@ -111,7 +115,13 @@ typedef struct {
     int32_t band_batch;   /* bands whose w-planes are resident at once; default n_band       */
     int32_t chunk;        /* bucket entries per work item before a tile is split (>= 64);
                              default max(4096, entries / compute units of the device)       */
-    int32_t reserved[7];
+    double  epsilon;      /* requested relative accuracy of grid / degrid (rel-l2); when
+                             support is 0 and epsilon > 0 the support is the smallest W whose
+                             tabulated error of the 3-D ES product kernel at sigma = 2 is
+                             <= epsilon (FP32: W 4..8, reach ~3e-7; FP64: W 9..16, reach
+                             ~5e-15); a smaller epsilon than the precision reaches is
+                             PFB_EINVAL.  0: the default support.                          */
+    int32_t reserved[6];
 } pfb_options;
 
 /* Read-only description of a created plan. */
@@ -136,14 +146,28 @@ typedef struct {
     int64_t occ_tiles, occ_tile_rows, need_tiles, need_tile_rows;
 } pfb_plan_info;
 
-/* Creates a plan: validates the problem, analyses uvw (copied to the host),
- * counts visibilities per (band, uv tile, w-plane) on the device with a
- * temporary buffer, and synchronises `stream`.  On success *plan must be
- * released with pfb_plan_destroy. */
+/* Creates a plan: validates the problem and analyses uvw (copied to the host on
+ * `stream`, which is synchronised) to fix the grids and w-planes of every band
+ * (Section 2: R per band).  Allocates no device memory.  On success *plan must be
+ * released with pfb_plan_destroy; pfb_plan_count comes next. */
 pfb_status pfb_plan_create(pfb_plan **plan, const pfb_problem *prob, const pfb_options *opt,
                            hipStream_t stream);
 
-/* Bytes of device workspace the plan needs (256-byte aligned pointer expected). */
+/* Bytes of the device scratch buffer pfb_plan_count needs: one band's counters per
+ * (uv tile, w base plane) of the operator and the PSF gridders plus small tables
+ * (bands are counted one after another). */
+pfb_status pfb_plan_count_scratch_size(const pfb_plan *plan, size_t *bytes);
+
+/* Counting pass: the visibilities of every band are counted per (uv tile, w base
+ * plane) in `scratch` (DEVICE, >= pfb_plan_count_scratch_size bytes, 256-byte
+ * aligned, borrowed only for this call: it may be reused once the call returns),
+ * then the work lists and the workspace layout are fixed on the host.
+ * Synchronises `stream`.  Fails with PFB_EINVAL if an unflagged weight is NaN,
+ * negative or infinite.  Once per plan (PFB_ESTATE on a second call). */
+pfb_status pfb_plan_count(pfb_plan *plan, void *scratch, size_t bytes, hipStream_t stream);
+
+/* Bytes of device workspace the plan needs (256-byte aligned pointer expected);
+ * valid after pfb_plan_count. */
 pfb_status pfb_plan_workspace_size(const pfb_plan *plan, size_t *bytes);
 
 /* Hands the plan its workspace and enqueues on `stream` the one-off set-up
@@ -174,12 +198,16 @@ pfb_status pfb_hessian(pfb_plan *plan, const void *x, void *y, hipStream_t strea
  * x, y DEVICE real [n_band][nx][ny]; x may equal y.  Needs pfb_grid(PFB_GRID_PSF) first. */
 pfb_status pfb_psf_conv(pfb_plan *plan, const void *x, void *y, hipStream_t stream);
 
-/* Solves (I^psf * + sigma Id) y = g by `iters` conjugate-gradient steps from y = 0
- * (eq. 8 and the sentence after it); every band independently.  Inner products and
- * step lengths are float64 on the device.  g, y DEVICE real [n_band][nx][ny], g != y.
+/* Solves (I^psf * + sigma Id) y = g by at most `iters` conjugate-gradient steps from
+ * y = 0 (eq. 8 and the sentence after it); every band independently.  Inner products
+ * and step lengths are float64 on the device.  g, y DEVICE real [n_band][nx][ny], g != y.
+ * tol = 0: exactly `iters` steps, no host synchronisation (graph-capturable).
+ * tol > 0: the loop stops after the first step at which every band has
+ * ||r||_2 <= tol ||g||_2; the residuals are read on the host after every step, so the
+ * call synchronises `stream` and is refused (PFB_ESTATE) while the stream is capturing.
  * dev_resid: NULL or DEVICE float64[n_band], receives the final squared residual norm. */
 pfb_status pfb_precond_solve(pfb_plan *plan, const void *g, void *y, double sigma, int iters,
-                             double *dev_resid, hipStream_t stream);
+                             double tol, double *dev_resid, hipStream_t stream);
 
 /* Power iteration for the largest eigenvalue of op (0 = I^psf *, 1 = R^dagger Sigma^-1 R),
  * per band: v <- A v / ||A v|| `iters` times from v0, then lambda = v^T A v.  float64

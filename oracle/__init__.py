@@ -13,7 +13,10 @@ wide-field continuum imaging of radio interferometric data", Section 2:
 * ``fidelity``    f(x)                      (eq. 2)
 * ``gradient``    exact gradient            (eq. 3)
 * ``psf``         I^psf, flat, 2nx x 2ny    (eq. 4)
+* ``psf_factored`` the same sum with each phase factor split over the two axes
+                  (a matrix product; for large images with few visibilities)
 * ``psf_conv``    I^psf * x, linear         (eq. 4)
+* ``psf_conv_op`` the same convolution by FFT with the PSF spectrum computed once
 * ``cg``          conjugate gradient on U = I^psf * + sigma Id    (eq. 8 and the text after it)
 * ``power_iteration``  largest eigenvalue of a symmetric operator (step-size rationale after eq. 8)
 * ``fb_step``     one forward (eq. 6) and Euclidean l1+positivity backward step
@@ -146,6 +149,39 @@ def psf(prob, pix=None):
     return out.reshape(prob.n_band, NX, NY) if full else out
 
 
+def psf_factored(prob):
+    """The flat PSF of ``psf`` evaluated as a matrix product (eq. 4).
+
+    The phase of the PSF sum is u dl + v dm, so each term
+    w cos(2 pi (u dl + v dm)) is the real part of w e^{2 pi i u dl} e^{2 pi i v dm}:
+    PSF_b = Re(E_l^T diag(w) E_m) over the visibilities of band b, with
+    E_l[k, i'] = e^{2 pi i u_k dl_i'} and E_m[k, j'] = e^{2 pi i v_k dm_j'}.  Phases are
+    reduced by their nearest integer in FP64 before the exponential; row 0 and
+    column 0 (offset -nx, -ny) are zero.  Exact in exact arithmetic; the cost is a
+    (2nx x K) by (K x 2ny) product, so it serves images too large for the
+    per-pixel direct sum when the visibility count K is small."""
+    wt = prob.effective_weight()
+    NX, NY = 2 * prob.nx, 2 * prob.ny
+    dl = (np.arange(NX) - prob.nx) * prob.cellx
+    dm = (np.arange(NY) - prob.ny) * prob.celly
+    out = np.zeros((prob.n_band, NX, NY))
+    for b in range(prob.n_band):
+        rr, cc = np.nonzero(wt * (prob.chan_band[None, :] == b))
+        if rr.size == 0:
+            continue
+        s = prob.freq[cc] / C0
+        u = prob.uvw[rr, 0] * s
+        v = prob.uvw[rr, 1] * s
+        tl = np.outer(u, dl)
+        tm = np.outer(v, dm)
+        El = np.exp(2j * np.pi * (tl - np.rint(tl))) * wt[rr, cc][:, None]
+        Em = np.exp(2j * np.pi * (tm - np.rint(tm)))
+        out[b] = (El.T @ Em).real
+    out[:, 0, :] = 0.0
+    out[:, :, 0] = 0.0
+    return out
+
+
 def fidelity(prob, x, vis):
     """f(x) = 1/2 (V - Rx)^H Sigma^-1 (V - Rx)   (eq. 2)."""
     r = np.asarray(vis).reshape(prob.n_row, prob.n_chan) - degrid(prob, x)
@@ -223,6 +259,31 @@ def psf_conv(psf_img, x):
     return out
 
 
+def psf_conv_op(psf_img):
+    """I^psf * (eq. 4) as a function of x, by FFT with the PSF spectrum computed once.
+
+    For output pixels i in [n, 2n) and inputs i2 in [0, n) the offset i - i2 lies in
+    [1, 2n - 1], so the circular convolution of period 2n (per axis) of the 2n x 2n
+    PSF with the zero-padded image, cropped to [n, 2n), is the linear convolution of
+    ``psf_conv`` exactly: no offset wraps.  scipy.fft (all cores) is the library FFT."""
+    import scipy.fft as sfft
+    psf_img = np.asarray(psf_img, dtype=np.float64)
+    nb, NX, NY = psf_img.shape
+    nx, ny = NX // 2, NY // 2
+    spec = [sfft.rfft2(psf_img[b], workers=-1) for b in range(nb)]
+
+    def band(b, v):
+        xs = sfft.rfft2(np.asarray(v, dtype=np.float64), s=(NX, NY), workers=-1)
+        xs *= spec[b]
+        return sfft.irfft2(xs, s=(NX, NY), workers=-1)[nx:, ny:].copy()
+
+    def apply(x):
+        x = np.asarray(x, dtype=np.float64).reshape(nb, nx, ny)
+        return np.stack([band(b, x[b]) for b in range(nb)])
+    apply.band = band
+    return apply
+
+
 def cg(apply_A, g, iters, y0=None):
     """Conjugate gradient for A y = g from y0 = 0, a fixed number of iterations.
 
@@ -248,18 +309,30 @@ def cg(apply_A, g, iters, y0=None):
     return y, np.array(trace)
 
 
-def precond_solve(psf_img, g, sigma, iters):
+def precond_solve(psf_img, g, sigma, iters, conv=None):
     """y ~= (I^psf * + sigma Id)^-1 g by ``iters`` CG steps (eq. 8 and the text after it).
 
     U acts on every band with that band's PSF (eq. 4), so the system is
     block-diagonal over bands; each band's system gets its own CG (its own step
-    lengths).  Returns (y, residual norms^2 with shape (n_band, iterations + 1))."""
+    lengths).  ``conv``: the PSF convolution of all bands as a function (default
+    ``psf_conv`` of ``psf_img``; e.g. ``psf_conv_op(psf_img)`` for large images).
+    Returns (y, residual norms^2 with shape (n_band, iterations + 1))."""
     g = np.asarray(g, dtype=np.float64)
     psf_img = np.asarray(psf_img, dtype=np.float64)
+    nb = g.shape[0]
     ys, traces = [], []
-    for b in range(g.shape[0]):
-        pb = psf_img[b:b + 1]
-        yb, tb = cg(lambda v: psf_conv(pb, v[None])[0] + sigma * v, g[b], iters)
+    for b in range(nb):
+        if conv is None:
+            pb = psf_img[b:b + 1]
+            conv_b = lambda v, pb=pb: psf_conv(pb, v[None])[0]  # noqa: E731
+        elif hasattr(conv, "band"):
+            conv_b = lambda v, b=b: conv.band(b, v)  # noqa: E731
+        else:
+            def conv_b(v, b=b):
+                full = np.zeros((nb,) + v.shape)
+                full[b] = v
+                return conv(full)[b]
+        yb, tb = cg(lambda v: conv_b(v) + sigma * v, g[b], iters)
         ys.append(yb)
         traces.append(tb)
     n = max(len(t) for t in traces)
@@ -277,14 +350,16 @@ def power_iteration(apply_A, v0, iters):
     return float(np.vdot(v, apply_A(v))), v
 
 
-def fb_step(psf_img, dirty, x, sigma, gamma, lam, cg_iters):
+def fb_step(psf_img, dirty, x, sigma, gamma, lam, cg_iters, conv=None):
     """One preconditioned forward-backward step with the PSF-approximate gradient.
 
     forward  (eq. 6): x_half = x - gamma U^-1 (I^psf * x - I^d), U = I^psf * + sigma Id
     backward (eq. 7 with U replaced by the identity): prox of gamma(lam ||.||_1 + positivity)
-             = max(x_half - gamma lam, 0)."""
-    grad = psf_conv(psf_img, x) - dirty
-    y, _ = precond_solve(psf_img, grad, sigma, cg_iters)
+             = max(x_half - gamma lam, 0).
+    ``conv`` as for ``precond_solve``."""
+    conv = conv or (lambda v: psf_conv(psf_img, v))
+    grad = conv(x) - dirty
+    y, _ = precond_solve(psf_img, grad, sigma, cg_iters, conv=conv)
     x_half = x - gamma * y
     return np.maximum(x_half - gamma * lam, 0.0)
 

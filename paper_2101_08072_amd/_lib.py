@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "PFB_OK", -1: "PFB_EINVAL", -2: "PFB_ENOMEM", -3: "PFB_EHIP",
                 -4: "PFB_EUNSUPPORTED", -5: "PFB_ESTATE"}
 
 # every symbol include/pfb.h declares
-EXPORTS = ["pfb_plan_create", "pfb_plan_workspace_size", "pfb_plan_set_workspace",
+EXPORTS = ["pfb_plan_create", "pfb_plan_count_scratch_size", "pfb_plan_count", "pfb_plan_workspace_size", "pfb_plan_set_workspace",
            "pfb_plan_get_info", "pfb_plan_destroy", "pfb_grid", "pfb_degrid", "pfb_hessian",
            "pfb_psf_conv", "pfb_precond_solve", "pfb_power_iteration", "pfb_fb_step",
            "pfb_fb_graph_create", "pfb_graph_launch", "pfb_graph_destroy",
@@ -35,7 +35,7 @@ class PfbOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("oversample", ctypes.c_double), ("tile", ctypes.c_int32), ("flat", ctypes.c_int32),
                 ("band_batch", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("epsilon", ctypes.c_double), ("reserved", ctypes.c_int32 * 6)]
 
 
 class PfbPlanInfo(ctypes.Structure):
@@ -67,6 +67,8 @@ def load():
     plan_pp = ctypes.POINTER(ctypes.c_void_p)
     sig = {
         "pfb_plan_create": [plan_pp, ctypes.POINTER(PfbProblem), ctypes.POINTER(PfbOptions), vp],
+        "pfb_plan_count_scratch_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "pfb_plan_count": [vp, vp, sz, vp],
         "pfb_plan_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "pfb_plan_set_workspace": [vp, vp, sz, vp],
         "pfb_plan_get_info": [vp, ctypes.POINTER(PfbPlanInfo)],
@@ -75,7 +77,7 @@ def load():
         "pfb_degrid": [vp, vp, vp, vp],
         "pfb_hessian": [vp, vp, vp, vp],
         "pfb_psf_conv": [vp, vp, vp, vp],
-        "pfb_precond_solve": [vp, vp, vp, f64, i32, vp, vp],
+        "pfb_precond_solve": [vp, vp, vp, f64, i32, f64, vp, vp],
         "pfb_power_iteration": [vp, i32, vp, i32, vp, vp],
         "pfb_fb_step": [vp, vp, vp, f64, f64, f64, i32, vp],
         "pfb_fb_graph_create": [vp, vp, vp, f64, f64, f64, i32, i32, vp, ctypes.POINTER(ctypes.c_void_p)],

@@ -225,7 +225,7 @@ struct pfb_plan {
     // workspace
     size_t ws_bytes = 0;
     char *ws = nullptr;
-    bool ws_ready = false, psf_ready = false;
+    bool counted = false, ws_ready = false, psf_ready = false;
     size_t o_freq = 0, o_cb = 0, o_cheb = 0, o_tw = 0, o_flagged = 0, o_flagcur = 0;
     size_t o_planes = 0, o_t1 = 0, o_t2 = 0, o_vals = 0, o_psfimg = 0;
     size_t o_t1c = 0, o_t2c = 0, o_psfhat = 0, o_vec = 0, o_partials = 0, o_scal = 0, o_absmax = 0;
@@ -464,7 +464,10 @@ InterpLaunch interp_args(const GridderHost &G, int b0, int nbb, int omode, const
             return fail(PFB_EHIP, "%s: %s", #expr, hipGetErrorString(_e));              \
     } while (0)
 
-pfb_status cg_solve(pfb_plan *P, const void *g, void *y, double sigma, int iters, hipStream_t s) {
+// tol > 0: after every iteration the squared residuals are read back (host
+// synchronisation) and the loop stops once every band has |r| <= tol |g|.
+pfb_status cg_solve(pfb_plan *P, const void *g, void *y, double sigma, int iters, hipStream_t s, double tol = 0.0,
+                    int *iters_done = nullptr) {
     const bool d = P->dbl;
     ConvArgs ca = conv_args(P);
     const int nb = P->prob.n_band;
@@ -482,6 +485,15 @@ pfb_status cg_solve(pfb_plan *P, const void *g, void *y, double sigma, int iters
         LAUNCH_OK(launch_vec(d, VEC_CG_UPDATE, nb, Pn, ca.partials, ca.max_partials, ca.scal, nullptr, y, r, p, ap,
                              0, 0, s));
         LAUNCH_OK(launch_reduce(RED_BETA, nb, ca.partials, vparts, ca.max_partials, ca.scal, s));
+        if (iters_done) *iters_done = it + 1;
+        if (tol > 0.0) {
+            std::vector<double> sc((size_t)nb * 8);
+            HIP_OK(hipMemcpyAsync(sc.data(), ca.scal, sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            bool done = true;
+            for (int b = 0; b < nb; ++b) done = done && sc[(size_t)b * 8 + S_RR] <= tol * tol * sc[(size_t)b * 8 + S_RR0];
+            if (done) break;
+        }
     }
     return PFB_OK;
 }
@@ -507,231 +519,111 @@ pfb_status hessian_impl(pfb_plan *P, const void *x, void *y, hipStream_t s) {
     return PFB_OK;
 }
 
-}  // namespace
 
-// ============================================================================
-// C ABI
-// ============================================================================
-extern "C" {
-
-const char *pfb_last_error(void) { return g_last_error.c_str(); }
-const char *pfb_version(void) { return "pfb-mi355x 0.1 (gfx950)"; }
-
-pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_options *opt_in, hipStream_t stream) {
-    if (!out) return fail(PFB_EINVAL, "plan output pointer is NULL");
-    *out = nullptr;
-    if (!prob) return fail(PFB_EINVAL, "problem is NULL");
-    pfb_options opt{};
-    if (opt_in) opt = *opt_in;
-    const pfb_problem &pr = *prob;
-    if (pr.n_row <= 0 || pr.n_chan <= 0 || pr.n_band <= 0)
-        return fail(PFB_EINVAL, "n_row, n_chan and n_band must be positive");
-    if (pr.n_band > pr.n_chan) return fail(PFB_EINVAL, "more bands than channels");
-    if (pr.n_row * pr.n_chan >= (int64_t(1) << 31))
-        return fail(PFB_EUNSUPPORTED, "n_row * n_chan must be below 2^31");
-    if (!pr.chan_band || !pr.freq || !pr.uvw || !pr.weight) return fail(PFB_EINVAL, "NULL array in problem");
-    if (!is_pow2(pr.nx) || !is_pow2(pr.ny) || pr.nx < 16 || pr.ny < 16)
-        return fail(PFB_EINVAL, "nx and ny must be powers of two >= 16 (got %d x %d)", pr.nx, pr.ny);
-    if (!(pr.cellx > 0) || !(pr.celly > 0) || !std::isfinite(pr.cellx) || !std::isfinite(pr.celly))
-        return fail(PFB_EINVAL, "cell sizes must be positive and finite");
-    if (opt.precision != PFB_FP32 && opt.precision != PFB_FP64) return fail(PFB_EINVAL, "unknown precision");
-    const bool dbl = opt.precision == PFB_FP64;
-    if (opt.support == 0) opt.support = dbl ? 13 : 7;
-    if (dbl ? (opt.support < 9 || opt.support > 16) : (opt.support < 4 || opt.support > 8))
-        return fail(PFB_EINVAL, "support %d outside the range compiled for this precision", opt.support);
-    if (opt.oversample == 0.0) opt.oversample = 2.0;
-    if (opt.oversample != 2.0) return fail(PFB_EUNSUPPORTED, "only oversampling 2.0 is implemented");
-    if (opt.tile == 0) opt.tile = std::max(8, std::min(dbl ? 8 : 32, std::min(pr.nx, pr.ny)));
-    if (!is_pow2(opt.tile) || opt.tile < 8 || opt.tile > 64)
-        return fail(PFB_EINVAL, "tile must be a power of two in [8, 64]");
-    if (2 * std::min(pr.nx, pr.ny) < 2 * opt.tile) return fail(PFB_EINVAL, "tile larger than half the grid");
-    if (gridder_lds_bytes(dbl, opt.support, opt.tile, opt.flat != 0) > kMaxLdsBytes)
-        return fail(PFB_EINVAL, "tile %d with support %d needs %zu bytes of LDS per block (at most %zu)", opt.tile,
-                    opt.support, gridder_lds_bytes(dbl, opt.support, opt.tile, opt.flat != 0), kMaxLdsBytes);
-    if (opt.flat != 0 && opt.flat != 1) return fail(PFB_EINVAL, "flat must be 0 or 1");
-    if (opt.chunk != 0 && opt.chunk < 64) return fail(PFB_EINVAL, "chunk must be >= 64");
-    // FFT length limits (LDS-resident rows)
-    const int max_row = dbl ? 8192 : 16384;
-    if (4 * pr.nx > max_row || 4 * pr.ny > max_row)
-        return fail(PFB_EUNSUPPORTED, "image %d x %d needs FFT rows longer than %d for this precision", pr.nx, pr.ny,
-                    max_row);
-    const double lmax2 = std::pow(0.5 * pr.nx * pr.cellx, 2) + std::pow(0.5 * pr.ny * pr.celly, 2);
-    if (!opt.flat && lmax2 >= 1.0) return fail(PFB_EINVAL, "field of view reaches l^2 + m^2 >= 1");
-
-    pfb_plan *P = new pfb_plan();
-    P->prob = pr;
-    P->opt = opt;
-    P->dbl = dbl;
-    P->rsz = dbl ? 8 : 4;
-    P->chan_band.assign(pr.chan_band, pr.chan_band + pr.n_chan);
-    P->freq.assign(pr.freq, pr.freq + pr.n_chan);
-    auto bail = [&](pfb_status st) {
-        delete P;
-        return st;
-    };
-    for (int64_t c = 0; c < pr.n_chan; ++c) {
-        if (P->chan_band[c] < 0 || P->chan_band[c] >= pr.n_band) {
-            fail(PFB_EINVAL, "chan_band[%lld] = %d outside [0, %d)", (long long)c, P->chan_band[c], pr.n_band);
-            return bail(PFB_EINVAL);
-        }
-        if (!(P->freq[c] > 0) || !std::isfinite(P->freq[c])) {
-            fail(PFB_EINVAL, "freq[%lld] is not a positive finite number", (long long)c);
-            return bail(PFB_EINVAL);
-        }
-    }
-    // uvw analysis on the host
-    std::vector<double> uvw(3 * pr.n_row);
-    {
-        hipError_t e = hipMemcpy(uvw.data(), pr.uvw, uvw.size() * sizeof(double), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) {
-            fail(PFB_EHIP, "copying uvw to the host failed: %s", hipGetErrorString(e));
-            return bail(PFB_EHIP);
-        }
-    }
-    double wlo = INFINITY, whi = -INFINITY;
-    for (int64_t r = 0; r < pr.n_row; ++r) {
-        for (int k = 0; k < 3; ++k)
-            if (!std::isfinite(uvw[3 * r + k])) {
-                fail(PFB_EINVAL, "uvw[%lld] is not finite", (long long)r);
-                return bail(PFB_EINVAL);
-            }
-        wlo = std::min(wlo, uvw[3 * r + 2]);
-        whi = std::max(whi, uvw[3 * r + 2]);
-    }
-    std::vector<double> fmin(pr.n_band, INFINITY), fmax(pr.n_band, 0.0);
-    for (int64_t c = 0; c < pr.n_chan; ++c) {
-        fmin[P->chan_band[c]] = std::min(fmin[P->chan_band[c]], P->freq[c]);
-        fmax[P->chan_band[c]] = std::max(fmax[P->chan_band[c]], P->freq[c]);
-    }
-
-    // geometry of the two gridders
-    GridderHost &M = P->main;
-    M.g = base_geom(*P, pr.nx, pr.ny, opt.flat != 0);
-    M.cs = make_split(M.g.gx);
-    {
-        const double r2 = lmax2;
-        P->s_min = opt.flat ? 0.0 : -r2 / (1.0 + std::sqrt(1.0 - r2));
-    }
-    M.bands.resize(pr.n_band);
-    M.g.nj0max = 1;
-    M.g.nwmax = 1;
-    for (int b = 0; b < pr.n_band; ++b) {
-        BandDev &bd = M.bands[b];
-        if (opt.flat || P->s_min == 0.0 || fmax[b] == 0.0) {
-            bd.w0 = 0.0;
-            bd.dw = 1.0;
-            bd.sc = 0.0;
-            bd.nw = 1;
-            bd.nj0 = 1;
-        } else {
-            const double s0 = fmin[b] / kC0, s1 = fmax[b] / kC0;
-            const double wmin = std::min({wlo * s0, wlo * s1, whi * s0, whi * s1});
-            const double wmax = std::max({wlo * s0, wlo * s1, whi * s0, whi * s1});
-            bd.dw = 1.0 / (2.0 * std::fabs(P->s_min));   // w oversampling 2
-            bd.sc = 0.5 * P->s_min;
-            const double D = (wmax - wmin) / bd.dw;
-            bd.nj0 = (int)std::floor(D) + 2;
-            bd.nw = bd.nj0 + opt.support - 1;
-            bd.w0 = wmin - (0.5 * opt.support - 0.5) * bd.dw;
-        }
-        M.g.nj0max = std::max(M.g.nj0max, bd.nj0);
-        M.g.nwmax = std::max(M.g.nwmax, bd.nw);
-    }
-    M.mfma = !dbl && !opt.flat;
-    if (M.mfma) mfma_window(opt.support, &M.sort_rb, &M.sort_cb);
-    GridderHost &Q = P->psf;
-    Q.g = base_geom(*P, 2 * pr.nx, 2 * pr.ny, true);
-    Q.cs = make_split(Q.g.gx);
-    Q.bands.assign(pr.n_band, BandDev{0.0, 1.0, 0.0, 1, 1});
-    Q.g.nj0max = 1;
-    Q.g.nwmax = 1;
-    Q.corr2d = false;
-
-    // device count pass with a temporary buffer
-    const int64_t kM = M.keys(), kQ = Q.keys();
-    size_t tmp_bytes = 0;
+// Bytes of the counting scratch of pfb_plan_count: the channel tables, both
+// gridders' band descriptors, ONE band's (tile, base plane) counters of both
+// gridders (bands are counted one after another) and the global counters.
+struct CountLayout {
+    size_t freq, cb, bm, bq, cm, cq, hm, hq, ctr, total;
+    int64_t kMb, kQb;   // keys per band of the main and the PSF gridder
+};
+CountLayout count_layout(const pfb_plan &P) {
+    CountLayout c{};
+    const pfb_problem &pr = P.prob;
+    c.kMb = P.main.keys() / pr.n_band;
+    c.kQb = P.psf.keys() / pr.n_band;
     Layout tl;
-    const size_t t_freq = tl.take(pr.n_chan * sizeof(double));
-    const size_t t_cb = tl.take(pr.n_chan * sizeof(int));
-    const size_t t_bm = tl.take(M.bands.size() * sizeof(BandDev));
-    const size_t t_bq = tl.take(Q.bands.size() * sizeof(BandDev));
-    const size_t t_cm = tl.take(kM * sizeof(unsigned));
-    const size_t t_cq = tl.take(kQ * sizeof(unsigned));
-    const size_t t_hm = tl.take(kM * sizeof(unsigned));
-    const size_t t_hq = tl.take(kQ * sizeof(unsigned));
-    const size_t t_ctr = tl.take(8 * sizeof(unsigned long long));
-    tmp_bytes = tl.off;
-    char *tmp = nullptr;
-    {
-        hipError_t e = hipMalloc(&tmp, tmp_bytes);
-        if (e != hipSuccess) {
-            fail(PFB_ENOMEM, "temporary device buffer of %zu bytes: %s", tmp_bytes, hipGetErrorString(e));
-            return bail(PFB_ENOMEM);
-        }
-    }
+    c.freq = tl.take(pr.n_chan * sizeof(double));
+    c.cb = tl.take(pr.n_chan * sizeof(int));
+    c.bm = tl.take(P.main.bands.size() * sizeof(BandDev));
+    c.bq = tl.take(P.psf.bands.size() * sizeof(BandDev));
+    c.cm = tl.take(c.kMb * sizeof(unsigned));
+    c.cq = tl.take(c.kQb * sizeof(unsigned));
+    c.hm = tl.take(c.kMb * sizeof(unsigned));
+    c.hq = tl.take(c.kQb * sizeof(unsigned));
+    c.ctr = tl.take(8 * sizeof(unsigned long long));
+    c.total = tl.off;
+    return c;
+}
+
+// Counting pass (per band, in `tmp`), then bucket offsets, work lists, tables and
+// the workspace layout.  Synchronises `stream` once, after the last band.
+pfb_status count_and_layout(pfb_plan *P, char *tmp, hipStream_t stream) {
+    const pfb_problem &pr = P->prob;
+    const pfb_options &opt = P->opt;
+    const bool dbl = P->dbl;
+    GridderHost &M = P->main;
+    GridderHost &Q = P->psf;
+    const CountLayout cl = count_layout(*P);
+    const int64_t kM = M.keys(), kQ = Q.keys();
     std::vector<unsigned> cM(kM), cQ(kQ), hM(kM), hQ(kQ);
     unsigned long long ctr[8] = {0};
+    std::vector<int> cb(P->chan_band.begin(), P->chan_band.end());
     pfb_status st = PFB_OK;
     do {
         hipError_t e = hipSuccess;
-        std::vector<int> cb(P->chan_band.begin(), P->chan_band.end());
 #define TMP_OK(x)                                                                    \
     e = (x);                                                                         \
     if (e != hipSuccess) {                                                           \
         st = fail(PFB_EHIP, "%s: %s", #x, hipGetErrorString(e));                    \
         break;                                                                       \
     }
-        TMP_OK(hipMemcpyAsync(tmp + t_freq, P->freq.data(), pr.n_chan * sizeof(double), hipMemcpyHostToDevice, stream));
-        TMP_OK(hipMemcpyAsync(tmp + t_cb, cb.data(), pr.n_chan * sizeof(int), hipMemcpyHostToDevice, stream));
-        TMP_OK(hipMemcpyAsync(tmp + t_bm, M.bands.data(), M.bands.size() * sizeof(BandDev), hipMemcpyHostToDevice, stream));
-        TMP_OK(hipMemcpyAsync(tmp + t_bq, Q.bands.data(), Q.bands.size() * sizeof(BandDev), hipMemcpyHostToDevice, stream));
-        TMP_OK(hipMemsetAsync(tmp + t_cm, 0, kM * sizeof(unsigned), stream));
-        TMP_OK(hipMemsetAsync(tmp + t_cq, 0, kQ * sizeof(unsigned), stream));
-        TMP_OK(hipMemsetAsync(tmp + t_hm, 0, kM * sizeof(unsigned), stream));
-        TMP_OK(hipMemsetAsync(tmp + t_hq, 0, kQ * sizeof(unsigned), stream));
-        TMP_OK(hipMemsetAsync(tmp + t_ctr, 0, 8 * sizeof(unsigned long long), stream));
-        BucketArgs ba{};
-        ba.uvw = pr.uvw;
-        ba.freq_dev = reinterpret_cast<const double *>(tmp + t_freq);
-        ba.chan_band_dev = reinterpret_cast<const int *>(tmp + t_cb);
-        ba.weight = pr.weight;
-        ba.flag = pr.flag;
-        ba.n_row = pr.n_row;
-        ba.n_chan = pr.n_chan;
-        unsigned long long *c = reinterpret_cast<unsigned long long *>(tmp + t_ctr);
-        ba.g = M.g;
-        ba.bands = reinterpret_cast<const BandDev *>(tmp + t_bm);
-        ba.counts = reinterpret_cast<unsigned *>(tmp + t_cm);
-        ba.home_counts = reinterpret_cast<unsigned *>(tmp + t_hm);
-        ba.n_active = c;
-        ba.n_flagged = c + 1;
-        ba.n_bad = c + 2;
-        TMP_OK(launch_count(dbl, ba, stream));
-        ba.g = Q.g;
-        ba.bands = reinterpret_cast<const BandDev *>(tmp + t_bq);
-        ba.counts = reinterpret_cast<unsigned *>(tmp + t_cq);
-        ba.home_counts = reinterpret_cast<unsigned *>(tmp + t_hq);
-        ba.n_active = c + 3;
-        ba.n_flagged = c + 4;
-        ba.n_bad = c + 5;
-        TMP_OK(launch_count(dbl, ba, stream));
-        TMP_OK(hipMemcpyAsync(cM.data(), tmp + t_cm, kM * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
-        TMP_OK(hipMemcpyAsync(cQ.data(), tmp + t_cq, kQ * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
-        TMP_OK(hipMemcpyAsync(hM.data(), tmp + t_hm, kM * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
-        TMP_OK(hipMemcpyAsync(hQ.data(), tmp + t_hq, kQ * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+        TMP_OK(hipMemcpyAsync(tmp + cl.freq, P->freq.data(), pr.n_chan * sizeof(double), hipMemcpyHostToDevice, stream));
+        TMP_OK(hipMemcpyAsync(tmp + cl.cb, cb.data(), pr.n_chan * sizeof(int), hipMemcpyHostToDevice, stream));
+        TMP_OK(hipMemcpyAsync(tmp + cl.bm, M.bands.data(), M.bands.size() * sizeof(BandDev), hipMemcpyHostToDevice, stream));
+        TMP_OK(hipMemcpyAsync(tmp + cl.bq, Q.bands.data(), Q.bands.size() * sizeof(BandDev), hipMemcpyHostToDevice, stream));
+        TMP_OK(hipMemsetAsync(tmp + cl.ctr, 0, 8 * sizeof(unsigned long long), stream));
+        unsigned long long *c = reinterpret_cast<unsigned long long *>(tmp + cl.ctr);
+        for (int b = 0; b < pr.n_band; ++b) {
+            TMP_OK(hipMemsetAsync(tmp + cl.cm, 0, cl.kMb * sizeof(unsigned), stream));
+            TMP_OK(hipMemsetAsync(tmp + cl.cq, 0, cl.kQb * sizeof(unsigned), stream));
+            TMP_OK(hipMemsetAsync(tmp + cl.hm, 0, cl.kMb * sizeof(unsigned), stream));
+            TMP_OK(hipMemsetAsync(tmp + cl.hq, 0, cl.kQb * sizeof(unsigned), stream));
+            BucketArgs ba{};
+            ba.uvw = pr.uvw;
+            ba.freq_dev = reinterpret_cast<const double *>(tmp + cl.freq);
+            ba.chan_band_dev = reinterpret_cast<const int *>(tmp + cl.cb);
+            ba.weight = pr.weight;
+            ba.flag = pr.flag;
+            ba.n_row = pr.n_row;
+            ba.n_chan = pr.n_chan;
+            ba.band_sel = b;
+            ba.g = M.g;
+            ba.bands = reinterpret_cast<const BandDev *>(tmp + cl.bm);
+            ba.counts = reinterpret_cast<unsigned *>(tmp + cl.cm);
+            ba.home_counts = reinterpret_cast<unsigned *>(tmp + cl.hm);
+            ba.n_active = c;
+            ba.n_flagged = c + 1;
+            ba.n_bad = c + 2;
+            ba.n_badw = c + 6;
+            TMP_OK(launch_count(dbl, ba, stream));
+            ba.n_badw = nullptr;
+            ba.g = Q.g;
+            ba.bands = reinterpret_cast<const BandDev *>(tmp + cl.bq);
+            ba.counts = reinterpret_cast<unsigned *>(tmp + cl.cq);
+            ba.home_counts = reinterpret_cast<unsigned *>(tmp + cl.hq);
+            ba.n_active = c + 3;
+            ba.n_flagged = c + 4;
+            ba.n_bad = c + 5;
+            TMP_OK(launch_count(dbl, ba, stream));
+            // stream order: each band's copies finish before the next band clears the counters
+            TMP_OK(hipMemcpyAsync(cM.data() + b * cl.kMb, tmp + cl.cm, cl.kMb * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+            TMP_OK(hipMemcpyAsync(cQ.data() + b * cl.kQb, tmp + cl.cq, cl.kQb * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+            TMP_OK(hipMemcpyAsync(hM.data() + b * cl.kMb, tmp + cl.hm, cl.kMb * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+            TMP_OK(hipMemcpyAsync(hQ.data() + b * cl.kQb, tmp + cl.hq, cl.kQb * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+        }
+        if (st != PFB_OK) break;
         TMP_OK(hipMemcpyAsync(ctr, c, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
         TMP_OK(hipStreamSynchronize(stream));
 #undef TMP_OK
     } while (0);
-    (void)hipFree(tmp);
-    if (st != PFB_OK) return bail(st);
-    if (ctr[2] || ctr[5]) {
-        fail(PFB_EINVAL, "%llu visibilities fell outside the planned w range", ctr[2] + ctr[5]);
-        return bail(PFB_EINVAL);
-    }
+    if (st != PFB_OK) return st;
+    if (ctr[6])
+        return fail(PFB_EINVAL, "%llu unflagged weights are NaN, negative or infinite (weights are diag(Sigma^-1) >= 0)",
+                    ctr[6]);
+    if (ctr[2] || ctr[5]) return fail(PFB_EINVAL, "%llu visibilities fell outside the planned w range", ctr[2] + ctr[5]);
     P->n_active = (int64_t)ctr[0];
     P->n_flagged = (int64_t)ctr[1];
-
     // bucket offsets and work lists
     for (GridderHost *G : {&M, &Q}) {
         const std::vector<unsigned> &cnt = (G == &M) ? cM : cQ;
@@ -754,7 +646,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         G->n_home = hacc;
         if (acc >= (int64_t(1) << 31)) {
             fail(PFB_EUNSUPPORTED, "%lld bucket entries exceed 2^31", (long long)acc);
-            return bail(PFB_EUNSUPPORTED);
+            return PFB_EUNSUPPORTED;
         }
         // work-item size: a given chunk, else one compute unit's share of all entries
         // (>= 4096): a spread item split by plane range re-reads the entries of the
@@ -778,7 +670,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
             }
         if (sort_key_bits(G->keys(), G->g.T, G->g.W, G->sort_rb, G->sort_cb, pr.n_row * pr.n_chan) > 64) {
             fail(PFB_EUNSUPPORTED, "bucket sort key exceeds 64 bits (too many buckets x visibilities)");
-            return bail(PFB_EUNSUPPORTED);
+            return PFB_EUNSUPPORTED;
         }
     }
 
@@ -789,7 +681,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
         P->cheb = psihat_chebyshev(ph, P->xi_max, 40, &err);
         if (err > 1e-13) {
             fail(PFB_EHIP, "correction expansion error %.3g too large", err);
-            return bail(PFB_EHIP);
+            return PFB_EHIP;
         }
     }
     // twiddles
@@ -880,18 +772,195 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     P->o_scal = L.take((size_t)nb * 8 * sizeof(double));
     P->o_absmax = L.take((kAbsmaxBlocks + 64) * sizeof(float));
     P->ws_bytes = L.off;
+    P->counted = true;
+    return PFB_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char *pfb_last_error(void) { return g_last_error.c_str(); }
+const char *pfb_version(void) { return "pfb-mi355x 0.1 (gfx950)"; }
+
+pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_options *opt_in, hipStream_t stream) {
+    if (!out) return fail(PFB_EINVAL, "plan output pointer is NULL");
+    *out = nullptr;
+    if (!prob) return fail(PFB_EINVAL, "problem is NULL");
+    pfb_options opt{};
+    if (opt_in) opt = *opt_in;
+    const pfb_problem &pr = *prob;
+    if (pr.n_row <= 0 || pr.n_chan <= 0 || pr.n_band <= 0)
+        return fail(PFB_EINVAL, "n_row, n_chan and n_band must be positive");
+    if (pr.n_band > pr.n_chan) return fail(PFB_EINVAL, "more bands than channels");
+    if (pr.n_row * pr.n_chan >= (int64_t(1) << 31))
+        return fail(PFB_EUNSUPPORTED, "n_row * n_chan must be below 2^31");
+    if (!pr.chan_band || !pr.freq || !pr.uvw || !pr.weight) return fail(PFB_EINVAL, "NULL array in problem");
+    if (!is_pow2(pr.nx) || !is_pow2(pr.ny) || pr.nx < 16 || pr.ny < 16)
+        return fail(PFB_EINVAL, "nx and ny must be powers of two >= 16 (got %d x %d)", pr.nx, pr.ny);
+    if (!(pr.cellx > 0) || !(pr.celly > 0) || !std::isfinite(pr.cellx) || !std::isfinite(pr.celly))
+        return fail(PFB_EINVAL, "cell sizes must be positive and finite");
+    if (opt.precision != PFB_FP32 && opt.precision != PFB_FP64) return fail(PFB_EINVAL, "unknown precision");
+    const bool dbl = opt.precision == PFB_FP64;
+    if (!(opt.epsilon >= 0.0) || !std::isfinite(opt.epsilon)) return fail(PFB_EINVAL, "epsilon must be finite and >= 0");
+    if (opt.support == 0 && opt.epsilon > 0.0) {
+        // rel-l2 error of the 1-D ES NUFFT at sigma = 2, beta = 2.30 W (W = 6..8 and
+        // 11..13 measured, the rest geometric inter- and extrapolation); the 3-D product
+        // kernel (u, v, w) is taken as three times that
+        static const double err1d[17] = {0, 0, 0, 0, 6.0e-4, 6.8e-5, 7.7e-6, 8.8e-7, 1.0e-7,
+                                         1.2e-8, 1.4e-9, 1.8e-10, 1.7e-11, 1.7e-12, 1.7e-13, 1.7e-14, 1.7e-15};
+        const int wlo = dbl ? 9 : 4, whi = dbl ? 16 : 8;
+        for (int W = wlo; W <= whi && opt.support == 0; ++W)
+            if (3.0 * err1d[W] <= opt.epsilon) opt.support = W;
+        if (opt.support == 0)
+            return fail(PFB_EINVAL, "epsilon %.3g is below what the %s path reaches (%.1e)", opt.epsilon,
+                        dbl ? "FP64" : "FP32", 3.0 * err1d[whi]);
+    }
+    if (opt.support == 0) opt.support = dbl ? 13 : 7;
+    if (dbl ? (opt.support < 9 || opt.support > 16) : (opt.support < 4 || opt.support > 8))
+        return fail(PFB_EINVAL, "support %d outside the range compiled for this precision", opt.support);
+    if (opt.oversample == 0.0) opt.oversample = 2.0;
+    if (opt.oversample != 2.0) return fail(PFB_EUNSUPPORTED, "only oversampling 2.0 is implemented");
+    if (opt.tile == 0) opt.tile = std::max(8, std::min(dbl ? 8 : 32, std::min(pr.nx, pr.ny)));
+    if (!is_pow2(opt.tile) || opt.tile < 8 || opt.tile > 64)
+        return fail(PFB_EINVAL, "tile must be a power of two in [8, 64]");
+    if (2 * std::min(pr.nx, pr.ny) < 2 * opt.tile) return fail(PFB_EINVAL, "tile larger than half the grid");
+    if (gridder_lds_bytes(dbl, opt.support, opt.tile, opt.flat != 0) > kMaxLdsBytes)
+        return fail(PFB_EINVAL, "tile %d with support %d needs %zu bytes of LDS per block (at most %zu)", opt.tile,
+                    opt.support, gridder_lds_bytes(dbl, opt.support, opt.tile, opt.flat != 0), kMaxLdsBytes);
+    if (opt.flat != 0 && opt.flat != 1) return fail(PFB_EINVAL, "flat must be 0 or 1");
+    if (opt.chunk != 0 && opt.chunk < 64) return fail(PFB_EINVAL, "chunk must be >= 64");
+    // FFT length limits (LDS-resident rows)
+    const int max_row = dbl ? 8192 : 16384;
+    if (4 * pr.nx > max_row || 4 * pr.ny > max_row)
+        return fail(PFB_EUNSUPPORTED, "image %d x %d needs FFT rows longer than %d for this precision", pr.nx, pr.ny,
+                    max_row);
+    const double lmax2 = std::pow(0.5 * pr.nx * pr.cellx, 2) + std::pow(0.5 * pr.ny * pr.celly, 2);
+    if (!opt.flat && lmax2 >= 1.0) return fail(PFB_EINVAL, "field of view reaches l^2 + m^2 >= 1");
+
+    pfb_plan *P = new pfb_plan();
+    P->prob = pr;
+    P->opt = opt;
+    P->dbl = dbl;
+    P->rsz = dbl ? 8 : 4;
+    P->chan_band.assign(pr.chan_band, pr.chan_band + pr.n_chan);
+    P->freq.assign(pr.freq, pr.freq + pr.n_chan);
+    auto bail = [&](pfb_status st) {
+        delete P;
+        return st;
+    };
+    for (int64_t c = 0; c < pr.n_chan; ++c) {
+        if (P->chan_band[c] < 0 || P->chan_band[c] >= pr.n_band) {
+            fail(PFB_EINVAL, "chan_band[%lld] = %d outside [0, %d)", (long long)c, P->chan_band[c], pr.n_band);
+            return bail(PFB_EINVAL);
+        }
+        if (!(P->freq[c] > 0) || !std::isfinite(P->freq[c])) {
+            fail(PFB_EINVAL, "freq[%lld] is not a positive finite number", (long long)c);
+            return bail(PFB_EINVAL);
+        }
+    }
+    // uvw analysis on the host
+    std::vector<double> uvw(3 * pr.n_row);
+    {
+        hipError_t e = hipMemcpyAsync(uvw.data(), pr.uvw, uvw.size() * sizeof(double), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            fail(PFB_EHIP, "copying uvw to the host failed: %s", hipGetErrorString(e));
+            return bail(PFB_EHIP);
+        }
+    }
+    double wlo = INFINITY, whi = -INFINITY;
+    for (int64_t r = 0; r < pr.n_row; ++r) {
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(uvw[3 * r + k])) {
+                fail(PFB_EINVAL, "uvw[%lld] is not finite", (long long)r);
+                return bail(PFB_EINVAL);
+            }
+        wlo = std::min(wlo, uvw[3 * r + 2]);
+        whi = std::max(whi, uvw[3 * r + 2]);
+    }
+    std::vector<double> fmin(pr.n_band, INFINITY), fmax(pr.n_band, 0.0);
+    for (int64_t c = 0; c < pr.n_chan; ++c) {
+        fmin[P->chan_band[c]] = std::min(fmin[P->chan_band[c]], P->freq[c]);
+        fmax[P->chan_band[c]] = std::max(fmax[P->chan_band[c]], P->freq[c]);
+    }
+
+    // geometry of the two gridders
+    GridderHost &M = P->main;
+    M.g = base_geom(*P, pr.nx, pr.ny, opt.flat != 0);
+    M.cs = make_split(M.g.gx);
+    {
+        const double r2 = lmax2;
+        P->s_min = opt.flat ? 0.0 : -r2 / (1.0 + std::sqrt(1.0 - r2));
+    }
+    M.bands.resize(pr.n_band);
+    M.g.nj0max = 1;
+    M.g.nwmax = 1;
+    for (int b = 0; b < pr.n_band; ++b) {
+        BandDev &bd = M.bands[b];
+        if (opt.flat || P->s_min == 0.0 || fmax[b] == 0.0) {
+            bd.w0 = 0.0;
+            bd.dw = 1.0;
+            bd.sc = 0.0;
+            bd.nw = 1;
+            bd.nj0 = 1;
+        } else {
+            const double s0 = fmin[b] / kC0, s1 = fmax[b] / kC0;
+            const double wmin = std::min({wlo * s0, wlo * s1, whi * s0, whi * s1});
+            const double wmax = std::max({wlo * s0, wlo * s1, whi * s0, whi * s1});
+            bd.dw = 1.0 / (2.0 * std::fabs(P->s_min));   // w oversampling 2
+            bd.sc = 0.5 * P->s_min;
+            const double D = (wmax - wmin) / bd.dw;
+            bd.nj0 = (int)std::floor(D) + 2;
+            bd.nw = bd.nj0 + opt.support - 1;
+            bd.w0 = wmin - (0.5 * opt.support - 0.5) * bd.dw;
+        }
+        M.g.nj0max = std::max(M.g.nj0max, bd.nj0);
+        M.g.nwmax = std::max(M.g.nwmax, bd.nw);
+    }
+    M.mfma = !dbl && !opt.flat;
+    if (M.mfma) mfma_window(opt.support, &M.sort_rb, &M.sort_cb);
+    GridderHost &Q = P->psf;
+    Q.g = base_geom(*P, 2 * pr.nx, 2 * pr.ny, true);
+    Q.cs = make_split(Q.g.gx);
+    Q.bands.assign(pr.n_band, BandDev{0.0, 1.0, 0.0, 1, 1});
+    Q.g.nj0max = 1;
+    Q.g.nwmax = 1;
+    Q.corr2d = false;
+
     *out = P;
     return PFB_OK;
 }
 
+pfb_status pfb_plan_count_scratch_size(const pfb_plan *P, size_t *bytes) {
+    if (!P || !bytes) return fail(PFB_EINVAL, "NULL argument");
+    *bytes = count_layout(*P).total;
+    return PFB_OK;
+}
+
+pfb_status pfb_plan_count(pfb_plan *P, void *scratch, size_t bytes, hipStream_t stream) {
+    if (!P) return fail(PFB_EINVAL, "plan is NULL");
+    if (P->counted) return fail(PFB_ESTATE, "the plan has already been counted");
+    const CountLayout cl = count_layout(*P);
+    if (!scratch) return fail(PFB_EINVAL, "count scratch is NULL");
+    if (bytes < cl.total) return fail(PFB_ENOMEM, "count scratch of %zu bytes < required %zu", bytes, cl.total);
+    if (reinterpret_cast<uintptr_t>(scratch) & 255) return fail(PFB_EINVAL, "count scratch must be 256-byte aligned");
+    return count_and_layout(P, reinterpret_cast<char *>(scratch), stream);
+}
+
 pfb_status pfb_plan_workspace_size(const pfb_plan *P, size_t *bytes) {
     if (!P || !bytes) return fail(PFB_EINVAL, "NULL argument");
+    if (!P->counted) return fail(PFB_ESTATE, "pfb_plan_count has not been called");
     *bytes = P->ws_bytes;
     return PFB_OK;
 }
 
 pfb_status pfb_plan_get_info(const pfb_plan *P, pfb_plan_info *info) {
     if (!P || !info) return fail(PFB_EINVAL, "NULL argument");
+    if (!P->counted) return fail(PFB_ESTATE, "pfb_plan_count has not been called");
     std::memset(info, 0, sizeof(*info));
     info->grid_x = P->main.g.gx;
     info->grid_y = P->main.g.gy;
@@ -932,6 +1001,7 @@ pfb_status pfb_plan_get_info(const pfb_plan *P, pfb_plan_info *info) {
 
 pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStream_t s) {
     if (!P) return fail(PFB_EINVAL, "plan is NULL");
+    if (!P->counted) return fail(PFB_ESTATE, "pfb_plan_count has not been called");
     if (!dev) return fail(PFB_ENOMEM, "workspace pointer is NULL");
     if (bytes < P->ws_bytes) return fail(PFB_ENOMEM, "workspace of %zu bytes < required %zu", bytes, P->ws_bytes);
     if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(PFB_EINVAL, "workspace must be 256-byte aligned");
@@ -1217,8 +1287,8 @@ pfb_status pfb_psf_conv(pfb_plan *P, const void *x, void *y, hipStream_t s) {
     return PFB_OK;
 }
 
-pfb_status pfb_precond_solve(pfb_plan *P, const void *g, void *y, double sigma, int iters, double *dev_resid,
-                             hipStream_t s) {
+pfb_status pfb_precond_solve(pfb_plan *P, const void *g, void *y, double sigma, int iters, double tol,
+                             double *dev_resid, hipStream_t s) {
     ProfScope prof_scope(P);
     pfb_status st = check_ready(P);
     if (st) return st;
@@ -1226,8 +1296,15 @@ pfb_status pfb_precond_solve(pfb_plan *P, const void *g, void *y, double sigma, 
     if (g == y) return fail(PFB_EINVAL, "g and y must differ");
     if (!(sigma >= 0) || !std::isfinite(sigma)) return fail(PFB_EINVAL, "sigma must be finite and >= 0");
     if (iters < 0) return fail(PFB_EINVAL, "iters must be >= 0");
+    if (!(tol >= 0) || !std::isfinite(tol)) return fail(PFB_EINVAL, "tol must be finite and >= 0");
     if (!P->psf_ready) return fail(PFB_ESTATE, "no PSF spectrum: call pfb_grid with PFB_GRID_PSF first");
-    st = cg_solve(P, g, y, sigma, iters, s);
+    if (tol > 0.0) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIP_OK(hipStreamIsCapturing(s, &cs));
+        if (cs != hipStreamCaptureStatusNone)
+            return fail(PFB_ESTATE, "tol > 0 reads the residual on the host and cannot be captured; use tol = 0");
+    }
+    st = cg_solve(P, g, y, sigma, iters, s, tol);
     if (st) return st;
     if (dev_resid) LAUNCH_OK(launch_copy_scalar(P->prob.n_band, reinterpret_cast<double *>(P->p(P->o_scal)), S_RR,
                                                 dev_resid, s));

@@ -62,9 +62,11 @@ struct BucketArgs {
     const BandDev *bands;
     int64_t n_row, n_chan;
     // count pass
-    unsigned int *counts;       // [n_band * ntiles * nj0max]
+    int band_sel;               // >= 0: count only entries of this band, counts relative to it
+    unsigned int *counts;       // [n_band * ntiles * nj0max] (one band's share when band_sel >= 0)
     unsigned int *home_counts;  // same shape: entries listed under their own (home) tile
     unsigned long long *n_active, *n_flagged, *n_bad;
+    unsigned long long *n_badw;  // may be null: unflagged entries whose weight is NaN, < 0 or infinite
     // scatter pass
     unsigned long long *cursor; // [n_band * ntiles * nj0max] (starts at offsets)
     void *recs;                 // Rec<R>[n_entries]

@@ -170,7 +170,7 @@ hipError_t launch_vec(bool dbl, int op, int n_band, int64_t P, double *partials,
 int vec_partials_per_band(int64_t P);
 
 // scalar slots in scal[b*8 + k]
-enum Slot { S_RR = 0, S_ALPHA = 1, S_BETA = 2, S_PAP = 3, S_SCALE = 4, S_LAMBDA = 5, S_TMP = 6 };
+enum Slot { S_RR = 0, S_ALPHA = 1, S_BETA = 2, S_PAP = 3, S_SCALE = 4, S_LAMBDA = 5, S_TMP = 6, S_RR0 = 7 };
 enum ReduceOp {
     RED_SET_RR = 0,       // rr = sum; beta = 0
     RED_ALPHA = 1,        // pAp = sum; alpha = rr / pAp

@@ -9,6 +9,7 @@
 #include <utility>
 
 #include "pfb_kernels.h"
+#include <limits>
 
 namespace pfb {
 
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void bucket_kernel(BucketArgs a) {
     const int64_t total = a.n_row * a.n_chan;
     const int ntiles = a.g.ntx * a.g.nty;
     const R *wt = reinterpret_cast<const R *>(a.weight);
-    unsigned long long n_act = 0, n_flag = 0, n_bad = 0;
+    unsigned long long n_act = 0, n_flag = 0, n_bad = 0, n_badw = 0;
     const int lane = threadIdx.x & 63;
     for (int64_t base = (int64_t)blockIdx.x * kThreads; base < total; base += (int64_t)gridDim.x * kThreads) {
         const int64_t e = base + threadIdx.x;
@@ -168,8 +169,15 @@ __global__ __launch_bounds__(kThreads) void bucket_kernel(BucketArgs a) {
         if (valid) {
             r = e / a.n_chan;
             c = (int)(e - r * a.n_chan);
+        }
+        if (!SCATTER && valid && a.band_sel >= 0 && a.chan_band_dev[c] != a.band_sel) valid = false;
+        if (valid) {
             w = wt[e];
-            flagged = (a.flag && a.flag[e]) || !(w > R(0));
+            const bool fl = a.flag && a.flag[e];
+            flagged = fl || !(w > R(0));
+            // the weights are diag(Sigma^-1): a NaN, negative or infinite weight of an
+            // unflagged entry is an input error (counted; the plan is refused)
+            if (!SCATTER && !fl && !(w >= R(0) && w <= std::numeric_limits<R>::max())) ++n_badw;
         }
         if (SCATTER && a.flagged) {
             // wave-aggregated append of flagged indices
@@ -205,8 +213,9 @@ __global__ __launch_bounds__(kThreads) void bucket_kernel(BucketArgs a) {
                 const int tile = wrapi(k.tu + ou, a.g.ntx) * a.g.nty + wrapi(k.tv + ov, a.g.nty);
                 const int64_t key = ((int64_t)b * ntiles + tile) * a.g.nj0max + k.j0;
                 if (!SCATTER) {
-                    atomicAdd(a.counts + key, 1u);
-                    if (ou == 0 && ov == 0) atomicAdd(a.home_counts + key, 1u);
+                    const int64_t kc = key - (a.band_sel >= 0 ? (int64_t)a.band_sel * ntiles * a.g.nj0max : 0);
+                    atomicAdd(a.counts + kc, 1u);
+                    if (ou == 0 && ov == 0) atomicAdd(a.home_counts + kc, 1u);
                 } else {
                     const unsigned long long pos = atomicAdd(a.cursor + key, 1ull);
                     Rec<R> rec;
@@ -224,6 +233,7 @@ __global__ __launch_bounds__(kThreads) void bucket_kernel(BucketArgs a) {
         if (n_act) atomicAdd(a.n_active, n_act);
         if (n_flag) atomicAdd(a.n_flagged, n_flag);
         if (n_bad) atomicAdd(a.n_bad, n_bad);
+        if (n_badw && a.n_badw) atomicAdd(a.n_badw, n_badw);
     }
 }
 
@@ -389,6 +399,26 @@ hipError_t launch_corr1d(bool dbl, int n, int gsize, const double *cheb, int nch
 // FP64 path: the ring holds doubles updated with LDS float atomics.
 constexpr int kTileThreads = 1024;   // 16 waves share one tile's LDS ring
 
+// Fixed-point scale of the FP32 spread from am >= max |z| of the values spread:
+// contributions are z * phi * fscale with |.| <= S, and the stored sums are
+// multiplied by finv.  am = 0 means every value is zero (exact zero grid).  An
+// am that is not finite (a NaN or infinite value, weight or product) or outside
+// [2^-96, 2^120] (where S / am or am / S would leave the FP32 range) turns every
+// output cell into NaN (fscale = 0, finv = NaN), so such input is never gridded
+// silently.
+__device__ __forceinline__ void fixed_point_scale(float am, float S, float &fscale, float &finv) {
+    if (am == 0.f) {
+        fscale = 1.f;
+        finv = 1.f;
+    } else if (am >= 0x1p-96f && am <= 0x1p+120f) {
+        fscale = S / am;
+        finv = am / S;
+    } else {
+        fscale = 0.f;
+        finv = __builtin_nanf("");
+    }
+}
+
 template <typename R> struct SpreadAcc { using T = R; };
 template <> struct SpreadAcc<float> { using T = unsigned long long; };
 
@@ -414,13 +444,7 @@ __global__ __launch_bounds__(kTileThreads) void spread_kernel(SpreadLaunch a) {
     cplx<R> *planes = reinterpret_cast<cplx<R> *>(a.planes);
     // fixed-point scale (FP32 path)
     R fscale = R(1), finv = R(1);
-    if (FIX) {
-        const float am = *a.absmax;
-        if (am > 0.f) {
-            fscale = 1073741824.0f / am;   // 2^30 / max|z|
-            finv = am / 1073741824.0f;
-        }
-    }
+    if constexpr (FIX) fixed_point_scale(*a.absmax, 1073741824.0f, fscale, finv);   // 2^30 / max|z|
 
     for (int k = threadIdx.x; k < 2 * WW * TT; k += NT) sre[k] = A(0);
     __syncthreads();
@@ -585,13 +609,7 @@ __global__ __launch_bounds__(kTileThreads) void spread_run_kernel(SpreadLaunch a
     const cplx<R> *vis = reinterpret_cast<const cplx<R> *>(a.vis);
     cplx<R> *planes = reinterpret_cast<cplx<R> *>(a.planes);
     R fscale = R(1), finv = R(1);
-    {
-        const float am = *a.absmax;
-        if (am > 0.f) {
-            fscale = kRunScale / am;
-            finv = am / kRunScale;
-        }
-    }
+    fixed_point_scale(*a.absmax, kRunScale, fscale, finv);
     for (int k = threadIdx.x; k < 2 * WW * TS; k += kTileThreads) sre[k] = A(0);
     __syncthreads();
 
@@ -834,13 +852,7 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
     const cplx<R_> *vis = reinterpret_cast<const cplx<R_> *>(a.vis);
     cplx<R_> *planes = reinterpret_cast<cplx<R_> *>(a.planes);
     R_ fscale = R_(1), finv = R_(1);
-    {
-        const float am = *a.absmax;
-        if (am > 0.f) {
-            fscale = kMfmaScale / am;
-            finv = am / kMfmaScale;
-        }
-    }
+    fixed_point_scale(*a.absmax, kMfmaScale, fscale, finv);
     const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
     const int qstart = max(0, wk.p0 - W + 1);
     const int qlast = min(wk.p1, bd.nj0);        // base planes qstart .. qlast - 1 can hold entries
@@ -1110,20 +1122,30 @@ __global__ __launch_bounds__(kThreads) void absmax_blocks_kernel(int vmode, cons
                                                                  const float *weight, const uint8_t *flag,
                                                                  int64_t n, float *partials) {
     __shared__ float red[kThreads / 64];
-    // squared magnitudes (the root is taken once, in the final kernel); every load is
-    // issued whatever the weight and flag, so that loads of later iterations overlap
-    float m = 0.f;
+    // per entry |w z| <= w hypot(|Re z|, |Im z|), the hypot formed without squaring
+    // in FP32 (max * sqrt(1 + (min / max)^2)); a NaN or infinite weight or value makes
+    // the bound infinite (x - x is then NaN).  Every load is issued whatever the
+    // weight and flag, so that loads of later iterations overlap.
+    float m = 0.f, bad = 0.f;
 #pragma unroll 4
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
         const float w = weight[e];
         const bool on = w > 0.f && !(flag && flag[e]);
-        float v = w * w;
+        float v = w;
         if (vmode != 1) {
             const cplx<float> z = vis[e];
-            v = (z.re * z.re + z.im * z.im) * (vmode == 0 ? w * w : 1.f);
+            const float ar = fabsf(z.re), ai = fabsf(z.im);
+            const float hi = fmaxf(ar, ai), lo = fminf(ar, ai);
+            const float t = hi > 0.f ? lo / hi : 0.f;
+            v = hi * sqrtf(1.f + t * t) * (vmode == 0 ? w : 1.f);
+            if (on) bad += (z.re - z.re) + (z.im - z.im);
         }
-        if (on) m = fmaxf(m, v);
+        if (on) {
+            m = fmaxf(m, v);
+            bad += v - v;
+        }
     }
+    if (bad != 0.f) m = INFINITY;   // NaN compares unequal to zero
     for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
@@ -1143,9 +1165,8 @@ __global__ __launch_bounds__(kThreads) void absmax_final_kernel(const float *par
     if (threadIdx.x == 0) {
         float t = 0.f;
         for (int k = 0; k < kThreads / 64; ++k) t = fmaxf(t, red[k]);
-        // partials hold squared magnitudes; margin so that rounding in z * phi * S
-        // never exceeds 2^31 - 1
-        out[0] = sqrtf(t) * 1.0001f;
+        // margin so that rounding in z * phi * S never exceeds 2^31 - 1
+        out[0] = t * 1.0001f;
     }
 }
 __global__ void absmax_clear_kernel(float *out) { out[0] = 0.f; }
@@ -1433,7 +1454,9 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
     const R w0 = (R)bd.w0, dw = (R)bd.dw, sc = (R)bd.sc;
     const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
 
-    R vmax2 = R(0);   // OMODE 1: largest |value|^2 written (scale of the FP32 spread that follows)
+    // OMODE 1: largest |Re| and |Im| of the values written (scale of the FP32 spread
+    // that follows); vbad turns NaN when a value is NaN or infinite (x - x)
+    R vmre = R(0), vmim = R(0), vbad = R(0);
     for (int q = wk.q0; q <= wk.q1; ++q) {
         const int64_t lo = max((int64_t)wk.e0, a.hoffsets[keybase + q]);
         const int64_t hi = min((int64_t)wk.e1, a.hoffsets[keybase + q + 1]);
@@ -1500,7 +1523,9 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
                 } else {
                     const cplx<R> o = acc * omega[e];
                     reinterpret_cast<cplx<R> *>(a.out)[h] = o;   // home-list order
-                    vmax2 = max(vmax2, o.re * o.re + o.im * o.im);
+                    vmre = max(vmre, fabsf(o.re));
+                    vmim = max(vmim, fabsf(o.im));
+                    vbad += (o.re - o.re) + (o.im - o.im);
                 }
             }
         }
@@ -1512,9 +1537,10 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
     }
     if constexpr (OMODE == 1) {
         if (a.absmax) {
-            float m = (float)vmax2;
+            // |value| <= hypot(max |Re|, max |Im|), formed in FP64 (no FP32 overflow of the
+            // squares); a NaN or infinite value makes the bound infinite
+            float m = vbad == R(0) ? (float)sqrt((double)vmre * vmre + (double)vmim * vmim) : INFINITY;
             for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-            m = sqrtf(m);
             // non-negative floats order like their bit patterns; the margin matches the pre-pass
             if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax(reinterpret_cast<unsigned *>(a.absmax), __float_as_uint(m * 1.0001f));
         }
@@ -2512,6 +2538,7 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(int op, const double *
     switch (op) {
         case RED_SET_RR:
             sc[S_RR] = t;
+            sc[S_RR0] = t;
             sc[S_BETA] = 0.0;
             break;
         case RED_ALPHA:

@@ -23,6 +23,7 @@ class Options:
     flat: bool = False          # drop the w term and 1/n (w = 0, n = 1)
     band_batch: int = 0         # bands whose w-planes are resident together (0 = all that fit)
     chunk: int = 0              # bucket entries per work item (0 = entries / compute units)
+    epsilon: float = 0.0        # requested grid/degrid accuracy: picks the support when support = 0
 
     def to_c(self) -> _lib.PfbOptions:
         o = _lib.PfbOptions()
@@ -33,6 +34,7 @@ class Options:
         o.flat = int(bool(self.flat))
         o.band_batch = int(self.band_batch)
         o.chunk = int(self.chunk)
+        o.epsilon = float(self.epsilon)
         return o
 
 
@@ -53,7 +55,7 @@ class Plan:
     the device tensors (the library borrows them)."""
 
     def __init__(self, uvw, freq, weight, flag, chan_band, n_band, nx, ny, cellx, celly,
-                 options: Options | None = None):
+                 options: Options | None = None, count_scratch: torch.Tensor | None = None):
         self.lib = _lib.load()
         self.opt = options or Options()
         self.real = torch.float64 if self.opt.precision == "fp64" else torch.float32
@@ -86,6 +88,13 @@ class Plan:
         _lib.check(self.lib.pfb_plan_create(ctypes.byref(handle), ctypes.byref(prob),
                                             ctypes.byref(copt), _stream()))
         self.handle = handle
+        # counting pass in a scratch buffer the caller may provide (it is free again on return)
+        cbytes = ctypes.c_size_t()
+        _lib.check(self.lib.pfb_plan_count_scratch_size(self.handle, ctypes.byref(cbytes)))
+        if count_scratch is None or count_scratch.numel() < cbytes.value:
+            count_scratch = torch.empty(max(int(cbytes.value), 256), dtype=torch.uint8, device=self.uvw.device)
+        _lib.check(self.lib.pfb_plan_count(self.handle, _ptr(count_scratch), count_scratch.numel(), _stream()))
+        del count_scratch
         nbytes = ctypes.c_size_t()
         _lib.check(self.lib.pfb_plan_workspace_size(self.handle, ctypes.byref(nbytes)))
         self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8,
@@ -201,15 +210,16 @@ class Plan:
         return out
 
     def precond_solve(self, g: torch.Tensor, sigma: float, iters: int,
-                      out: torch.Tensor | None = None, resid: torch.Tensor | None = None):
-        """(I^psf * + sigma Id) y = g by `iters` CG steps (eq. 8)."""
+                      out: torch.Tensor | None = None, resid: torch.Tensor | None = None, tol: float = 0.0):
+        """(I^psf * + sigma Id) y = g by `iters` CG steps (eq. 8); tol > 0 stops once every
+        band has ||r|| <= tol ||g|| (host-synchronising)."""
         self._chk(g, (self.n_band, self.nx, self.ny), self.real)
         out = self.image() if out is None else out
         self._chk(out, (self.n_band, self.nx, self.ny), self.real)
         if resid is not None:
             self._chk(resid, (self.n_band,), torch.float64)
         _lib.check(self.lib.pfb_precond_solve(self.handle, _ptr(g), _ptr(out), float(sigma), int(iters),
-                                              _ptr(resid), _stream()))
+                                              float(tol), _ptr(resid), _stream()))
         return out
 
     def power_iteration(self, v0: torch.Tensor, iters: int, op: str = "psf") -> torch.Tensor:

@@ -95,3 +95,38 @@ def test_shape_validation_without_gpu(lib):
     cb[1] = 3
     assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
     assert b"chan_band" in lib.pfb_last_error()
+
+
+def test_count_and_solve_arguments_without_gpu(lib):
+    """The counting pass and its scratch-size query need a plan; the solve's tol is
+    validated like its other scalars."""
+    n = ctypes.c_size_t(0)
+    assert lib.pfb_plan_count_scratch_size(None, ctypes.byref(n)) == -1
+    assert lib.pfb_plan_count(None, None, 0, None) == -1
+    assert lib.pfb_precond_solve(None, None, None, 1.0, 1, 0.0, None, None) == -1
+
+
+def test_epsilon_option_validation_without_gpu(lib):
+    """epsilon picks the support; a negative or non-finite value, or one below what the
+    precision reaches, is rejected before any device access."""
+    import numpy as np
+    from paper_2101_08072_amd import _lib
+    freq = np.array([1e9, 1.1e9])
+    cb = np.array([0, 0], np.int32)
+    prob = _lib.PfbProblem()
+    prob.n_row, prob.n_chan, prob.n_band = 10, 2, 1
+    prob.chan_band, prob.freq = cb.ctypes.data, freq.ctypes.data
+    prob.uvw, prob.weight = 16, 16            # never dereferenced: validation fails first
+    prob.nx, prob.ny, prob.cellx, prob.celly = 64, 64, 1e-4, 1e-4
+    h = ctypes.c_void_p()
+    opt = _lib.PfbOptions()
+    for bad in (-1e-3, float("nan"), float("inf")):
+        opt.epsilon = bad
+        assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
+        assert b"epsilon" in lib.pfb_last_error()
+    opt.epsilon = 1e-9                        # beyond the FP32 path (W <= 8)
+    assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
+    assert b"FP32" in lib.pfb_last_error()
+    opt.precision, opt.epsilon = 1, 1e-16     # beyond the FP64 path (W <= 16)
+    assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
+    assert b"FP64" in lib.pfb_last_error()

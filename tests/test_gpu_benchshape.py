@@ -1,0 +1,129 @@
+"""Oracle parity at the benchmark's image shape and solver regime (FP32 path).
+
+The timed step works on 2048^2 images: the PSF and the zero-padded convolution
+grid are 4096^2, sigma = 1e-3 lambda_max(I^psf *) (condition number ~1e3) and
+the CG solve of U y = g (eq. 8) runs 20 steps.  Here the same shapes and regime
+are compared element by element with the FP64 oracle on two bands with about
+1e3 active visibilities, so that the oracle's PSF stays a full direct sum (in
+its factored, matrix-product form): the PSF (eq. 4), the PSF convolution, the
+20-step solve of both bands (also reported against a converged FP64 solve) and
+one forward-backward step (eqs. 6-7), plus the early-stopping tolerance of the
+solve.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import TOL, host, make_plan, rel, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+N = 2048
+CG_ITERS = 20
+# k-step CG at condition ~1e3 in FP32: the FP32 PSF convolution carries ~1e-6
+# relative error per application and CG amplifies it by up to ~sqrt(kappa) per
+# reorthogonalisation-free step; 1e-4 (10x the tiny-size bound) is the stated bar.
+TOL_CG = 1e-4
+
+
+@pytest.fixture(scope="module")
+def bs():
+    import torch
+    say("bench shape: 2048^2, two bands, ~1e3 visibilities")
+    prob = synth.rotation_problem(synth.SEED_BASE + 20, N, 300, 4, n_band=2)
+    plan = make_plan(prob, "fp32")
+    say("bench shape: oracle PSF (factored direct sum)")
+    psf = oracle.psf_factored(prob)
+    conv = oracle.psf_conv_op(psf)
+    lam = [oracle.power_iteration(lambda v, b=b: conv.band(b, v), np.ones((N, N)), 20)[0] for b in range(2)]
+    sigma = 1e-3 * max(lam)
+    sky = synth.extended_sky(synth.SEED_BASE + 20, 2, N, N).astype(np.float64)
+    say(f"bench shape: lambda_max {lam}, sigma {sigma:.4g}")
+    torch.cuda.synchronize()
+    return dict(prob=prob, plan=plan, psf=psf, conv=conv, sigma=sigma, sky=sky)
+
+
+def test_psf_full_image(bs):
+    p = host(bs["plan"].make_psf())
+    e = rel(p, bs["psf"])
+    say(f"bench shape: PSF 2 x 4096^2 rel-l2 {e:.2e}")
+    assert e < TOL["fp32"]
+
+
+def test_psf_conv_full_image(bs):
+    import torch
+    y = host(bs["plan"].psf_conv(to_dev(bs["sky"], torch.float32)))
+    e = rel(y, bs["conv"](bs["sky"]))
+    say(f"bench shape: PSF convolution rel-l2 {e:.2e}")
+    assert e < TOL["fp32"]
+
+
+def test_precond_solve_bench_regime(bs):
+    """20 CG steps at sigma = 1e-3 lambda_max, both bands, against the same 20 FP64
+    steps; the distance of both to a converged FP64 solve is reported."""
+    import torch
+    g = bs["conv"](bs["sky"])
+    y = host(bs["plan"].precond_solve(to_dev(g, torch.float32), bs["sigma"], CG_ITERS))
+    y_ref, trace = oracle.precond_solve(bs["psf"], g, bs["sigma"], CG_ITERS, conv=bs["conv"])
+    e = rel(y, y_ref)
+    y_conv, tr_conv = oracle.precond_solve(bs["psf"], g, bs["sigma"], 150, conv=bs["conv"])
+    say(f"bench shape: CG {CG_ITERS} steps rel-l2 vs FP64 same steps {e:.2e}; vs converged FP64 "
+        f"solve: GPU {rel(y, y_conv):.2e}, FP64 {rel(y_ref, y_conv):.2e} (converged residual "
+        f"{np.sqrt(tr_conv[:, -1] / tr_conv[:, 0]).max():.1e})")
+    for b in range(2):
+        assert rel(y[b], y_ref[b]) < TOL_CG
+    assert e < TOL_CG
+
+
+def test_fb_step_bench_regime(bs):
+    import torch
+    prob = bs["prob"]
+    dirty = bs["conv"](bs["sky"])
+    x0 = 0.5 * bs["sky"]
+    lam = 1e-3 * np.abs(dirty).max()
+    xg = to_dev(x0, torch.float32)
+    bs["plan"].fb_step(to_dev(dirty, torch.float32), xg, bs["sigma"], 1.0, lam, CG_ITERS)
+    x_ref = oracle.fb_step(bs["psf"], dirty, x0, bs["sigma"], 1.0, lam, CG_ITERS, conv=bs["conv"])
+    e = rel(host(xg), x_ref)
+    say(f"bench shape: FB step rel-l2 {e:.2e} ({prob.n_band} bands)")
+    assert e < TOL_CG
+
+
+def test_precond_solve_tolerance_stops_early(bs):
+    """tol > 0: the solve stops at the first step with ||r|| <= tol ||g|| in every
+    band; the returned residual obeys it, the FP64 residual of the returned y agrees,
+    and the call is refused while the stream is being captured."""
+    import torch
+    from paper_2101_08072_amd import _lib
+    g = bs["conv"](bs["sky"])
+    gd = to_dev(g, torch.float32)
+    tol = 1e-2
+    resid = torch.empty(2, dtype=torch.float64, device="cuda")
+    y = host(bs["plan"].precond_solve(gd, bs["sigma"], 200, resid=resid, tol=tol))
+    r2 = host(resid)
+    g2 = (g.reshape(2, -1) ** 2).sum(axis=1)
+    assert (r2 <= tol * tol * g2 * (1 + 1e-3)).all()
+    r_true = np.stack([g[b] - bs["conv"].band(b, y[b]) - bs["sigma"] * y[b] for b in range(2)])
+    rel_res = np.sqrt((r_true.reshape(2, -1) ** 2).sum(axis=1) / g2)
+    say(f"bench shape: tol {tol}: device residual {np.sqrt(r2 / g2)}, FP64 residual of y {rel_res}")
+    assert (rel_res < 1.2 * tol).all()
+    # it stopped early: the solve to the same tolerance took fewer than 200 steps, so
+    # 200 fixed steps reach a much smaller residual
+    r2_fixed = torch.empty(2, dtype=torch.float64, device="cuda")
+    bs["plan"].precond_solve(gd, bs["sigma"], 200, resid=r2_fixed)
+    assert (host(r2_fixed) < 0.01 * r2).all()
+    s = torch.cuda.Stream()
+    refused = None
+    with torch.cuda.stream(s):
+        graph = torch.cuda.CUDAGraph()
+        try:
+            with torch.cuda.graph(graph, stream=s):
+                try:
+                    bs["plan"].precond_solve(gd, bs["sigma"], 5, tol=tol)
+                except _lib.PfbError as exc:
+                    refused = exc
+        except RuntimeError:
+            pass   # an empty capture may be reported by torch
+    torch.cuda.synchronize()
+    assert refused is not None and refused.status == -5

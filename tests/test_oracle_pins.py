@@ -347,3 +347,37 @@ def test_fb_step_scaled_delta_psf_closed_form(oracle_mod, gamma):
     assert np.abs(out - ref).max() < 1e-12
     # positivity is enforced and active; the threshold leaves some pixels positive
     assert (out >= 0).all() and (out == 0).any() and (out > 0).any()
+
+
+def test_factored_psf_equals_the_direct_sum(oracle_mod):
+    """The matrix-product form of the PSF sum (each phase split over the two axes)
+    agrees with the C direct sum, including the zeroed offset -n row and column, in
+    several bands with flags and a non-square image."""
+    p = synth.tiny_problem(seed=51, nx=24, ny=16, n_row=90, n_band=2, freqs=(1.0e9, 1.2e9, 1.3e9, 1.4e9),
+                           flag_frac=0.2)
+    ref = oracle_mod.psf(p)
+    got = oracle_mod.psf_factored(p)
+    assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_fft_convolution_operator_equals_direct_sum_and_library(oracle_mod):
+    """psf_conv_op (period-2n FFT, spectrum computed once) equals the plain O(N^4)
+    sum and scipy's full linear convolution, for several bands and a non-square
+    image; the CG and FB step give the same result with either convolution."""
+    p = synth.tiny_problem(seed=52, nx=12, ny=10, n_row=50, n_band=2, freqs=(1.0e9, 1.2e9))
+    P = oracle_mod.psf(p)
+    x = np.random.default_rng(53).normal(size=(2, 12, 10))
+    op = oracle_mod.psf_conv_op(P)
+    y = op(x)
+    for b in range(2):
+        d = oracle_mod.psf_conv_direct(P[b], x[b])
+        assert np.abs(y[b] - d).max() < 1e-12 * np.abs(d).max()
+    assert np.abs(y - oracle_mod.psf_conv(P, x)).max() < 1e-12 * np.abs(y).max()
+    g = np.random.default_rng(54).normal(size=(2, 12, 10))
+    y1, t1 = oracle_mod.precond_solve(P, g, 0.3, 7)
+    y2, t2 = oracle_mod.precond_solve(P, g, 0.3, 7, conv=op)
+    assert np.abs(y1 - y2).max() < 1e-10 * np.abs(y1).max()
+    x0 = np.abs(x)
+    f1 = oracle_mod.fb_step(P, g, x0, 0.3, 0.8, 0.01, 5)
+    f2 = oracle_mod.fb_step(P, g, x0, 0.3, 0.8, 0.01, 5, conv=op)
+    assert np.abs(f1 - f2).max() < 1e-10 * np.abs(f1).max()
