@@ -117,10 +117,11 @@ typedef struct {
                              default max(4096, entries / compute units of the device)       */
     double  epsilon;      /* requested relative accuracy of grid / degrid (rel-l2); when
                              support is 0 and epsilon > 0 the support is the smallest W whose
-                             tabulated error of the 3-D ES product kernel at sigma = 2 is
-                             <= epsilon (FP32: W 4..8, reach ~3e-7; FP64: W 9..16, reach
-                             ~5e-15); a smaller epsilon than the precision reaches is
-                             PFB_EINVAL.  0: the default support.                          */
+                             tabulated error of the 3-D ES product kernel at sigma = 2 plus
+                             the arithmetic's rounding floor is <= epsilon (FP32: W 4..8,
+                             reach ~2.3e-6; FP64: W 9..16, reach ~1.5e-14); a smaller
+                             epsilon than the precision reaches is PFB_EINVAL.  0: the
+                             default support.                                               */
     int32_t reserved[6];
 } pfb_options;
 

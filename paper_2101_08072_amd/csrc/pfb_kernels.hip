@@ -399,6 +399,10 @@ hipError_t launch_corr1d(bool dbl, int n, int gsize, const double *cheb, int nch
 // FP64 path: the ring holds doubles updated with LDS float atomics.
 constexpr int kTileThreads = 1024;   // 16 waves share one tile's LDS ring
 
+// true for an infinite or NaN float (all exponent bits set); a bit test, so that no
+// floating-point contraction or fast-math assumption can change it
+__device__ __forceinline__ bool not_finite(float x) { return (__float_as_uint(x) & 0x7f800000u) == 0x7f800000u; }
+
 // Fixed-point scale of the FP32 spread from am >= max |z| of the values spread:
 // contributions are z * phi * fscale with |.| <= S, and the stored sums are
 // multiplied by finv.  am = 0 means every value is zero (exact zero grid).  An
@@ -1123,10 +1127,11 @@ __global__ __launch_bounds__(kThreads) void absmax_blocks_kernel(int vmode, cons
                                                                  int64_t n, float *partials) {
     __shared__ float red[kThreads / 64];
     // per entry |w z| <= w hypot(|Re z|, |Im z|), the hypot formed without squaring
-    // in FP32 (max * sqrt(1 + (min / max)^2)); a NaN or infinite weight or value makes
-    // the bound infinite (x - x is then NaN).  Every load is issued whatever the
-    // weight and flag, so that loads of later iterations overlap.
-    float m = 0.f, bad = 0.f;
+    // in FP32 (max * sqrt(1 + (min / max)^2)); a NaN or infinite weight, value or
+    // product makes the bound infinite.  Every load is issued whatever the weight
+    // and flag, so that loads of later iterations overlap.
+    float m = 0.f;
+    bool bad = false;
 #pragma unroll 4
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
         const float w = weight[e];
@@ -1138,14 +1143,14 @@ __global__ __launch_bounds__(kThreads) void absmax_blocks_kernel(int vmode, cons
             const float hi = fmaxf(ar, ai), lo = fminf(ar, ai);
             const float t = hi > 0.f ? lo / hi : 0.f;
             v = hi * sqrtf(1.f + t * t) * (vmode == 0 ? w : 1.f);
-            if (on) bad += (z.re - z.re) + (z.im - z.im);
+            if (on) bad = bad || not_finite(z.re) || not_finite(z.im);
         }
         if (on) {
             m = fmaxf(m, v);
-            bad += v - v;
+            bad = bad || not_finite(v);
         }
     }
-    if (bad != 0.f) m = INFINITY;   // NaN compares unequal to zero
+    if (bad) m = INFINITY;
     for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
@@ -1455,8 +1460,9 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
     const int64_t keybase = ((int64_t)wk.band * ntiles + wk.tile) * a.g.nj0max;
 
     // OMODE 1: largest |Re| and |Im| of the values written (scale of the FP32 spread
-    // that follows); vbad turns NaN when a value is NaN or infinite (x - x)
-    R vmre = R(0), vmim = R(0), vbad = R(0);
+    // that follows); vbad: some value is NaN or infinite
+    R vmre = R(0), vmim = R(0);
+    bool vbad = false;
     for (int q = wk.q0; q <= wk.q1; ++q) {
         const int64_t lo = max((int64_t)wk.e0, a.hoffsets[keybase + q]);
         const int64_t hi = min((int64_t)wk.e1, a.hoffsets[keybase + q + 1]);
@@ -1525,7 +1531,7 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
                     reinterpret_cast<cplx<R> *>(a.out)[h] = o;   // home-list order
                     vmre = max(vmre, fabsf(o.re));
                     vmim = max(vmim, fabsf(o.im));
-                    vbad += (o.re - o.re) + (o.im - o.im);
+                    vbad = vbad || not_finite(o.re) || not_finite(o.im);
                 }
             }
         }
@@ -1539,7 +1545,7 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
         if (a.absmax) {
             // |value| <= hypot(max |Re|, max |Im|), formed in FP64 (no FP32 overflow of the
             // squares); a NaN or infinite value makes the bound infinite
-            float m = vbad == R(0) ? (float)sqrt((double)vmre * vmre + (double)vmim * vmim) : INFINITY;
+            float m = vbad ? INFINITY : (float)sqrt((double)vmre * vmre + (double)vmim * vmim);
             for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
             // non-negative floats order like their bit patterns; the margin matches the pre-pass
             if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax(reinterpret_cast<unsigned *>(a.absmax), __float_as_uint(m * 1.0001f));
