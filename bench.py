@@ -45,14 +45,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="single-band-2048")
+    ap.add_argument("--workload", default="batched-8x4096")
     ap.add_argument("--cg-iters", type=int, default=20)
     ap.add_argument("--support", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-fp64-baseline", action="store_true")
-    ap.add_argument("--band-batch-compare", action="store_true",
-                    help="also time the Hessian with one band per launch (FP32)")
+    ap.add_argument("--no-band-batch-compare", action="store_true",
+                    help="skip timing the Hessian with one band per launch (FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of one HIP graph per step")
@@ -333,6 +333,7 @@ def main():
     wall = time.perf_counter() - w0
     ms_step = e0.elapsed_time(e1) / args.steps
     value = 2.0 * M / (ms_step * 1e-3)
+    used_graph = run is not step
     log(f"step {ms_step:.3f} ms (wall {wall / args.steps * 1e3:.3f} ms, {'graph' if run is not step else 'eager'}); "
         f"{value:.4g} vis/s")
     # per-kernel times: the same steps launched eagerly with HIP events around every kernel
@@ -394,6 +395,18 @@ def main():
     del prox_ws
     grid_degrid_vis_s = M / ((breakdown["grid"] + breakdown["degrid"]) * 1e-3)
     hess_apps = 1e3 / breakdown["hessian"]
+    # PSF convolution (eq. 4) and one CG step (eq. 8) against HBM: algorithmic bytes of
+    # the three-pass zero-padded FFT convolution, 48 B per pixel and band (x read, the
+    # row spectrum written and read twice, the PSF spectrum read, y written), and for a
+    # CG step that plus 36 B per pixel of vector updates
+    Pb = prob.n_band * prob.nx * prob.ny
+
+    def hbm(bytes_, ms):
+        ach = bytes_ / (ms * 1e-3) / 1e9
+        return {"bytes": bytes_, "ms": round(ms, 4), "achieved_GBps": round(ach, 1),
+                "frac": round(ach / PEAK["hbm_GBps"], 4)}
+    psf_hbm = hbm(48 * Pb, breakdown["psf_conv"])
+    cg_hbm = hbm(84 * Pb, breakdown["cg_solve"] / max(args.cg_iters, 1))
 
     # dominant kernel and its roofline
     W = info["support"]
@@ -449,31 +462,65 @@ def main():
                 "kernels": prox_k}
     log("prox:", json.dumps(prox_out))
 
-    # plain per-band FP64 path on the same GPU (Hessian applications/s)
+    # sampled parity against the FP64 oracle at the full size (every band sampled)
+    parity = None
+    vis_host = None
+    if not args.no_parity or not args.no_cpu_baseline:
+        vis_host = vis.cpu().numpy()
+    if not args.no_parity:
+        import oracle
+        rng = np.random.default_rng(3)
+        P = prob.nx * prob.ny
+        pix = np.concatenate([b * P + rng.integers(0, P, 16) for b in range(prob.n_band)])
+        plan.grid(vis, out=dirty)
+        d = dirty.cpu().numpy().ravel()[pix]
+        d_ref = oracle.grid(prob, vis_host, pix=pix)
+        active = np.flatnonzero(prob.effective_weight().ravel())
+        sel = rng.choice(active, 128, replace=False)
+        v_ref = oracle.degrid(prob, x_true.astype(np.float64), sel=sel)
+        xs = np.zeros_like(x_true)
+        for b in range(prob.n_band):
+            xs[b].ravel()[rng.integers(0, P, 40)] = rng.uniform(0.1, 1.0, 40)
+        hs = plan.hessian(torch.as_tensor(xs, device=dev)).cpu().numpy().ravel()[pix]
+        hs_ref = oracle.hessian(prob, xs, pix=pix)
+        parity = {"dirty_image": oracle.rel_l2(d, d_ref), "degrid": oracle.rel_l2(vis_host.ravel()[sel], v_ref),
+                  "hessian": oracle.rel_l2(hs, hs_ref),
+                  "sample": f"16 random pixels per band ({pix.size} in all: dirty image, Hessian of a "
+                            f"40-source sparse sky per band), 128 random visibilities (degrid)"}
+        log("parity", parity)
+
+    # the FP32 Hessian of x_true for the precision comparison, then free the batched plan
+    h32_host = plan.hessian(xg, out=hx).double().cpu().numpy()
+    graph = None
+    del plan, step, run, graph, vis, dirty, vmod, hx, xk, xp, xc
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+
+    # plain per-band FP64 path on the same GPU (Hessian applications/s): one band per
+    # launch (band_batch = 1), everything in FP64 with W = 13
     plain = None
     if not args.no_fp64_baseline:
         try:
-            del_list = [dirty, vmod]
             p64 = Plan.from_problem(prob, device=dev, options=Options(precision="fp64", band_batch=1))
             x64 = xg.double()
             h64 = p64.image()
             t64 = timed(lambda: p64.hessian(x64, out=h64), n=2)
-            plain = {"precision": "fp64", "support": p64.info()["support"], "tile": p64.info()["tile"],
+            i64 = p64.info()
+            plain = {"precision": "fp64", "support": i64["support"], "tile": i64["tile"], "band_batch": 1,
                      "hessian_ms": round(t64, 3), "hessian_apps_per_s": round(1e3 / t64, 3),
-                     "speedup_fp32_over_fp64": round(t64 / breakdown["hessian"], 2)}
-            h32 = hx
-            plan.hessian(xg, out=h32)
-            torch.cuda.synchronize()
-            a, b = h32.double().cpu().numpy(), h64.cpu().numpy()
-            plain["fp32_vs_fp64_hessian_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
-            del p64, x64, h64, del_list
+                     "speedup_batched_fp32_over_plain_fp64": round(t64 / breakdown["hessian"], 2)}
+            b64 = h64.cpu().numpy()
+            plain["fp32_vs_fp64_hessian_rel_l2"] = float(np.linalg.norm(h32_host - b64) / np.linalg.norm(b64))
+            log("plain fp64", plain)
+            del p64, x64, h64
         except Exception as exc:  # report, do not hide
             plain = {"error": str(exc)}
         torch.cuda.empty_cache()
 
     # all bands in one launch vs one band per launch (same FP32 kernels)
     per_band = None
-    if args.band_batch_compare and prob.n_band > 1:
+    if not args.no_band_batch_compare and prob.n_band > 1:
         pb = Plan.from_problem(prob, device=dev, options=Options(precision="fp32", band_batch=1,
                                                                  support=args.support, tile=args.tile))
         hb = pb.image()
@@ -484,33 +531,6 @@ def main():
         torch.cuda.empty_cache()
         log("one band per launch", per_band)
 
-    # sampled parity against the FP64 oracle at the full size
-    parity = None
-    vis_host = None
-    if not args.no_parity or not args.no_cpu_baseline:
-        vis_host = vis.cpu().numpy()
-    if not args.no_parity:
-        import oracle
-        rng = np.random.default_rng(3)
-        P = prob.nx * prob.ny
-        pix = rng.integers(0, P, 16)
-        plan.grid(vis, out=dirty)
-        d = dirty.cpu().numpy().ravel()[pix]
-        d_ref = oracle.grid(prob, vis_host, pix=pix)
-        active = np.flatnonzero(prob.effective_weight().ravel())
-        sel = rng.choice(active, 128, replace=False)
-        v_ref = oracle.degrid(prob, x_true.astype(np.float64), sel=sel)
-        xs = np.zeros_like(x_true)
-        idx = rng.integers(0, P, 40)
-        xs[0].ravel()[idx] = rng.uniform(0.1, 1.0, 40)
-        hs = plan.hessian(torch.as_tensor(xs, device=dev)).cpu().numpy().ravel()[pix]
-        hs_ref = oracle.hessian(prob, xs, pix=pix)
-        parity = {"dirty_image": oracle.rel_l2(d, d_ref), "degrid": oracle.rel_l2(vis_host.ravel()[sel], v_ref),
-                  "hessian": oracle.rel_l2(hs, hs_ref),
-                  "sample": "16 random pixels (dirty image, Hessian of a 40-source sparse sky), "
-                            "128 random visibilities (degrid)"}
-        log("parity", parity)
-
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, vis_host, x_true.astype(np.float64), M, args.cpu_seconds)
@@ -519,7 +539,7 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "visibilities/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
-        "hip_graph": run is not step,
+        "hip_graph": used_graph,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded VLA-like earth-rotation uvw, 10% flags, 500 points + 20 blobs)",
         "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "n_band": prob.n_band,
@@ -533,6 +553,8 @@ def main():
         "plain_fp64": plain,
         "one_band_per_launch": per_band,
         "breakdown_ms": {k: round(v, 4) for k, v in breakdown.items()},
+        "psf_conv_hbm": psf_hbm,
+        "cg_iteration_hbm": cg_hbm,
         "kernels": kernels,
         "prox": prox_out,
         "clean": clean_out,

@@ -835,9 +835,11 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
                     opt.support, gridder_lds_bytes(dbl, opt.support, opt.tile, opt.flat != 0), kMaxLdsBytes);
     if (opt.flat != 0 && opt.flat != 1) return fail(PFB_EINVAL, "flat must be 0 or 1");
     if (opt.chunk != 0 && opt.chunk < 64) return fail(PFB_EINVAL, "chunk must be >= 64");
-    // FFT length limits (LDS-resident rows)
+    // FFT length limits (LDS-resident rows): the operator's grid rows have 2n points,
+    // the PSF gridder's (a 2n x 2n image) 4n; in FP64 the latter stop at n = 2048, so
+    // larger FP64 plans serve grid, degrid and the Hessian but not the PSF
     const int max_row = dbl ? 8192 : 16384;
-    if (4 * pr.nx > max_row || 4 * pr.ny > max_row)
+    if (2 * pr.nx > max_row || 2 * pr.ny > max_row)
         return fail(PFB_EUNSUPPORTED, "image %d x %d needs FFT rows longer than %d for this precision", pr.nx, pr.ny,
                     max_row);
     const double lmax2 = std::pow(0.5 * pr.nx * pr.cellx, 2) + std::pow(0.5 * pr.ny * pr.celly, 2);
@@ -1234,6 +1236,9 @@ pfb_status pfb_grid(pfb_plan *P, const void *vis, void *image, int mode, hipStre
     }
     if (mode == PFB_GRID_PSF) {
         GridderHost &G = P->psf;
+        if (G.g.gx > (d ? 8192 : 16384) || G.g.gy > (d ? 8192 : 16384))
+            return fail(PFB_EUNSUPPORTED, "the PSF of a %d x %d image needs FFT rows of %d points, longer than this "
+                        "precision's %d", P->prob.nx, P->prob.ny, std::max(G.g.gx, G.g.gy), d ? 8192 : 16384);
         void *img = image ? image : P->p(P->o_psfimg);
         st = spread_prepass(P, 1, nullptr, s);
         if (st) return st;

@@ -85,8 +85,8 @@ def test_shape_validation_without_gpu(lib):
     assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
     assert b"LDS" in lib.pfb_last_error()
     opt.tile = 0
-    # FP64 mode: the PSF rows (4n points) must fit LDS in FP64, so 2048 is its largest side
-    prob.nx, prob.ny, prob.cellx, prob.celly = 4096, 4096, 1e-6, 1e-6
+    # FP64 mode: the operator's rows (2n points) must fit LDS in FP64, so 4096 is its largest side
+    prob.nx, prob.ny, prob.cellx, prob.celly = 8192, 8192, 1e-7, 1e-7
     opt.precision = 1
     assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -4
     assert b"FFT rows" in lib.pfb_last_error()
