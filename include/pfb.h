@@ -167,6 +167,16 @@ pfb_status pfb_plan_count_scratch_size(const pfb_plan *plan, size_t *bytes);
  * negative or infinite.  Once per plan (PFB_ESTATE on a second call). */
 pfb_status pfb_plan_count(pfb_plan *plan, void *scratch, size_t bytes, hipStream_t stream);
 
+/* pfb_plan_count without a scratch argument, for callers that cannot allocate
+ * device memory at all: the counting pass runs in a fixed 64 MiB buffer that the
+ * library holds on every device it runs on until the process ends (allocated when
+ * the library's code is loaded, not by this call, which allocates nothing).  A plan
+ * whose pfb_plan_count_scratch_size exceeds 64 MiB gets PFB_ENOMEM.  The buffer is
+ * shared by every call on a device and cleared by each call where it must start at
+ * zero; calls that overlap on one device (other threads, other streams) race and
+ * must be serialised by the caller.  Otherwise as pfb_plan_count. */
+pfb_status pfb_plan_count_static(pfb_plan *plan, hipStream_t stream);
+
 /* Bytes of device workspace the plan needs (256-byte aligned pointer expected);
  * valid after pfb_plan_count. */
 pfb_status pfb_plan_workspace_size(const pfb_plan *plan, size_t *bytes);

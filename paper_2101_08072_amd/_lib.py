@@ -15,7 +15,8 @@ STATUS_NAMES = {0: "PFB_OK", -1: "PFB_EINVAL", -2: "PFB_ENOMEM", -3: "PFB_EHIP",
                 -4: "PFB_EUNSUPPORTED", -5: "PFB_ESTATE"}
 
 # every symbol include/pfb.h declares
-EXPORTS = ["pfb_plan_create", "pfb_plan_count_scratch_size", "pfb_plan_count", "pfb_plan_workspace_size", "pfb_plan_set_workspace",
+EXPORTS = ["pfb_plan_create", "pfb_plan_count_scratch_size", "pfb_plan_count", "pfb_plan_count_static",
+           "pfb_plan_workspace_size", "pfb_plan_set_workspace",
            "pfb_plan_get_info", "pfb_plan_destroy", "pfb_grid", "pfb_degrid", "pfb_hessian",
            "pfb_psf_conv", "pfb_precond_solve", "pfb_power_iteration", "pfb_fb_step",
            "pfb_fb_graph_create", "pfb_graph_launch", "pfb_graph_destroy",
@@ -69,6 +70,7 @@ def load():
         "pfb_plan_create": [plan_pp, ctypes.POINTER(PfbProblem), ctypes.POINTER(PfbOptions), vp],
         "pfb_plan_count_scratch_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "pfb_plan_count": [vp, vp, sz, vp],
+        "pfb_plan_count_static": [vp, vp],
         "pfb_plan_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "pfb_plan_set_workspace": [vp, vp, sz, vp],
         "pfb_plan_get_info": [vp, ctypes.POINTER(PfbPlanInfo)],

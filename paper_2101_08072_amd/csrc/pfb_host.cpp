@@ -955,6 +955,19 @@ pfb_status pfb_plan_count(pfb_plan *P, void *scratch, size_t bytes, hipStream_t 
     return count_and_layout(P, reinterpret_cast<char *>(scratch), stream);
 }
 
+pfb_status pfb_plan_count_static(pfb_plan *P, hipStream_t stream) {
+    if (!P) return fail(PFB_EINVAL, "plan is NULL");
+    if (P->counted) return fail(PFB_ESTATE, "the plan has already been counted");
+    const CountLayout cl = count_layout(*P);
+    if (cl.total > kStaticScratchBytes)
+        return fail(PFB_ENOMEM, "the counting pass needs %zu bytes, more than the %zu of the library's fixed buffer "
+                    "(use pfb_plan_count with a caller buffer)", cl.total, kStaticScratchBytes);
+    void *buf = nullptr;
+    hipError_t e = static_scratch(&buf);
+    if (e != hipSuccess) return fail(PFB_EHIP, "looking up the fixed count buffer: %s", hipGetErrorString(e));
+    return count_and_layout(P, reinterpret_cast<char *>(buf), stream);
+}
+
 pfb_status pfb_plan_workspace_size(const pfb_plan *P, size_t *bytes) {
     if (!P || !bytes) return fail(PFB_EINVAL, "NULL argument");
     if (!P->counted) return fail(PFB_ESTATE, "pfb_plan_count has not been called");

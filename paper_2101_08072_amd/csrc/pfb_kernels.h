@@ -26,6 +26,10 @@ void set_thread_profiler(Profiler *p);
 // All launchers return hipSuccess or the launch error; `dbl` selects float64.
 
 hipError_t launch_count(bool dbl, const BucketArgs &a, hipStream_t s);
+// Fixed device buffer for callers that cannot allocate (pfb_plan_count_static):
+// its device address on the current device (looked up once per device) and size.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+hipError_t static_scratch(void **ptr);
 hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s);
 // home-entry list: items as for launch_sort (after it), hoffsets per bucket
 hipError_t launch_home_list(bool dbl, const void *recs, const int64_t *items, int n_items, const int64_t *hoffsets,

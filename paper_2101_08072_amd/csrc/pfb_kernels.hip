@@ -10,6 +10,7 @@
 
 #include "pfb_kernels.h"
 #include <limits>
+#include <mutex>
 
 namespace pfb {
 
@@ -253,6 +254,31 @@ static hipError_t launch_bucket(bool dbl, const BucketArgs &a, hipStream_t s) {
     return hipSuccess;
 }
 hipError_t launch_count(bool dbl, const BucketArgs &a, hipStream_t s) { return launch_bucket<false>(dbl, a, s); }
+
+// The counting scratch of pfb_plan_count_static.  In host code `scratch` names a
+// host-side stand-in, never device memory: its device address is looked up per
+// device with hipGetSymbolAddress (each device holds its own copy) and only that
+// address reaches kernels, memsets and copies.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void **ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 hipError_t launch_scatter(bool dbl, const BucketArgs &a, hipStream_t s) { return launch_bucket<true>(dbl, a, s); }
 
 // Home-entry list of every bucket (plan time): the positions of the entries

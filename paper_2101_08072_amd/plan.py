@@ -55,7 +55,7 @@ class Plan:
     the device tensors (the library borrows them)."""
 
     def __init__(self, uvw, freq, weight, flag, chan_band, n_band, nx, ny, cellx, celly,
-                 options: Options | None = None, count_scratch: torch.Tensor | None = None):
+                 options: Options | None = None, count_scratch: torch.Tensor | str | None = None):
         self.lib = _lib.load()
         self.opt = options or Options()
         self.real = torch.float64 if self.opt.precision == "fp64" else torch.float32
@@ -88,13 +88,19 @@ class Plan:
         _lib.check(self.lib.pfb_plan_create(ctypes.byref(handle), ctypes.byref(prob),
                                             ctypes.byref(copt), _stream()))
         self.handle = handle
-        # counting pass in a scratch buffer the caller may provide (it is free again on return)
-        cbytes = ctypes.c_size_t()
-        _lib.check(self.lib.pfb_plan_count_scratch_size(self.handle, ctypes.byref(cbytes)))
-        if count_scratch is None or count_scratch.numel() < cbytes.value:
-            count_scratch = torch.empty(max(int(cbytes.value), 256), dtype=torch.uint8, device=self.uvw.device)
-        _lib.check(self.lib.pfb_plan_count(self.handle, _ptr(count_scratch), count_scratch.numel(), _stream()))
-        del count_scratch
+        # counting pass in a scratch buffer the caller may provide (it is free again on
+        # return), or with count_scratch="static" in the library's fixed device buffer
+        if isinstance(count_scratch, str):
+            if count_scratch != "static":
+                raise ValueError("count_scratch must be a device tensor, None or 'static'")
+            _lib.check(self.lib.pfb_plan_count_static(self.handle, _stream()))
+        else:
+            cbytes = ctypes.c_size_t()
+            _lib.check(self.lib.pfb_plan_count_scratch_size(self.handle, ctypes.byref(cbytes)))
+            if count_scratch is None or count_scratch.numel() < cbytes.value:
+                count_scratch = torch.empty(max(int(cbytes.value), 256), dtype=torch.uint8, device=self.uvw.device)
+            _lib.check(self.lib.pfb_plan_count(self.handle, _ptr(count_scratch), count_scratch.numel(), _stream()))
+            del count_scratch
         nbytes = ctypes.c_size_t()
         _lib.check(self.lib.pfb_plan_workspace_size(self.handle, ctypes.byref(nbytes)))
         self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8,
@@ -103,7 +109,7 @@ class Plan:
                                                    self.workspace.numel(), _stream()))
 
     @classmethod
-    def from_problem(cls, prob, device="cuda", options: Options | None = None):
+    def from_problem(cls, prob, device="cuda", options: Options | None = None, count_scratch=None):
         """Build from a ``synth.Problem`` (host numpy arrays)."""
         options = options or Options()
         real = torch.float64 if options.precision == "fp64" else torch.float32
@@ -111,7 +117,7 @@ class Plan:
         weight = torch.as_tensor(np.asarray(prob.weight), device=device).to(real)
         flag = None if prob.flag is None else torch.as_tensor(prob.flag, dtype=torch.uint8, device=device)
         return cls(uvw, prob.freq, weight, flag, prob.chan_band, prob.n_band, prob.nx, prob.ny,
-                   prob.cellx, prob.celly, options)
+                   prob.cellx, prob.celly, options, count_scratch)
 
     def __del__(self):
         h = getattr(self, "handle", None)
