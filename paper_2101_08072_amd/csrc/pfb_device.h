@@ -223,6 +223,63 @@ __device__ __forceinline__ void lds_fft(cplx<R> *buf, int C, int ld, const TwTab
     }
 }
 
+// One decimation-in-frequency stage: the transpose of dit_stage (the radix-RAD
+// DFT first, then the twiddles of the same butterfly).
+template <typename R, bool INV, int RAD, int LOG2L, int NT>
+__device__ __forceinline__ void dif_stage(cplx<R> *buf, int C, int ld, int m, const TwTab<R> &tw, int tw_shift) {
+    constexpr int L = 1 << LOG2L;
+    constexpr int NB = L / RAD;
+    const int total = NB * C;
+    const int estep = (L / (RAD * m)) << tw_shift;
+    for (int id = threadIdx.x; id < total; id += NT) {
+        const int c = id / NB;
+        const int bfly = id - c * NB;
+        const int j = bfly % m;
+        const int g = bfly / m;
+        cplx<R> *vb = buf + c * ld + Lds<R, LOG2L>::pad(g * RAD * m + j);
+        cplx<R> v[RAD];
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) v[t] = vb[Lds<R, LOG2L>::pad(t * m)];
+        dft_small<R, INV, RAD>(v);
+        if (m > 1) stage_twiddles<R, INV, RAD>(v, tw, j * estep);
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) vb[Lds<R, LOG2L>::pad(t * m)] = v[t];
+    }
+}
+
+// In-place FFT of C vectors given in natural order at Lds::pad(n); the result
+// X[k] is left at Lds::pad(dit_pos<LOG2L>(k)), which is the input order of
+// lds_fft.  The DFT matrix is symmetric, so the transpose of lds_fft's sequence
+// (stages in reverse order, each transposed) computes it.  Ends with a barrier.
+template <typename R, bool INV, int LOG2L, int NT = kThreads>
+__device__ __forceinline__ void lds_fft_dif(cplx<R> *buf, int C, int ld, const TwTab<R> &tw, int tw_shift) {
+    using P = FftPlan<LOG2L>;
+    int m = P::L;
+#pragma unroll
+    for (int st = P::NSTAGE - 1; st >= 0; --st) {
+        const int RAD = P::radix(st);
+        m /= RAD;   // span of DIT stage st: the product of the radices before it
+        if (RAD == 2) dif_stage<R, INV, 2, LOG2L, NT>(buf, C, ld, m, tw, tw_shift);
+        else if (RAD == 4) dif_stage<R, INV, 4, LOG2L, NT>(buf, C, ld, m, tw, tw_shift);
+        else dif_stage<R, INV, 8, LOG2L, NT>(buf, C, ld, m, tw, tw_shift);
+        __syncthreads();
+    }
+}
+
+// Inverse of dit_pos: the input index n whose DIT position is q.
+template <int LOG2L> __device__ __forceinline__ int dit_inv(int q) {
+    using P = FftPlan<LOG2L>;
+    int n = 0, W = P::L, x = q;
+#pragma unroll
+    for (int st = 0; st < P::NSTAGE; ++st) {
+        const int R = P::radix(st);
+        W /= R;   // weight of this digit in n: the product of the later stages' radices
+        n += (x % R) * W;
+        x /= R;
+    }
+    return n;
+}
+
 // base-8 digit reversal of q over D digits
 template <int D> __device__ __forceinline__ int rev8(int q) {
     int r = 0;

@@ -213,7 +213,7 @@ struct pfb_plan {
     int64_t n_active = 0, n_flagged = 0;
     double s_min = 0.0;
     int band_batch = 1;
-    ColSplit ccs{};
+    int conv_cgc = 1;
     int ldh = 0;
     int log2_lmax = 0;
     std::vector<double> cheb;
@@ -228,7 +228,7 @@ struct pfb_plan {
     bool counted = false, ws_ready = false, psf_ready = false;
     size_t o_freq = 0, o_cb = 0, o_cheb = 0, o_tw = 0, o_flagged = 0, o_flagcur = 0;
     size_t o_planes = 0, o_t1 = 0, o_t2 = 0, o_vals = 0, o_psfimg = 0;
-    size_t o_t1c = 0, o_t2c = 0, o_psfhat = 0, o_vec = 0, o_partials = 0, o_scal = 0, o_absmax = 0;
+    size_t o_t1c = 0, o_psfhat = 0, o_vec = 0, o_partials = 0, o_scal = 0, o_absmax = 0;
     size_t planes_bytes = 0, t_bytes = 0, vec_bytes = 0;
     size_t o_sorttmp = 0;   // scratch for the plan-time sort (aliases the w-plane area when it fits)
     Profiler prof;
@@ -396,11 +396,10 @@ ConvArgs conv_args(const pfb_plan *P) {
     a.nx = P->prob.nx;
     a.ny = P->prob.ny;
     a.ldh = P->ldh;
-    a.cs = P->ccs;
+    a.cgc = P->conv_cgc;
     a.tw = P->p(P->o_tw);
     a.log2_lmax = P->log2_lmax;
     a.t1c = P->p(P->o_t1c);
-    a.t2c = P->p(P->o_t2c);
     a.psfhat = P->p(P->o_psfhat);
     a.partials = reinterpret_cast<double *>(P->p(P->o_partials));
     a.max_partials = P->max_partials;
@@ -693,7 +692,7 @@ pfb_status count_and_layout(pfb_plan *P, char *tmp, hipStream_t stream) {
         P->tw_host[2 * e2] = std::cos(a);
         P->tw_host[2 * e2 + 1] = std::sin(a);
     }
-    P->ccs = make_split(2 * pr.nx);
+    P->conv_cgc = conv_group_cols(dbl, pr.nx);
     P->ldh = ((pr.ny + 1 + 15) / 16) * 16;
 
     // band batch
@@ -758,7 +757,6 @@ pfb_status count_and_layout(pfb_plan *P, char *tmp, hipStream_t stream) {
     P->o_vals = L.take((size_t)pr.n_row * pr.n_chan * csz);
     P->o_psfimg = L.take((size_t)nb * 4 * Pimg * P->rsz);
     P->o_t1c = L.take((size_t)nb * 2 * pr.nx * P->ldh * csz);
-    P->o_t2c = L.take(P->ccs.n2 > 1 ? (size_t)nb * 2 * pr.nx * P->ldh * csz : 256);
     P->o_psfhat = L.take((size_t)nb * 2 * pr.nx * P->ldh * P->rsz);
     P->vec_bytes = ((Pimg * nb * P->rsz) + 255) & ~size_t(255);
     P->o_vec = L.take(6 * P->vec_bytes);

@@ -133,12 +133,12 @@ hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s);  //
 
 // PSF convolution machinery.
 struct ConvArgs {
-    int n_band, nx, ny, ldh;   // image nx x ny; half-spectrum row stride ldh >= ny + 1
-    ColSplit cs;               // factorisation of 2 nx
+    int n_band, nx, ny, ldh;   // image nx x ny; per-band stride 2 nx ldh, ldh >= ny + 1 rounded to 16
+    int cgc;                   // columns per group of the group-major layout (conv_group_cols)
     const void *tw;
     int log2_lmax;
-    void *t1c, *t2c;           // [n_band][2nx][ldh] complex
-    void *psfhat;              // [n_band][2nx][ldh] real (four-step order when split)
+    void *t1c;                 // [n_band][2nx ldh] complex: row spectra, group-major
+    void *psfhat;              // [n_band][2nx ldh] real: PSF spectrum, group-major, even/odd split
     double *partials;          // [n_band][max_partials]
     int max_partials;
     double *scal;              // [n_band][8] device scalars
@@ -152,6 +152,8 @@ enum ConvOut { CONV_OUT_Y = 0, CONV_OUT_SUB = 1, CONV_OUT_CG = 2, CONV_OUT_NORM 
 //       CONV_OUT_CG  : y = conv + sigma p, partial p . y  (CG, aux_out = p)
 //       CONV_OUT_NORM: partial y . y
 //       CONV_OUT_DOT : partial aux_out . y
+// columns per group of the convolution's group-major layout for images of nx rows
+int conv_group_cols(bool dbl, int nx);
 hipError_t launch_psf_conv(bool dbl, const ConvArgs &a, const void *x, void *aux_in, void *y,
                            const void *aux_out, double sigma, int in_mode, int out_mode,
                            hipStream_t s);

@@ -2052,6 +2052,15 @@ hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s) {
 // PSF convolution on the 2nx x 2ny zero-padded grid
 // ---------------------------------------------------------------------------
 
+// Blocks go to the eight XCDs in turn (block i on XCD i mod 8).  For a grid that
+// is a multiple of 8 this returns the logical block of block i such that each XCD
+// runs one contiguous range of logical blocks: neighbouring rows of the row
+// passes then share an XCD and their partial cache lines of the group-major
+// layout meet in its L2.
+__device__ __forceinline__ int xcd_block(int i, int n) {
+    return (n & 7) ? i : (i & 7) * (n >> 3) + (i >> 3);
+}
+
 // S1: forward row DFT (length 2ny) of real rows, keeping the half spectrum k = 0..ny.
 //   in_mode CONV_IN_X      : row i of x (ny values, zero padded)
 //           CONV_IN_CG_P   : p = r + beta p, written back, then transformed
@@ -2071,8 +2080,9 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a,
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
     const int ngrp = nrows / (2 * C);
-    const int ig = blockIdx.x % ngrp;
-    const int b = blockIdx.x / ngrp;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int ig = lb % ngrp;
+    const int b = lb / ngrp;
     R bscale = R(1);
     if (IN == CONV_IN_CG_P) bscale = (R)a.scal[b * 8 + S_BETA];
     if (IN == CONV_IN_SCALED) bscale = (R)a.scal[b * 8 + S_SCALE];
@@ -2101,210 +2111,187 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a,
             return cplx<R>{load(i, r), load(i + 1, r)};
         },
         [](int, int, const cplx<R> &) {});
-    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * 2 * C) * a.ldh;
+    // group-major store: frequency k = g CG + cc of row i at (g nrows + i) CG + cc
+    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + (size_t)b * 2 * nx * a.ldh;
+    const int lgc = __builtin_ctz(a.cgc), cmask = a.cgc - 1;
     for (int id = threadIdx.x; id < C * (ny + 1); id += row_threads<LOG2L>()) {
         const int c = id / (ny + 1), k = id - c * (ny + 1);
         const cplx<R> z = buf[c * ld + Lds<R, LOG2L>::pad(k)];
         const cplx<R> zc = conj(buf[c * ld + Lds<R, LOG2L>::pad((L - k) & (L - 1))]);
-        t1[(size_t)(2 * c) * a.ldh + k] = cplx<R>{(z.re + zc.re) * R(0.5), (z.im + zc.im) * R(0.5)};
-        t1[(size_t)(2 * c + 1) * a.ldh + k] = cplx<R>{(z.im - zc.im) * R(0.5), (zc.re - z.re) * R(0.5)};
+        const size_t o = (((size_t)(k >> lgc) * nrows + ig * 2 * C + 2 * c) << lgc) + (k & cmask);
+        t1[o] = cplx<R>{(z.re + zc.re) * R(0.5), (z.im + zc.im) * R(0.5)};
+        t1[o + a.cgc] = cplx<R>{(z.im - zc.im) * R(0.5), (zc.re - z.re) * R(0.5)};
     }
 }
 
-// In-LDS product with the PSF spectrum followed by a re-ordering into DIT input
-// order for the inverse transform.  Values pass through registers.
-template <typename R, int LOG2L>
-__device__ __forceinline__ void mul_reorder(cplx<R> *buf, int C, int ld, const R *h, size_t hstride,
-                                            int col0, int ncol) {
-    constexpr int L = 1 << LOG2L;
-    constexpr int PER = (L * col_group<R>() + kThreads - 1) / kThreads;
-    cplx<R> v[PER];
+// Group-major half-spectrum layout of the convolution's intermediate: frequency
+// column k = g C + c of row i sits at T[band][(g rows + i) C + c] (rows = nx, or
+// 2nx for the PSF), so the nx values of a group of C columns form one contiguous
+// block (the column pass reads and writes whole blocks) and two adjacent rows of
+// a group are 2 C contiguous values (the row passes store and load 128-byte
+// pieces).  The PSF spectrum uses the same groups: psfhat[band][(g 2 + p) nx + k'][c]
+// holds frequency 2k' + p of column g C + c.
+
+// Column pass: for every column (nx complex values of the row spectra; rows nx ..
+// 2nx - 1 of the zero-padded grid are zero) the 2nx-point DFT, the product with
+// the PSF spectrum, the inverse DFT and the crop to rows 0 .. nx - 1, in one pass.
+// With N = nx and w = exp(-2 pi i / 2N) the zero padding splits the 2N-point
+// transforms into N-point ones:
+//   X[2k'] = DFT_N(x)[k'],  X[2k' + 1] = DFT_N(x[r] w^r)[k'],
+//   y[n] = IDFT_N(H X)_even[n] + w^-n IDFT_N(H X)_odd[n]   (n < N; unnormalised),
+// so one column needs N complex values of LDS at a time (C columns per block).
+// PSF mode: the 2N rows of the rolled PSF (x[r] and x[r + N] both present):
+//   X[2k'] = DFT_N(x[r] + x[r + N]),  X[2k' + 1] = DFT_N((x[r] - x[r + N]) w^r),
+// and the real parts are stored into psfhat.
+template <typename R, int LOG2N, int C> struct ConvCols {
+    static constexpr int N = 1 << LOG2N;
+    static constexpr int NT0 = C * N / 8;   // one radix-8 butterfly per thread and stage
+    static constexpr int NT = NT0 < 64 ? 64 : NT0;
+    static_assert(NT0 <= 1024, "at most 1024 threads per block");
+    static constexpr size_t lds = (size_t)C * Lds<R, LOG2N>::ld * sizeof(cplx<R>) + kTwEntries * sizeof(cplx<R>);
+};
+
+// A block transforms C of the CG columns of a group (CG / C blocks per group).
+// Blocks are dispatched to the eight XCDs in turn (block i on XCD i mod 8), so
+// the blocks of one group get indices that share i mod 8 and follow each other
+// there: they run at the same time on one XCD and read the group's rows through
+// its L2 (each block reads C of every CG contiguous values).
+template <typename R, int LOG2N, int C, int CG, bool PSF>
+__global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(ConvArgs a) {
+    using K = ConvCols<R, LOG2N, C>;
+    using LD = Lds<R, LOG2N>;
+    using P = FftPlan<LOG2N>;
+    constexpr int N = K::N, NT = K::NT;
+    constexpr int S = P::NSTAGE;
+    static_assert(S >= 2 && P::radix(S - 1) == 8, "columns of at least 16 points");
+    constexpr int M = N / 8;          // span of the outermost (radix-8) stage
+    constexpr int R0 = P::radix(0);   // radix of the innermost stage (span 1)
+    constexpr int NSUB = CG / C;
+    constexpr int ld = LD::ld;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, NT>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    const int G = (a.ny + CG) / CG;   // groups of the ny + 1 columns
+    const int xcd = blockIdx.x & 7, jb = blockIdx.x >> 3;
+    const int sub = jb % NSUB, gi = (jb / NSUB) * 8 + xcd;
+    if (gi >= a.n_band * G) return;   // the grid is padded to whole rounds of eight
+    const int g = gi % G, b = gi / G;
+    const size_t boff = (size_t)b * 2 * a.nx * a.ldh;
+    cplx<R> *T = reinterpret_cast<cplx<R> *>(a.t1c) + boff + (size_t)g * (PSF ? 2 * N : N) * CG + sub * C;
+    R *H = reinterpret_cast<R *>(a.psfhat) + boff + (size_t)g * 2 * N * CG + sub * C;
+    const int sh2n = a.log2_lmax - (LOG2N + 1);   // table step of w = exp(-2 pi i / 2N)
+    const int shn = a.log2_lmax - LOG2N;
+    // outermost stage: thread (c, j) owns the butterfly of rows j + t M (t < 8) of
+    // column c; consecutive threads read consecutive values of T
+    const int c = threadIdx.x % C, j = threadIdx.x / C;
+    const bool own = j < M;
+    cplx<R> ev[8];   // the even half's outputs y_e[j + t M], kept for the odd half
+    __syncthreads();   // twiddle table
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-        const int id = threadIdx.x + t * kThreads;
-        if (id < C * L) {
-            const int c = id % C, k = id / C;
-            const R hv = (col0 + c) < ncol ? h[(size_t)k * hstride + col0 + c] : R(0);
-            v[t] = buf[c * ld + Lds<R, LOG2L>::pad(k)] * hv;
-        }
-    }
-    __syncthreads();
+    for (int p = 0; p < 2; ++p) {
+        // forward N-point DFT of the even (p = 0) or odd (p = 1) half by decimation in
+        // frequency: the first stage straight from HBM, X[k] ends at the DIT position of k
+        if (own) {
+            cplx<R> v[8];
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-        const int id = threadIdx.x + t * kThreads;
-        if (id < C * L) {
-            const int c = id % C, k = id / C;
-            buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(k))] = v[t];
+            for (int t = 0; t < 8; ++t) {
+                const int r = j + t * M;
+                cplx<R> x = T[r * CG + c];
+                if (PSF) {
+                    const cplx<R> hi = T[(r + N) * CG + c];
+                    x = p == 0 ? x + hi : x - hi;
+                }
+                v[t] = p == 0 ? x : x * twiddle<R, false>(tt, r << sh2n);
+            }
+            dft_small<R, false, 8>(v);
+            stage_twiddles<R, false, 8>(v, tt, (j * (N / (8 * M))) << shn);
+            cplx<R> *vb = buf + c * ld + LD::pad(j);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) vb[LD::pad(t * M)] = v[t];
         }
-    }
-    __syncthreads();
-}
-
-// S2 single pass (2nx <= 512): column DFT, product with psfhat, inverse, crop.
-// psf mode: forward only, stores Re into psfhat.
-template <typename R, int LOG2L>
-__global__ __launch_bounds__(kThreads) void s2_single_kernel(ConvArgs a, int psf) {
-    constexpr int L = 1 << LOG2L;
-    constexpr int C = col_group<R>();
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
-    const int ld = Lds<R, LOG2L>::ld;
-    const int nx = a.nx, ncol = a.ny + 1;
-    const int ncg = (ncol + C - 1) / C;
-    const int cg = blockIdx.x % ncg, b = blockIdx.x / ncg;
-    const int col0 = cg * C;
-    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + (size_t)b * 2 * nx * a.ldh;
-    R *h = reinterpret_cast<R *>(a.psfhat) + (size_t)b * 2 * nx * a.ldh;
-    const int nin = psf ? 2 * nx : nx;
-    for (int id = threadIdx.x; id < C * L; id += kThreads) {
-        const int c = id % C, r = id / C;
-        const int col = col0 + c;
-        buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] =
-            (r < nin && col < ncol) ? t1[(size_t)r * a.ldh + col] : cplx<R>{R(0), R(0)};
-    }
-    __syncthreads();
-    lds_fft<R, false, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
-    if (psf) {
-        for (int id = threadIdx.x; id < C * L; id += kThreads) {
-            const int c = id % C, k = id / C;
-            if (col0 + c < ncol) h[(size_t)k * a.ldh + col0 + c] = buf[c * ld + Lds<R, LOG2L>::pad(k)].re;
+        __syncthreads();
+        {
+            int m = M;
+#pragma unroll
+            for (int st = S - 2; st >= 1; --st) {   // middle stages, radix 8
+                m /= 8;
+                dif_stage<R, false, 8, LOG2N, NT>(buf, C, ld, m, tt, shn);
+                __syncthreads();
+            }
         }
-        return;
-    }
-    mul_reorder<R, LOG2L>(buf, C, ld, h, a.ldh, col0, ncol);
-    lds_fft<R, true, LOG2L>(buf, C, ld, tt, a.log2_lmax - LOG2L);
-    for (int id = threadIdx.x; id < C * nx; id += kThreads) {
-        const int c = id % C, r = id / C;
-        if (col0 + c < ncol) t1[(size_t)r * a.ldh + col0 + c] = buf[c * ld + Lds<R, LOG2L>::pad(r)];
-    }
-}
-
-// S2A: four-step step A (forward) over r1 for fixed r2: t1c rows r1*n2+r2 -> t2c rows k1*n2+r2.
-template <typename R, int LOG2N1>
-__global__ __launch_bounds__(kThreads) void s2a_kernel(ConvArgs a, int psf) {
-    constexpr int N1 = 1 << LOG2N1;
-    constexpr int C = col_group<R>();
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
-    const int ld = Lds<R, LOG2N1>::ld;
-    const int nx = a.nx, ncol = a.ny + 1, n2 = a.cs.n2;
-    const int ncg = (ncol + C - 1) / C;
-    int blk = blockIdx.x;
-    const int cg = blk % ncg;
-    blk /= ncg;
-    const int r2 = blk % n2;
-    const int b = blk / n2;
-    const int col0 = cg * C;
-    const size_t boff = (size_t)b * 2 * nx * a.ldh;
-    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + boff;
-    cplx<R> *t2 = reinterpret_cast<cplx<R> *>(a.t2c) + boff;
-    const int nin = psf ? 2 * nx : nx;
-    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
-        const int c = id % C, r1 = id / C;
-        const int r = r1 * n2 + r2;
-        const int col = col0 + c;
-        buf[c * ld + Lds<R, LOG2N1>::pad(dit_pos<LOG2N1>(r1))] =
-            (r < nin && col < ncol) ? t1[(size_t)r * a.ldh + col] : cplx<R>{R(0), R(0)};
-    }
-    __syncthreads();
-    lds_fft<R, false, LOG2N1>(buf, C, ld, tt, a.log2_lmax - LOG2N1);
-    const int shift_n = a.log2_lmax - (a.cs.log2n1 + a.cs.log2n2);
-    const int nmask = 2 * nx - 1;
-    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
-        const int c = id % C, k1 = id / C;
-        if (col0 + c >= ncol) continue;
-        t2[(size_t)(k1 * n2 + r2) * a.ldh + col0 + c] =
-            buf[c * ld + Lds<R, LOG2N1>::pad(k1)] * twiddle<R, false>(tt, ((r2 * k1) & nmask) << shift_n);
-    }
-}
-
-// S2B: for fixed k1, forward DFT over r2, product with psfhat (stored in the
-// same [k1*n2 + k2] order), inverse DFT over k2, twiddle w^(+r2 k1); in place.
-// psf mode: forward only, Re stored to psfhat.
-template <typename R, int LOG2N2>
-__global__ __launch_bounds__(kThreads) void s2b_kernel(ConvArgs a, int psf) {
-    constexpr int N2 = 1 << LOG2N2;
-    constexpr int C = col_group<R>();
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
-    const int ld = Lds<R, LOG2N2>::ld;
-    const int nx = a.nx, ncol = a.ny + 1, n1 = a.cs.n1;
-    const int ncg = (ncol + C - 1) / C;
-    int blk = blockIdx.x;
-    const int cg = blk % ncg;
-    blk /= ncg;
-    const int k1 = blk % n1;
-    const int b = blk / n1;
-    const int col0 = cg * C;
-    const size_t boff = (size_t)b * 2 * nx * a.ldh;
-    cplx<R> *t2 = reinterpret_cast<cplx<R> *>(a.t2c) + boff + (size_t)k1 * N2 * a.ldh;
-    R *h = reinterpret_cast<R *>(a.psfhat) + boff + (size_t)k1 * N2 * a.ldh;
-    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
-        const int c = id % C, r2 = id / C;
-        const int col = col0 + c;
-        buf[c * ld + Lds<R, LOG2N2>::pad(dit_pos<LOG2N2>(r2))] = col < ncol ? t2[(size_t)r2 * a.ldh + col] : cplx<R>{R(0), R(0)};
-    }
-    __syncthreads();
-    lds_fft<R, false, LOG2N2>(buf, C, ld, tt, a.log2_lmax - LOG2N2);
-    if (psf) {
-        for (int id = threadIdx.x; id < C * N2; id += kThreads) {
-            const int c = id % C, k2 = id / C;
-            if (col0 + c < ncol) h[(size_t)k2 * a.ldh + col0 + c] = buf[c * ld + Lds<R, LOG2N2>::pad(k2)].re;
+        // innermost stage (span 1) of the forward transform, the product with the PSF
+        // spectrum and the innermost stage of the inverse, in registers
+        for (int id = threadIdx.x; id < C * (N / R0); id += NT) {
+            const int cc = id / (N / R0), gq = id - cc * (N / R0);
+            cplx<R> *vb = buf + cc * ld + LD::pad(gq * R0);
+            cplx<R> v[R0];
+#pragma unroll
+            for (int t = 0; t < R0; ++t) v[t] = vb[LD::pad(t)];
+            dft_small<R, false, R0>(v);
+#pragma unroll
+            for (int t = 0; t < R0; ++t) {
+                const int k = dit_inv<LOG2N>(gq * R0 + t);
+                if (PSF) H[(p * N + k) * CG + cc] = v[t].re;
+                else v[t] = v[t] * H[(p * N + k) * CG + cc];
+            }
+            if (!PSF) {
+                dft_small<R, true, R0>(v);
+#pragma unroll
+                for (int t = 0; t < R0; ++t) vb[LD::pad(t)] = v[t];
+            }
         }
-        return;
-    }
-    mul_reorder<R, LOG2N2>(buf, C, ld, h, a.ldh, col0, ncol);
-    lds_fft<R, true, LOG2N2>(buf, C, ld, tt, a.log2_lmax - LOG2N2);
-    const int shift_n = a.log2_lmax - (a.cs.log2n1 + a.cs.log2n2);
-    const int nmask = 2 * nx - 1;
-    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
-        const int c = id % C, r2 = id / C;
-        if (col0 + c >= ncol) continue;
-        t2[(size_t)r2 * a.ldh + col0 + c] =
-            buf[c * ld + Lds<R, LOG2N2>::pad(r2)] * twiddle<R, true>(tt, ((r2 * k1) & nmask) << shift_n);
+        __syncthreads();
+        if (PSF) continue;
+        {
+            int m = R0;
+#pragma unroll
+            for (int st = 1; st <= S - 2; ++st) {   // middle stages of the inverse (DIT)
+                dit_stage<R, true, 8, LOG2N, NT>(buf, C, ld, m, tt, shn);
+                m *= 8;
+                __syncthreads();
+            }
+        }
+        // outermost stage of the inverse, outputs y[j + t M] in registers
+        if (own) {
+            const cplx<R> *vb = buf + c * ld + LD::pad(j);
+            cplx<R> v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = vb[LD::pad(t * M)];
+            stage_twiddles<R, true, 8>(v, tt, j << shn);
+            dft_small<R, true, 8>(v);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (p == 0) ev[t] = v[t];
+                else T[(j + t * M) * CG + c] = ev[t] + v[t] * twiddle<R, true>(tt, (j + t * M) << sh2n);
+            }
+        }
+        __syncthreads();
     }
 }
 
-// S2C: inverse step A over k1 for fixed r2: t2c rows k1*n2 + r2 -> t1c row r2 + n2 r1 (< nx only).
-template <typename R, int LOG2N1>
-__global__ __launch_bounds__(kThreads) void s2c_kernel(ConvArgs a) {
-    constexpr int N1 = 1 << LOG2N1;
-    constexpr int C = col_group<R>();
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
-    const int ld = Lds<R, LOG2N1>::ld;
-    const int nx = a.nx, ncol = a.ny + 1, n2 = a.cs.n2;
-    const int ncg = (ncol + C - 1) / C;
-    int blk = blockIdx.x;
-    const int cg = blk % ncg;
-    blk /= ncg;
-    const int r2 = blk % n2;
-    const int b = blk / n2;
-    const int col0 = cg * C;
-    const size_t boff = (size_t)b * 2 * nx * a.ldh;
-    const cplx<R> *t2 = reinterpret_cast<const cplx<R> *>(a.t2c) + boff;
-    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + boff;
-    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
-        const int c = id % C, k1 = id / C;
-        const int col = col0 + c;
-        buf[c * ld + Lds<R, LOG2N1>::pad(dit_pos<LOG2N1>(k1))] =
-            col < ncol ? t2[(size_t)(k1 * n2 + r2) * a.ldh + col] : cplx<R>{R(0), R(0)};
-    }
-    __syncthreads();
-    lds_fft<R, true, LOG2N1>(buf, C, ld, tt, a.log2_lmax - LOG2N1);
-    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
-        const int c = id % C, r1 = id / C;
-        const int r = r2 + n2 * r1;
-        if (r < nx && col0 + c < ncol) t1[(size_t)r * a.ldh + col0 + c] = buf[c * ld + Lds<R, LOG2N1>::pad(r1)];
-    }
+// columns per block of the column pass: the most (up to 8) whose C x nx block
+// spans at most 512 threads x 8 values (one radix-8 butterfly per thread and
+// stage; the even half's outputs stay in registers) and fits the LDS
+template <typename R, int LG> constexpr int conv_cgc() {
+    constexpr int N = 1 << LG;
+    constexpr int budget = (int)(16384 / sizeof(R));   // values of a C x nx block
+    constexpr int C = budget / N >= 8 ? 8 : (budget / N >= 1 ? budget / N : 1);
+    static_assert(ConvCols<R, LG, C>::lds <= kMaxLdsBytes, "column group exceeds the LDS");
+    return C;
+}
+// layout group width: the column pass's columns per block, at least 2 (two rows
+// of a group are then at least 32 contiguous bytes for the row passes; blocks of
+// one column share a group with a neighbour on the same XCD)
+template <typename R, int LG> constexpr int conv_layout_cg() { return conv_cgc<R, LG>() < 2 ? 2 : conv_cgc<R, LG>(); }
+int conv_group_cols(bool dbl, int nx) {
+    int C = 1;
+    (void)dispatch_int<4, 12>(__builtin_ctz(nx), [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        C = dbl ? conv_layout_cg<double, LG>() : conv_layout_cg<float, LG>();
+        return hipSuccess;
+    });
+    return C;
 }
 
 // S3: inverse row DFT (length 2ny) of the Hermitian half spectrum, real part,
@@ -2323,17 +2310,24 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a,
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
     const int ngrp = nx / (2 * C);
-    const int ig = blockIdx.x % ngrp;
-    const int b = blockIdx.x / ngrp;
-    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + ((size_t)b * 2 * nx + (size_t)ig * 2 * C) * a.ldh;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int ig = lb % ngrp;
+    const int b = lb / ngrp;
+    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + (size_t)b * 2 * nx * a.ldh;
+    const int lgc = __builtin_ctz(a.cgc), cmask = a.cgc - 1;
     const R scale = R(1) / (R(4) * R(nx) * R(ny));
     double part = 0.0;
     row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>()>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
         [&](int c, int k) -> cplx<R> {
-            const cplx<R> *ra = t1 + (size_t)(2 * c) * a.ldh, *rb = ra + a.ldh;
-            const cplx<R> xa = k <= ny ? ra[k] : conj(ra[L - k]);
-            const cplx<R> xb = k <= ny ? rb[k] : conj(rb[L - k]);
+            // group-major load of rows i, i + 1 at frequency kk (Hermitian: k > ny reads L - k)
+            const int kk = k <= ny ? k : L - k;
+            const size_t o = (((size_t)(kk >> lgc) * nx + ig * 2 * C + 2 * c) << lgc) + (kk & cmask);
+            cplx<R> xa = t1[o], xb = t1[o + a.cgc];
+            if (k > ny) {
+                xa = conj(xa);
+                xb = conj(xb);
+            }
             return cplx<R>{xa.re - xb.im, xa.im + xb.re};
         },
         [&](int c, int j, const cplx<R> &z) {
@@ -2361,34 +2355,16 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a,
 
 template <typename R>
 static hipError_t conv_columns(const ConvArgs &a, int psf, hipStream_t s) {
-    constexpr int C = col_group<R>();
-    const int ncg = (a.ny + 1 + C - 1) / C;
-    if (a.cs.n2 == 1) {
-        return dispatch_int<5, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
-            constexpr int LG = decltype(Lc)::value;
-            const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-            PFB_LAUNCH((s2_single_kernel<R, LG>), a.n_band * ncg, lds, s, a, psf);
-            return hipSuccess;
-        });
-    }
-    hipError_t e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
+    return dispatch_int<4, 12>(__builtin_ctz(a.nx), [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-        PFB_LAUNCH((s2a_kernel<R, LG>), a.n_band * a.cs.n2 * ncg, lds, s, a, psf);
-        return hipSuccess;
-    });
-    if (e != hipSuccess) return e;
-    e = dispatch_int<3, 9>(a.cs.log2n2, [&](auto Lc) -> hipError_t {
-        constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-        PFB_LAUNCH((s2b_kernel<R, LG>), a.n_band * a.cs.n1 * ncg, lds, s, a, psf);
-        return hipSuccess;
-    });
-    if (e != hipSuccess || psf) return e;
-    return dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
-        constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-        PFB_LAUNCH((s2c_kernel<R, LG>), a.n_band * a.cs.n2 * ncg, lds, s, a);
+        constexpr int CG = conv_layout_cg<R, LG>();
+        constexpr int CB = conv_cgc<R, LG>();   // columns per block
+        using K = ConvCols<R, LG, CB>;
+        if (a.cgc != CG) return hipErrorInvalidValue;
+        const int G = (a.ny + CG) / CG;
+        const int nb = ((a.n_band * G + 7) / 8) * 8 * (CG / CB);
+        if (psf) PFB_LAUNCH_NT((conv_cols_kernel<R, LG, CB, CG, true>), nb, K::NT, K::lds, s, a);
+        else PFB_LAUNCH_NT((conv_cols_kernel<R, LG, CB, CG, false>), nb, K::NT, K::lds, s, a);
         return hipSuccess;
     });
 }
