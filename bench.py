@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--support", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--tuned", default=os.path.join(ROOT, "profiles", "autotune_{workload}.json"),
+                    help="autotuner record whose choice (support, tile, chunk) the FP32 plan uses when "
+                         "the command line leaves them at 0 (see paper_2101_08072_amd.tune)")
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-band-batch-compare", action="store_true",
                     help="skip timing the Hessian with one band per launch (FP32)")
@@ -269,6 +272,15 @@ def main():
     n_vis = prob.n_row * prob.n_chan
     x_true = synth.extended_sky(synth.SEED_BASE, prob.n_band, prob.nx, prob.ny)
 
+    tuned = None
+    tuned_path = args.tuned.format(workload=args.workload)
+    if not (args.support or args.tile or args.chunk) and os.path.exists(tuned_path):
+        with open(tuned_path) as f:
+            rec = json.load(f)
+        if rec.get("workload") == args.workload:
+            tuned = rec["choice"]
+            args.support, args.tile, args.chunk = tuned["support"], tuned["tile"], tuned["chunk"]
+            log(f"autotuned options from {tuned_path}: {tuned}")
     opts = Options(precision="fp32", support=args.support, tile=args.tile, chunk=args.chunk)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -545,7 +557,8 @@ def main():
         "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "n_band": prob.n_band,
                    "n_row": prob.n_row, "n_chan": prob.n_chan, "visibilities": n_vis,
                    "active_visibilities": M, "cg_iters": args.cg_iters, "support": W,
-                   "tile": info["tile"], "w_planes": info["n_wplanes_max"], "oversample": 2.0},
+                   "tile": info["tile"], "w_planes": info["n_wplanes_max"], "oversample": 2.0,
+                   "autotuned": tuned},
         "roofline": roof,
         "cpu_baseline": cpu,
         "grid_degrid_vis_per_s": round(grid_degrid_vis_s, 1),

@@ -10,7 +10,10 @@ are free (not only when a batch finishes), keeps each admitted job's
 visibilities, weights, PSF spectrum and iterates resident, and advances every
 active job by one stage per tick.  On the GPU each job runs on its own stream,
 so the kernels of different jobs overlap on the device; the host never waits
-for a job — completion is polled with events.
+for a job — completion is polled with events — and a job's set-up (input
+generation and plan creation, which reads uvw and the bucket counts back on the
+host) runs on a worker thread, so admissions do not stall the other jobs.  The
+slot count defaults to the device's four hardware queues.
 
 The scheduling core (`Scheduler`) is independent of the executor, so the
 admission logic is tested on the CPU with a fake executor.
@@ -64,7 +67,7 @@ class Scheduler:
       now() -> float
     """
 
-    def __init__(self, executor, hbm_budget: int, max_slots: int = 8, backfill: bool = True):
+    def __init__(self, executor, hbm_budget: int, max_slots: int = 4, backfill: bool = True):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_slots = max_slots
@@ -113,7 +116,12 @@ class Scheduler:
             for jid in list(self.active):
                 spec, handle, need, admitted, enq = self.active[jid]
                 if not enq:
-                    self.active[jid][4] = self.ex.advance(handle)
+                    try:
+                        self.active[jid][4] = self.ex.advance(handle)
+                    except Exception as exc:              # set-up or a stage failed: free the slot
+                        self.failed.append((jid, str(exc)))
+                        self.used -= need
+                        del self.active[jid]
                     progressed = True
                 elif self.ex.done(handle):
                     n_act, passes = self.ex.finish(handle)
@@ -211,15 +219,23 @@ class FakeExecutor:
 class GpuExecutor:
     """Runs jobs through the C ABI, one HIP stream per job.  Inputs are generated
     on the device from the seeded earth-rotation uvw (synth) and a seeded torch
-    generator for weights, flags and visibilities."""
+    generator for weights, flags and visibilities.  Set-up (inputs, plan) runs on
+    a pool of `setup_workers` threads; the first stage waits for it without
+    blocking the tick.  Large jobs keep at most `max_plane_bytes` of w-planes
+    resident (the plan's band batch)."""
 
-    def __init__(self, device="cuda", cell_fov_deg: float = 1.0, keep_results: bool = False):
+    def __init__(self, device="cuda", cell_fov_deg: float = 1.0, keep_results: bool = False,
+                 setup_workers: int = 2, max_plane_bytes: int = 48 << 30):
+        import concurrent.futures as cf
         import torch
         self.torch = torch
-        self.device = device
+        dev = torch.device(device)
+        self.device = torch.device("cuda", dev.index if dev.index is not None else torch.cuda.current_device())
         self.fov = cell_fov_deg
         self.keep = keep_results
         self.outputs = {}
+        self.pool = cf.ThreadPoolExecutor(max_workers=setup_workers)
+        self.max_plane_bytes = int(max_plane_bytes)
 
     def now(self):
         return time.perf_counter()
@@ -229,25 +245,38 @@ class GpuExecutor:
         n_row = max(1, -(-spec.n_vis // n_chan))
         return n_row, n_chan
 
+    def _band_batch(self, spec):
+        """Bands whose w-planes are resident at once (planes + two intermediates)."""
+        per_band = self._per_band_planes(spec) * 3
+        return max(1, min(spec.n_band, self.max_plane_bytes // per_band))
+
+    @staticmethod
+    def _per_band_planes(spec):
+        g = 2 * spec.nx
+        nw = 24                                    # generous w-plane bound for a 1 degree field
+        return max(nw * g * g, 4 * g * g) * 8
+
     def estimate(self, spec):
         """Upper bound of the device bytes of a job (inputs + workspace), from shapes."""
         n_row, n_chan = self._shape(spec)
         nv = n_row * n_chan
         nx = spec.nx
-        g = 2 * nx
-        nw = 24                                    # generous w-plane bound for a 1 degree field
-        per_band_planes = max(nw * g * g, 4 * g * g) * 8
-        planes = per_band_planes * 3 * spec.n_band  # planes + two intermediates
-        recs = int(nv * 2.2) * 20 * 2              # two gridders, up to 2.2 copies per visibility
+        planes = self._per_band_planes(spec) * 3 * self._band_batch(spec)  # planes + two intermediates
+        recs = int(nv * 2.2) * 28 * 2              # two gridders, up to 2.2 copies per visibility
         inputs = nv * (8 + 4 + 1 + 8) + n_row * 24
-        images = spec.n_band * nx * nx * 4 * 20
-        return int(planes + recs + inputs + images + (64 << 20))
+        images = spec.n_band * nx * nx * 4 * 40    # images, PSF, row spectra, CG vectors
+        return int(planes + recs + inputs + images + (256 << 20))
 
     def start(self, spec):
+        """Hands the job's set-up to a worker thread; the handle's first stage waits for it."""
+        stream = self.torch.cuda.Stream(device=self.device)
+        return {"spec": spec, "stream": stream, "stage": -1, "setup": self.pool.submit(self._setup, spec, stream)}
+
+    def _setup(self, spec, stream):
         import synth
         torch = self.torch
         from .plan import Options, Plan
-        stream = torch.cuda.Stream(device=self.device)
+        torch.cuda.set_device(self.device)   # the worker thread's current device
         n_row, n_chan = self._shape(spec)
         with torch.cuda.stream(stream):
             uvw = torch.as_tensor(synth.earth_rotation_uvw(synth.antenna_enu(spec.seed), n_row),
@@ -258,15 +287,20 @@ class GpuExecutor:
             flag = (torch.rand((n_row, n_chan), generator=gen, device=self.device) < 0.1).to(torch.uint8)
             cell = math.radians(self.fov) / spec.nx
             plan = Plan(uvw, freq, weight, flag, synth.contiguous_bands(n_chan, spec.n_band), spec.n_band,
-                        spec.nx, spec.nx, cell, cell, Options(precision="fp32", band_batch=spec.n_band))
+                        spec.nx, spec.nx, cell, cell, Options(precision="fp32", band_batch=self._band_batch(spec)))
             vis = torch.complex(torch.randn((n_row, n_chan), generator=gen, device=self.device),
                                 torch.randn((n_row, n_chan), generator=gen, device=self.device)).contiguous()
-            job = {"spec": spec, "stream": stream, "plan": plan, "vis": vis, "stage": 0,
-                   "x": plan.image().zero_(), "n_act": plan.info()["n_vis_active"], "graph": None}
+            job = {"plan": plan, "vis": vis, "x": plan.image().zero_(), "n_act": plan.info()["n_vis_active"],
+                   "graph": None, "uvw": uvw, "freq": freq, "weight": weight, "flag": flag, "cell": cell}
         return job
 
     def advance(self, job):
         torch = self.torch
+        if job["stage"] < 0:
+            if not job["setup"].done():
+                return False                                   # set-up still running on its worker
+            job.update(job.pop("setup").result())             # re-raises a set-up failure
+            job["stage"] = 0
         plan, spec = job["plan"], job["spec"]
         with torch.cuda.stream(job["stream"]):
             s = job["stage"]
@@ -299,7 +333,9 @@ class GpuExecutor:
     def finish(self, job):
         spec = job["spec"]
         if self.keep:
-            self.outputs[spec.job_id] = {k: job[k].detach().cpu().numpy() for k in ("dirty", "x", "resid")}
+            out = {k: job[k].detach().cpu().numpy() for k in ("dirty", "x", "resid", "vis", "uvw", "weight", "flag")}
+            out.update(freq=job["freq"], cell=job["cell"])
+            self.outputs[spec.job_id] = out
         n_act = job["n_act"]
         job.clear()
         return n_act, 4        # dirty-image grid, PSF grid, Hessian degrid + grid
@@ -323,7 +359,7 @@ def main(argv=None):
     ap.add_argument("--vis-max", type=float, default=2e7)
     ap.add_argument("--max-band", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=64.0)
-    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--n-fb", type=int, default=10)
     ap.add_argument("--cg-iters", type=int, default=20)
     a = ap.parse_args(argv)

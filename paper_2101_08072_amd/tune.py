@@ -3,9 +3,14 @@
 Picks ES support W, uv tile T and work-item size for a given problem: every
 candidate is built, timed on grid + degrid of the resident data, and its error
 is measured against a reference computed on the same GPU in FP64 mode (support
-13, relative error ~1e-12 against the direct sum); the fastest candidate whose
+13, relative error ~1e-12 against the direct sum; FP64 plans serve grid and
+degrid up to 4096^2 images, one band at a time); the fastest candidate whose
 dirty-image and degrid errors both stay within the budget wins.  The grid
 oversampling is fixed at 2 (the FFTs are power-of-two only).
+
+    python -m paper_2101_08072_amd.tune --workload batched-8x4096 --out tune.json
+
+writes the choice and the candidate table as JSON (the benchmark can load it).
 """
 from __future__ import annotations
 
@@ -71,3 +76,35 @@ def autotune(prob, err_budget: float = 3e-6, supports=(6, 7, 8), tiles=(16, 32),
         raise RuntimeError(f"no candidate meets the error budget {err_budget}: {table}")
     best = min(ok, key=lambda r: r["grid_ms"] + r["degrid_ms"])
     return Options(precision="fp32", support=best["support"], tile=best["tile"], chunk=best["chunk"]), table
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+    import os
+    ap = argparse.ArgumentParser(prog="python -m paper_2101_08072_amd.tune")
+    ap.add_argument("--workload", default="batched-8x4096")
+    ap.add_argument("--budget", type=float, default=3e-6)
+    ap.add_argument("--supports", default="6,7,8")
+    ap.add_argument("--tiles", default="16,32")
+    ap.add_argument("--chunks", default="0")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import synth
+    prob = synth.workload(a.workload)
+    ints = lambda t: tuple(int(v) for v in t.split(","))  # noqa: E731
+    best, table = autotune(prob, err_budget=a.budget, supports=ints(a.supports), tiles=ints(a.tiles),
+                           chunks=ints(a.chunks))
+    rec = {"workload": a.workload, "err_budget": a.budget,
+           "choice": {"support": best.support, "tile": best.tile, "chunk": best.chunk}, "candidates": table}
+    text = json.dumps(rec, indent=1)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text + "\n")
+    print(text, flush=True)
+
+
+if __name__ == "__main__":
+    main()
