@@ -102,6 +102,9 @@ typedef struct {
     int32_t        nx, ny;     /* image side lengths, even, >= 16                           */
     double         cellx;      /* pixel size along l, radians                               */
     double         celly;      /* pixel size along m, radians                               */
+    int32_t        offx, offy; /* facet offset in pixels: pixel (nx/2, ny/2) of this image sits at
+                                  l = offx cellx, m = offy celly (0, 0: centred on the phase
+                                  centre).  Non-zero offsets: FP32, not flat                   */
 } pfb_problem;
 
 /* Accuracy / tiling choices.  Zero fields take the defaults given. */
@@ -145,6 +148,8 @@ typedef struct {
        tile row) triples with at least one such tile                           */
     int64_t n_wplanes_total;       /* sum over bands of their w-planes                      */
     int64_t occ_tiles, occ_tile_rows, need_tiles, need_tile_rows;
+    double  s_max;                 /* max over pixels of n - 1 (0 when the image holds the
+                                      phase centre)                                          */
 } pfb_plan_info;
 
 /* Creates a plan: validates the problem and analyses uvw (copied to the host on
@@ -201,6 +206,12 @@ pfb_status pfb_grid(pfb_plan *plan, const void *vis, void *image, int mode, hipS
  *   image DEVICE real [n_band][nx][ny];  vis DEVICE complex [n_row][n_chan] (fully written;
  *   flagged / zero-weight entries get 0). */
 pfb_status pfb_degrid(pfb_plan *plan, const void *image, void *vis, hipStream_t stream);
+
+/* V += R x: as pfb_degrid, but the model visibilities of x are added to vis, and
+ * flagged / zero-weight entries are left as they are.  With facet plans (pfb_problem
+ * offx, offy) that share one set of visibilities, the model visibilities of a whole
+ * image are the sum over its facets (Section 2: R is linear in x). */
+pfb_status pfb_degrid_add(pfb_plan *plan, const void *image, void *vis, hipStream_t stream);
 
 /* y = R^dagger Sigma^-1 R x (eq. 3), x and y DEVICE real [n_band][nx][ny]; x != y. */
 pfb_status pfb_hessian(pfb_plan *plan, const void *x, void *y, hipStream_t stream);

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "PFB_OK", -1: "PFB_EINVAL", -2: "PFB_ENOMEM", -3: "PFB_EHIP",
 # every symbol include/pfb.h declares
 EXPORTS = ["pfb_plan_create", "pfb_plan_count_scratch_size", "pfb_plan_count", "pfb_plan_count_static",
            "pfb_plan_workspace_size", "pfb_plan_set_workspace",
-           "pfb_plan_get_info", "pfb_plan_destroy", "pfb_grid", "pfb_degrid", "pfb_hessian",
+           "pfb_plan_get_info", "pfb_plan_destroy", "pfb_grid", "pfb_degrid", "pfb_degrid_add", "pfb_hessian",
            "pfb_psf_conv", "pfb_precond_solve", "pfb_power_iteration", "pfb_fb_step",
            "pfb_fb_graph_create", "pfb_graph_launch", "pfb_graph_destroy",
            "pfb_profile_enable", "pfb_profile_report", "pfb_last_error", "pfb_version",
@@ -29,7 +29,8 @@ class PfbProblem(ctypes.Structure):
     _fields_ = [("n_row", ctypes.c_int64), ("n_chan", ctypes.c_int64), ("n_band", ctypes.c_int32),
                 ("chan_band", ctypes.c_void_p), ("freq", ctypes.c_void_p), ("uvw", ctypes.c_void_p),
                 ("weight", ctypes.c_void_p), ("flag", ctypes.c_void_p), ("nx", ctypes.c_int32),
-                ("ny", ctypes.c_int32), ("cellx", ctypes.c_double), ("celly", ctypes.c_double)]
+                ("ny", ctypes.c_int32), ("cellx", ctypes.c_double), ("celly", ctypes.c_double),
+                ("offx", ctypes.c_int32), ("offy", ctypes.c_int32)]
 
 
 class PfbOptions(ctypes.Structure):
@@ -49,7 +50,7 @@ class PfbPlanInfo(ctypes.Structure):
                 ("es_beta", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
                 ("n_wplanes_total", ctypes.c_int64), ("occ_tiles", ctypes.c_int64),
                 ("occ_tile_rows", ctypes.c_int64), ("need_tiles", ctypes.c_int64),
-                ("need_tile_rows", ctypes.c_int64)]
+                ("need_tile_rows", ctypes.c_int64), ("s_max", ctypes.c_double)]
 
 
 _lib = None
@@ -77,6 +78,7 @@ def load():
         "pfb_plan_destroy": [vp],
         "pfb_grid": [vp, vp, vp, i32, vp],
         "pfb_degrid": [vp, vp, vp, vp],
+        "pfb_degrid_add": [vp, vp, vp, vp],
         "pfb_hessian": [vp, vp, vp, vp],
         "pfb_psf_conv": [vp, vp, vp, vp],
         "pfb_precond_solve": [vp, vp, vp, f64, i32, f64, vp, vp],

@@ -211,7 +211,7 @@ struct pfb_plan {
     std::vector<double> freq;
     GridderHost main, psf;
     int64_t n_active = 0, n_flagged = 0;
-    double s_min = 0.0;
+    double s_min = 0.0, s_max = 0.0;
     int band_batch = 1;
     int conv_cgc = 1;
     int ldh = 0;
@@ -250,6 +250,8 @@ GeomDev base_geom(const pfb_plan &P, int nx, int ny, bool flat) {
     g.W = P.opt.support;
     g.n_band = P.prob.n_band;
     g.flat = flat ? 1 : 0;
+    g.offx = flat ? 0 : P.prob.offx;   // the flat (PSF) gridder is shift invariant
+    g.offy = flat ? 0 : P.prob.offy;
     g.cellx = P.prob.cellx;
     g.celly = P.prob.celly;
     g.beta = 2.30 * g.W;
@@ -451,6 +453,7 @@ InterpLaunch interp_args(const GridderHost &G, int b0, int nbb, int omode, const
     s.band0 = b0;
     s.omode = omode;
     s.phase = G.mfma ? G.d_phase : nullptr;
+    s.use_phase = G.mfma && (G.g.offx || G.g.offy);
     s.hidx = G.d_hidx;
     s.hoffsets = G.d_hoffsets;
     return s;
@@ -840,7 +843,21 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     if (2 * pr.nx > max_row || 2 * pr.ny > max_row)
         return fail(PFB_EUNSUPPORTED, "image %d x %d needs FFT rows longer than %d for this precision", pr.nx, pr.ny,
                     max_row);
-    const double lmax2 = std::pow(0.5 * pr.nx * pr.cellx, 2) + std::pow(0.5 * pr.ny * pr.celly, 2);
+    if ((pr.offx || pr.offy) && (dbl || opt.flat))
+        return fail(PFB_EUNSUPPORTED, "facet offsets need the FP32 w-stacked path (not FP64, not flat)");
+    if (std::abs((int64_t)pr.offx) > (int64_t)1 << 24 || std::abs((int64_t)pr.offy) > (int64_t)1 << 24)
+        return fail(PFB_EINVAL, "facet offset out of range");
+    // extreme l^2 + m^2 over the pixels: pixel i sits at l = (i - nx/2 + offx) cellx
+    auto axis_range = [](int n, int off, double cell, double *amin, double *amax) {
+        const double lo = (double)(off - n / 2) * cell, hi = (double)(off + n / 2 - 1) * cell;
+        *amax = std::max(std::fabs(lo), std::fabs(hi));
+        *amin = (lo <= 0.0 && hi >= 0.0) ? 0.0 : std::min(std::fabs(lo), std::fabs(hi));
+    };
+    double lmin_abs, lmax_abs, mmin_abs, mmax_abs;
+    axis_range(pr.nx, pr.offx, pr.cellx, &lmin_abs, &lmax_abs);
+    axis_range(pr.ny, pr.offy, pr.celly, &mmin_abs, &mmax_abs);
+    const double lmax2 = lmax_abs * lmax_abs + mmax_abs * mmax_abs;
+    const double lmin2 = lmin_abs * lmin_abs + mmin_abs * mmin_abs;
     if (!opt.flat && lmax2 >= 1.0) return fail(PFB_EINVAL, "field of view reaches l^2 + m^2 >= 1");
 
     pfb_plan *P = new pfb_plan();
@@ -894,16 +911,16 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     GridderHost &M = P->main;
     M.g = base_geom(*P, pr.nx, pr.ny, opt.flat != 0);
     M.cs = make_split(M.g.gx);
-    {
-        const double r2 = lmax2;
-        P->s_min = opt.flat ? 0.0 : -r2 / (1.0 + std::sqrt(1.0 - r2));
-    }
+    // n - 1 over the pixels lies in [s_min, s_max] (s_max = 0 when the image holds the
+    // phase centre; a facet away from it has a narrower range and so fewer w-planes)
+    P->s_min = opt.flat ? 0.0 : -lmax2 / (1.0 + std::sqrt(1.0 - lmax2));
+    P->s_max = opt.flat ? 0.0 : -lmin2 / (1.0 + std::sqrt(1.0 - lmin2));
     M.bands.resize(pr.n_band);
     M.g.nj0max = 1;
     M.g.nwmax = 1;
     for (int b = 0; b < pr.n_band; ++b) {
         BandDev &bd = M.bands[b];
-        if (opt.flat || P->s_min == 0.0 || fmax[b] == 0.0) {
+        if (opt.flat || P->s_max - P->s_min <= 0.0 || fmax[b] == 0.0) {
             bd.w0 = 0.0;
             bd.dw = 1.0;
             bd.sc = 0.0;
@@ -913,8 +930,9 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
             const double s0 = fmin[b] / kC0, s1 = fmax[b] / kC0;
             const double wmin = std::min({wlo * s0, wlo * s1, whi * s0, whi * s1});
             const double wmax = std::max({wlo * s0, wlo * s1, whi * s0, whi * s1});
-            bd.dw = 1.0 / (2.0 * std::fabs(P->s_min));   // w oversampling 2
-            bd.sc = 0.5 * P->s_min;
+            // w oversampling 2: |dw (s - sc)| <= 1/4 over the pixels
+            bd.dw = 1.0 / (2.0 * (P->s_max - P->s_min));
+            bd.sc = 0.5 * (P->s_min + P->s_max);
             const double D = (wmax - wmin) / bd.dw;
             bd.nj0 = (int)std::floor(D) + 2;
             bd.nw = bd.nj0 + opt.support - 1;
@@ -989,6 +1007,7 @@ pfb_status pfb_plan_get_info(const pfb_plan *P, pfb_plan_info *info) {
     info->n_entries = P->main.n_entries;
     info->n_psf_entries = P->psf.n_entries;
     info->s_min = P->s_min;
+    info->s_max = P->s_max;
     info->es_beta = P->main.g.beta;
     info->workspace_bytes = (int64_t)P->ws_bytes;
     const GridderHost &G = P->main;
@@ -1107,8 +1126,8 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
         LAUNCH_OK(launch_sort(d, tmp_recs, tmp_om, G->d_recs, G->d_omega,
                               reinterpret_cast<const int64_t *>(P->p(G->o_sortitems)), (int)(G->sort_items.size() / 4),
                               G->n_entries, G->keys(), (int64_t)G->g.ntx * G->g.nty * G->g.nj0max,
-                              pr.n_row * pr.n_chan, G->g.T, G->g.W, G->sort_rb, G->sort_cb, G->d_bands, G->d_phase,
-                              sort_scratch, s));
+                              pr.n_row * pr.n_chan, G->g.T, G->g.W, G->sort_rb, G->sort_cb, G->d_bands, G->g,
+                              G->d_phase, sort_scratch, s));
         LAUNCH_OK(launch_home_list(d, G->d_recs, reinterpret_cast<const int64_t *>(P->p(G->o_sortitems)),
                                    (int)(G->sort_items.size() / 4), G->d_hoffsets, G->d_hidx, s));
         if (G == &P->main) {   // Hessian values travel in home-list order; o_vals is scratch here
@@ -1282,6 +1301,23 @@ pfb_status pfb_degrid(pfb_plan *P, const void *image, void *vis, hipStream_t s) 
         xa.image_in = image;
         LAUNCH_OK(launch_degrid_xform(d, xa, s));
         LAUNCH_OK(launch_interp(d, interp_args(G, b0, nbb, 0, P->p(P->o_planes), vis), s));
+    }
+    return PFB_OK;
+}
+
+pfb_status pfb_degrid_add(pfb_plan *P, const void *image, void *vis, hipStream_t s) {
+    ProfScope prof_scope(P);
+    pfb_status st = check_ready(P);
+    if (st) return st;
+    if (!image || !vis) return fail(PFB_EINVAL, "image and vis must be non-NULL");
+    const bool d = P->dbl;
+    GridderHost &G = P->main;
+    for (int b0 = 0; b0 < P->prob.n_band; b0 += P->band_batch) {
+        const int nbb = std::min(P->band_batch, P->prob.n_band - b0);
+        XformArgs xa = xform_args(P, G, b0, nbb);
+        xa.image_in = image;
+        LAUNCH_OK(launch_degrid_xform(d, xa, s));
+        LAUNCH_OK(launch_interp(d, interp_args(G, b0, nbb, 2, P->p(P->o_planes), vis), s));
     }
     return PFB_OK;
 }

@@ -47,6 +47,7 @@ struct GeomDev {
     int nj0max, nwmax;   // strides
     int n_band;
     int flat;
+    int offx, offy;      // pixel (nx/2, ny/2) sits at l = offx cellx, m = offy celly (a facet)
     double cellx, celly;
     double beta;
 };

@@ -47,8 +47,8 @@ size_t sort_scratch_bytes(int64_t n_entries);
 int sort_key_bits(int64_t n_buckets, int T, int W, int rb, int cb, int64_t n_vis);
 hipError_t launch_sort(bool dbl, const void *src, const void *src_om, void *dst, void *dst_om, const int64_t *items,
                        int n_items, int64_t n_entries, int64_t n_buckets, int64_t bucket_per_band, int64_t n_vis,
-                       int T, int W, int rb, int cb, const BandDev *bands, void *phase, void *scratch,
-                       hipStream_t s);
+                       int T, int W, int rb, int cb, const BandDev *bands, const GeomDev &geo, void *phase,
+                       void *scratch, hipStream_t s);
 hipError_t launch_corr2d(bool dbl, const GeomDev &g, const BandDev *bands, const double *cheb,
                          int ncheb, double xi_max, void *corr, hipStream_t s);
 hipError_t launch_corr1d(bool dbl, int n, int gsize, const double *cheb, int ncheb, double xi_max,
@@ -91,10 +91,12 @@ struct InterpLaunch {
     const int64_t *offsets;
     const void *recs, *omega;
     const void *planes;
-    void *out;            // OMODE 0: visibilities; OMODE 1: values in home-list order
+    void *out;            // OMODE 0: visibilities; OMODE 1: values in home-list order; OMODE 2: added to
+                          // the visibilities
     int band0;
     int omode;
-    const void *phase;    // FP32 w-stacked gridder: exp(2 pi i s_c w) per entry (else null: computed)
+    const void *phase;    // FP32 w-stacked gridder: exp(2 pi i (s_c w + u l0 + v m0)) per entry (else null)
+    int use_phase;        // OMODE 0/2 take the visibility phase from `phase` (facets) instead of computing it
     float *absmax;        // FP32, OMODE 1: raised to max |value| x 1.0001 (cleared by the caller), or null
     const uint32_t *hidx;       // home-entry list (entry positions)
     const int64_t *hoffsets;    // per bucket: start of its home entries in hidx

@@ -374,7 +374,7 @@ __global__ __launch_bounds__(kThreads) void corr2d_kernel(GeomDev g, const BandD
         const double qi = i - g.nx / 2, qj = j - g.ny / 2;
         double c = psihat_eval(cheb, ncheb, qi / g.gx, xi_max) * psihat_eval(cheb, ncheb, qj / g.gy, xi_max);
         if (!g.flat) {
-            const double l = qi * g.cellx, m = qj * g.celly;
+            const double l = (qi + g.offx) * g.cellx, m = (qj + g.offy) * g.celly;
             const double r2 = l * l + m * m;
             const double n = sqrt(1.0 - r2);
             const double sm1 = -r2 / (1.0 + n);
@@ -1395,9 +1395,10 @@ __global__ __launch_bounds__(kTileThreads) void interp_kernel(InterpLaunch a) {
             }
             if (lane == 0) {
                 const uint32_t vid = rec.idx & ~kHomeBit;
-                if (OMODE == 0) {
+                if (OMODE != 1) {
                     cplx<R> out = FLAT ? acc : acc * conj(cis_cycles<R>((w0 + rec.fw * dw) * sc));
-                    reinterpret_cast<cplx<R> *>(a.out)[vid] = out;
+                    cplx<R> *ov = reinterpret_cast<cplx<R> *>(a.out) + vid;
+                    *ov = OMODE == 2 ? *ov + out : out;
                 } else {
                     const cplx<R> o = acc * omega[e];
                     reinterpret_cast<cplx<R> *>(a.out)[h] = o;   // home-list order
@@ -1549,9 +1550,13 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
             acc.im = quad_sum(acc.im);
             if (lq == 0) {
                 const uint32_t vid = rec.idx & ~kHomeBit;
-                if (OMODE == 0) {
-                    cplx<R> out = FLAT ? acc : acc * conj(cis_cycles<R>((w0 + rec.fw * dw) * sc));
-                    reinterpret_cast<cplx<R> *>(a.out)[vid] = out;
+                if (OMODE != 1) {
+                    cplx<R> out = acc;
+                    if (!FLAT)
+                        out = out * conj(a.use_phase ? reinterpret_cast<const cplx<R> *>(a.phase)[e]
+                                                     : cis_cycles<R>((w0 + rec.fw * dw) * sc));
+                    cplx<R> *ov = reinterpret_cast<cplx<R> *>(a.out) + vid;
+                    *ov = OMODE == 2 ? *ov + out : out;
                 } else {
                     const cplx<R> o = acc * omega[e];
                     reinterpret_cast<cplx<R> *>(a.out)[h] = o;   // home-list order
@@ -1591,8 +1596,10 @@ static hipError_t interp_w(const InterpLaunch &a, hipStream_t s) {
     }
     INTERP_CASE(false, 0)
     INTERP_CASE(false, 1)
+    INTERP_CASE(false, 2)
     INTERP_CASE(true, 0)
     INTERP_CASE(true, 1)
+    INTERP_CASE(true, 2)
 #undef INTERP_CASE
     return hipErrorInvalidValue;
 }
@@ -1613,8 +1620,10 @@ hipError_t launch_interp(bool dbl, const InterpLaunch &a, hipStream_t s) {
         }
         INTERP4_CASE(false, 0)
         INTERP4_CASE(false, 1)
+        INTERP4_CASE(false, 2)
         INTERP4_CASE(true, 0)
         INTERP4_CASE(true, 1)
+        INTERP4_CASE(true, 2)
 #undef INTERP4_CASE
         return hipErrorInvalidValue;
     });
@@ -1641,8 +1650,8 @@ hipError_t launch_zero_flagged(bool dbl, const uint32_t *flagged, int64_t n, voi
 // i = (q + n/2) mod g, valid when < n.
 
 template <typename R>
-__device__ __forceinline__ R pixel_sm1(int i, int j, int nx, int ny, R cellx, R celly) {
-    const R l = R(i - nx / 2) * cellx, m = R(j - ny / 2) * celly;
+__device__ __forceinline__ R pixel_sm1(int i, int j, const GeomDev &g) {
+    const R l = R(i - g.nx / 2 + g.offx) * (R)g.cellx, m = R(j - g.ny / 2 + g.offy) * (R)g.celly;
     const R r2 = l * l + m * m;
     return -r2 / (R(1) + dev_sqrt(R(1) - r2));
 }
@@ -1770,7 +1779,7 @@ __global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
                                           : reinterpret_cast<const R *>(a.corr_x)[i] * reinterpret_cast<const R *>(a.corr_y)[col];
                     v = cplx<R>{x * cr, R(0)};
                     if (!a.g.flat) {
-                        const R s = pixel_sm1<R>(i, col, nx, ny, (R)a.g.cellx, (R)a.g.celly) - sc;
+                        const R s = pixel_sm1<R>(i, col, a.g) - sc;
                         v = v * conj(cis_cycles<R>(wj * s));
                     }
                 }
@@ -1828,7 +1837,7 @@ __global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
         const int i = wrapi(k1 + n1 * k2 + nx / 2, gx);
         const int col = col0 + c;
         sv[c * NS + k2] = (!a.g.flat && i < nx && col < ny)
-                              ? pixel_sm1<R>(i, col, nx, ny, (R)a.g.cellx, (R)a.g.celly) - sc
+                              ? pixel_sm1<R>(i, col, a.g) - sc
                               : R(0);
     }
     for (int j = 0; j < nw; ++j) {

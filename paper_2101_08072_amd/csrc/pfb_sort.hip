@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kSortThreads) void sort_gather_kernel(const Rec<R> 
                                                                    R *dst_om, const uint32_t *perm, int64_t n,
                                                                    const uint64_t *keys, int sh_bucket,
                                                                    int64_t bucket_per_band, const BandDev *bands,
-                                                                   cplx<float> *phase) {
+                                                                   GeomDev geo, cplx<float> *phase) {
     for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kSortThreads) {
         const uint32_t j = perm[i];
@@ -61,8 +61,19 @@ __global__ __launch_bounds__(kSortThreads) void sort_gather_kernel(const Rec<R> 
         dst[i] = r;
         dst_om[i] = src_om[j];
         if (phase) {
-            const BandDev bd = bands[(int64_t)(keys[i] >> sh_bucket) / bucket_per_band];
-            const cplx<double> z = cis_cycles<double>((bd.w0 + (double)r.fw * bd.dw) * bd.sc);
+            // exp(2 pi i (w s_c + u l0 + v m0)): the w factor split off the w-stacking and,
+            // for a facet centred at pixel offsets (offx, offy), its shift from the phase
+            // centre; u l0 = t_u offx / g_x modulo whole turns, t_u = tile row * T + fu
+            const int64_t bucket = (int64_t)(keys[i] >> sh_bucket);
+            const BandDev bd = bands[bucket / bucket_per_band];
+            double t = (bd.w0 + (double)r.fw * bd.dw) * bd.sc;
+            if (geo.offx | geo.offy) {
+                const int tile = (int)((bucket % bucket_per_band) / geo.nj0max);
+                const double tu = (double)(tile / geo.nty) * geo.T + (double)r.fu;
+                const double tv = (double)(tile % geo.nty) * geo.T + (double)r.fv;
+                t += tu * geo.offx / geo.gx + tv * geo.offy / geo.gy;
+            }
+            const cplx<double> z = cis_cycles<double>(t - rint(t));
             phase[i] = cplx<float>{(float)z.re, (float)z.im};
         }
     }
@@ -102,8 +113,8 @@ int sort_key_bits(int64_t n_buckets, int T, int W, int rb, int cb, int64_t n_vis
 
 hipError_t launch_sort(bool dbl, const void *src, const void *src_om, void *dst, void *dst_om, const int64_t *items,
                        int n_items, int64_t n_entries, int64_t n_buckets, int64_t bucket_per_band, int64_t n_vis,
-                       int T, int W, int rb, int cb, const BandDev *bands, void *phase, void *scratch,
-                       hipStream_t s) {
+                       int T, int W, int rb, int cb, const BandDev *bands, const GeomDev &geo, void *phase,
+                       void *scratch, hipStream_t s) {
     if (n_items <= 0 || n_entries <= 0) return hipSuccess;
     const int KS = T + W - 1;
     const int64_t nblk = (int64_t)((KS + rb - 1) / rb) * ((KS + cb - 1) / cb);
@@ -135,11 +146,11 @@ hipError_t launch_sort(bool dbl, const void *src, const void *src_om, void *dst,
     if (dbl)
         hipLaunchKernelGGL(sort_gather_kernel<double>, dim3(nb), dim3(kSortThreads), 0, s, (const Rec<double> *)src,
                            (const double *)src_om, (Rec<double> *)dst, (double *)dst_om, vout, n_entries, kout,
-                           sh_bucket, bucket_per_band, bands, (cplx<float> *)phase);
+                           sh_bucket, bucket_per_band, bands, geo, (cplx<float> *)phase);
     else
         hipLaunchKernelGGL(sort_gather_kernel<float>, dim3(nb), dim3(kSortThreads), 0, s, (const Rec<float> *)src,
                            (const float *)src_om, (Rec<float> *)dst, (float *)dst_om, vout, n_entries, kout,
-                           sh_bucket, bucket_per_band, bands, (cplx<float> *)phase);
+                           sh_bucket, bucket_per_band, bands, geo, (cplx<float> *)phase);
     return hipGetLastError();
 }
 

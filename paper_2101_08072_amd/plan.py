@@ -55,7 +55,8 @@ class Plan:
     the device tensors (the library borrows them)."""
 
     def __init__(self, uvw, freq, weight, flag, chan_band, n_band, nx, ny, cellx, celly,
-                 options: Options | None = None, count_scratch: torch.Tensor | str | None = None):
+                 options: Options | None = None, count_scratch: torch.Tensor | str | None = None,
+                 offset: tuple[int, int] = (0, 0)):
         self.lib = _lib.load()
         self.opt = options or Options()
         self.real = torch.float64 if self.opt.precision == "fp64" else torch.float32
@@ -82,6 +83,7 @@ class Plan:
         prob.flag = 0 if self.flag is None else self.flag.data_ptr()
         prob.nx, prob.ny = self.nx, self.ny
         prob.cellx, prob.celly = float(cellx), float(celly)
+        prob.offx, prob.offy = int(offset[0]), int(offset[1])   # facet: centre pixel's offset
         self._prob = prob
         copt = self.opt.to_c()
         handle = ctypes.c_void_p()
@@ -197,6 +199,13 @@ class Plan:
         out = self.vis() if out is None else out
         self._chk(out, (self.n_row, self.n_chan), self.cplx)
         _lib.check(self.lib.pfb_degrid(self.handle, _ptr(image), _ptr(out), _stream()))
+        return out
+
+    def degrid_add(self, image: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """V += R x (flagged entries of V untouched)."""
+        self._chk(image, (self.n_band, self.nx, self.ny), self.real)
+        self._chk(out, (self.n_row, self.n_chan), self.cplx)
+        _lib.check(self.lib.pfb_degrid_add(self.handle, _ptr(image), _ptr(out), _stream()))
         return out
 
     def hessian(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

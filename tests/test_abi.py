@@ -130,3 +130,24 @@ def test_epsilon_option_validation_without_gpu(lib):
     opt.precision, opt.epsilon = 1, 1e-16     # beyond the FP64 path (W <= 16)
     assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
     assert b"FP64" in lib.pfb_last_error()
+
+
+def test_facet_offsets_need_the_fp32_w_stacked_path(lib):
+    """A facet offset is refused in FP64 mode and in flat mode before any device access."""
+    import numpy as np
+    from paper_2101_08072_amd import _lib
+    freq = np.array([1e9, 1.1e9])
+    cb = np.array([0, 0], np.int32)
+    prob = _lib.PfbProblem()
+    prob.n_row, prob.n_chan, prob.n_band = 10, 2, 1
+    prob.chan_band, prob.freq = cb.ctypes.data, freq.ctypes.data
+    prob.uvw, prob.weight = 16, 16            # never dereferenced: validation fails first
+    prob.nx, prob.ny, prob.cellx, prob.celly = 64, 64, 1e-4, 1e-4
+    prob.offx, prob.offy = 32, -32
+    h = ctypes.c_void_p()
+    opt = _lib.PfbOptions()
+    opt.precision = 1
+    assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -4
+    opt.precision, opt.flat = 0, 1
+    assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -4
+    assert b"facet" in lib.pfb_last_error()
