@@ -40,6 +40,12 @@ pfb_status fail(pfb_status st, const char *fmt, ...) {
     } while (0)
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+// smallest power of two >= v (v >= 1)
+int next_pow2(int64_t v) {
+    int p = 1;
+    while (p < v) p *= 2;
+    return p;
+}
 int ilog2(int64_t v) {
     int l = 0;
     while ((int64_t(1) << l) < v) ++l;
@@ -214,6 +220,7 @@ struct pfb_plan {
     double s_min = 0.0, s_max = 0.0;
     int band_batch = 1;
     int conv_cgc = 1;
+    int conv_lx = 0, conv_ly = 0;
     int ldh = 0;
     int log2_lmax = 0;
     std::vector<double> cheb;
@@ -242,8 +249,10 @@ GeomDev base_geom(const pfb_plan &P, int nx, int ny, bool flat) {
     GeomDev g{};
     g.nx = nx;
     g.ny = ny;
-    g.gx = 2 * nx;
-    g.gy = 2 * ny;
+    // oversampled grid: the smallest power of two >= 2 n (sigma = 2 for power-of-two
+    // sides, 2 .. 4 otherwise; the ES kernel's error only falls with sigma)
+    g.gx = next_pow2(2 * (int64_t)nx);
+    g.gy = next_pow2(2 * (int64_t)ny);
     g.T = P.opt.tile;
     g.ntx = g.gx / g.T;
     g.nty = g.gy / g.T;
@@ -396,6 +405,8 @@ ConvArgs conv_args(const pfb_plan *P) {
     ConvArgs a{};
     a.n_band = P->prob.n_band;
     a.nx = P->prob.nx;
+    a.lx = P->conv_lx;
+    a.ly = P->conv_ly;
     a.ny = P->prob.ny;
     a.ldh = P->ldh;
     a.cgc = P->conv_cgc;
@@ -695,8 +706,11 @@ pfb_status count_and_layout(pfb_plan *P, char *tmp, hipStream_t stream) {
         P->tw_host[2 * e2] = std::cos(a);
         P->tw_host[2 * e2 + 1] = std::sin(a);
     }
-    P->conv_cgc = conv_group_cols(dbl, pr.nx);
-    P->ldh = ((pr.ny + 1 + 15) / 16) * 16;
+    // zero-padded grid of the PSF convolution: powers of two >= 2 nx, 2 ny
+    P->conv_lx = next_pow2(2 * (int64_t)pr.nx);
+    P->conv_ly = next_pow2(2 * (int64_t)pr.ny);
+    P->conv_cgc = conv_group_cols(dbl, P->conv_lx / 2);
+    P->ldh = ((P->conv_ly / 2 + 1 + 15) / 16) * 16;
 
     // band batch
     P->band_batch = opt.band_batch > 0 ? std::min(opt.band_batch, pr.n_band) : pr.n_band;
@@ -759,14 +773,16 @@ pfb_status count_and_layout(pfb_plan *P, char *tmp, hipStream_t stream) {
     }
     P->o_vals = L.take((size_t)pr.n_row * pr.n_chan * csz);
     P->o_psfimg = L.take((size_t)nb * 4 * Pimg * P->rsz);
-    P->o_t1c = L.take((size_t)nb * 2 * pr.nx * P->ldh * csz);
-    P->o_psfhat = L.take((size_t)nb * 2 * pr.nx * P->ldh * P->rsz);
+    P->o_t1c = L.take((size_t)nb * P->conv_lx * P->ldh * csz);
+    P->o_psfhat = L.take((size_t)nb * P->conv_lx * P->ldh * P->rsz);
     P->vec_bytes = ((Pimg * nb * P->rsz) + 255) & ~size_t(255);
     P->o_vec = L.take(6 * P->vec_bytes);
     {
         ConvArgs ca{};
         ca.nx = pr.nx;
         ca.ny = pr.ny;
+        ca.lx = P->conv_lx;
+        ca.ly = P->conv_ly;
         P->max_partials = std::max(vec_partials_per_band((int64_t)Pimg), conv_partials_per_band(dbl, ca));
     }
     P->o_partials = L.take((size_t)nb * P->max_partials * sizeof(double));
@@ -800,8 +816,8 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     if (pr.n_row * pr.n_chan >= (int64_t(1) << 31))
         return fail(PFB_EUNSUPPORTED, "n_row * n_chan must be below 2^31");
     if (!pr.chan_band || !pr.freq || !pr.uvw || !pr.weight) return fail(PFB_EINVAL, "NULL array in problem");
-    if (!is_pow2(pr.nx) || !is_pow2(pr.ny) || pr.nx < 16 || pr.ny < 16)
-        return fail(PFB_EINVAL, "nx and ny must be powers of two >= 16 (got %d x %d)", pr.nx, pr.ny);
+    if ((pr.nx & 1) || (pr.ny & 1) || pr.nx < 16 || pr.ny < 16)
+        return fail(PFB_EINVAL, "nx and ny must be even and >= 16 (got %d x %d)", pr.nx, pr.ny);
     if (!(pr.cellx > 0) || !(pr.celly > 0) || !std::isfinite(pr.cellx) || !std::isfinite(pr.celly))
         return fail(PFB_EINVAL, "cell sizes must be positive and finite");
     if (opt.precision != PFB_FP32 && opt.precision != PFB_FP64) return fail(PFB_EINVAL, "unknown precision");
@@ -830,7 +846,8 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     if (opt.tile == 0) opt.tile = std::max(8, std::min(dbl ? 8 : 32, std::min(pr.nx, pr.ny)));
     if (!is_pow2(opt.tile) || opt.tile < 8 || opt.tile > 64)
         return fail(PFB_EINVAL, "tile must be a power of two in [8, 64]");
-    if (2 * std::min(pr.nx, pr.ny) < 2 * opt.tile) return fail(PFB_EINVAL, "tile larger than half the grid");
+    if (std::min(next_pow2(2 * (int64_t)pr.nx), next_pow2(2 * (int64_t)pr.ny)) < 2 * opt.tile)
+        return fail(PFB_EINVAL, "tile larger than half the grid");
     if (gridder_lds_bytes(dbl, opt.support, opt.tile, opt.flat != 0) > kMaxLdsBytes)
         return fail(PFB_EINVAL, "tile %d with support %d needs %zu bytes of LDS per block (at most %zu)", opt.tile,
                     opt.support, gridder_lds_bytes(dbl, opt.support, opt.tile, opt.flat != 0), kMaxLdsBytes);
@@ -840,7 +857,7 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     // the PSF gridder's (a 2n x 2n image) 4n; in FP64 the latter stop at n = 2048, so
     // larger FP64 plans serve grid, degrid and the Hessian but not the PSF
     const int max_row = dbl ? 8192 : 16384;
-    if (2 * pr.nx > max_row || 2 * pr.ny > max_row)
+    if (next_pow2(2 * (int64_t)pr.nx) > max_row || next_pow2(2 * (int64_t)pr.ny) > max_row)
         return fail(PFB_EUNSUPPORTED, "image %d x %d needs FFT rows longer than %d for this precision", pr.nx, pr.ny,
                     max_row);
     if ((pr.offx || pr.offy) && (dbl || opt.flat))

@@ -135,12 +135,14 @@ hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s);  //
 
 // PSF convolution machinery.
 struct ConvArgs {
-    int n_band, nx, ny, ldh;   // image nx x ny; per-band stride 2 nx ldh, ldh >= ny + 1 rounded to 16
+    int n_band, nx, ny, ldh;   // image nx x ny; per-band stride lx ldh, ldh >= ly / 2 + 1 rounded to 16
+    int lx, ly;                // zero-padded grid: powers of two >= 2 nx, 2 ny (no wrap-around
+                               // within the crop of the linear convolution)
     int cgc;                   // columns per group of the group-major layout (conv_group_cols)
     const void *tw;
     int log2_lmax;
-    void *t1c;                 // [n_band][2nx ldh] complex: row spectra, group-major
-    void *psfhat;              // [n_band][2nx ldh] real: PSF spectrum, group-major, even/odd split
+    void *t1c;                 // [n_band][lx ldh] complex: row spectra, group-major
+    void *psfhat;              // [n_band][lx ldh] real: PSF spectrum, group-major, even/odd split
     double *partials;          // [n_band][max_partials]
     int max_partials;
     double *scal;              // [n_band][8] device scalars

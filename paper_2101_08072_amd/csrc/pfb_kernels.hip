@@ -2098,8 +2098,11 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a,
     auto load = [&](int i, int r) -> R {
         R v = R(0);
         if (psf) {
-            const int si = wrapi(i + nx, 2 * nx), sj = wrapi(r + ny, 2 * ny);
-            v = x[((size_t)b * 2 * nx + si) * 2 * ny + sj];
+            // grid index i holds offset di = i (first half) or i - lx (second half) of the
+            // PSF; offsets outside [-nx, nx) x [-ny, ny) are zero
+            const int di = i < a.lx / 2 ? i : i - a.lx, dj = r < a.ly / 2 ? r : r - a.ly;
+            if (di >= -nx && di < nx && dj >= -ny && dj < ny)
+                v = x[((size_t)b * 2 * nx + di + nx) * 2 * ny + dj + ny];
         } else if (r < ny) {
             const size_t pix = ((size_t)b * nx + i) * ny + r;
             if (IN == CONV_IN_X) {
@@ -2121,10 +2124,11 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a,
         },
         [](int, int, const cplx<R> &) {});
     // group-major store: frequency k = g CG + cc of row i at (g nrows + i) CG + cc
-    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + (size_t)b * 2 * nx * a.ldh;
+    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + (size_t)b * a.lx * a.ldh;
     const int lgc = __builtin_ctz(a.cgc), cmask = a.cgc - 1;
-    for (int id = threadIdx.x; id < C * (ny + 1); id += row_threads<LOG2L>()) {
-        const int c = id / (ny + 1), k = id - c * (ny + 1);
+    constexpr int NK = L / 2 + 1;   // frequencies 0 .. L/2 of a real row
+    for (int id = threadIdx.x; id < C * NK; id += row_threads<LOG2L>()) {
+        const int c = id / NK, k = id - c * NK;
         const cplx<R> z = buf[c * ld + Lds<R, LOG2L>::pad(k)];
         const cplx<R> zc = conj(buf[c * ld + Lds<R, LOG2L>::pad((L - k) & (L - 1))]);
         const size_t o = (((size_t)(k >> lgc) * nrows + ig * 2 * C + 2 * c) << lgc) + (k & cmask);
@@ -2181,13 +2185,15 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
     cplx<R> *buf = twl + kTwEntries;
     const TwTab<R> tt = tw_fill<R, NT>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
-    const int G = (a.ny + CG) / CG;   // groups of the ny + 1 columns
+    const int G = (a.ly / 2 + CG) / CG;   // groups of the ly / 2 + 1 columns
     const int xcd = blockIdx.x & 7, jb = blockIdx.x >> 3;
     const int sub = jb % NSUB, gi = (jb / NSUB) * 8 + xcd;
     if (gi >= a.n_band * G) return;   // the grid is padded to whole rounds of eight
     const int g = gi % G, b = gi / G;
-    const size_t boff = (size_t)b * 2 * a.nx * a.ldh;
-    cplx<R> *T = reinterpret_cast<cplx<R> *>(a.t1c) + boff + (size_t)g * (PSF ? 2 * N : N) * CG + sub * C;
+    const size_t boff = (size_t)b * a.lx * a.ldh;
+    const int nin = PSF ? 2 * N : a.nx;   // rows with data; the rest of the padded column is zero
+    // a group holds the rows the row pass wrote: all 2N of the PSF, the image's nx otherwise
+    cplx<R> *T = reinterpret_cast<cplx<R> *>(a.t1c) + boff + (size_t)g * (PSF ? 2 * N : a.nx) * CG + sub * C;
     R *H = reinterpret_cast<R *>(a.psfhat) + boff + (size_t)g * 2 * N * CG + sub * C;
     const int sh2n = a.log2_lmax - (LOG2N + 1);   // table step of w = exp(-2 pi i / 2N)
     const int shn = a.log2_lmax - LOG2N;
@@ -2206,7 +2212,7 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const int r = j + t * M;
-                cplx<R> x = T[r * CG + c];
+                cplx<R> x = r < nin ? T[r * CG + c] : cplx<R>{R(0), R(0)};
                 if (PSF) {
                     const cplx<R> hi = T[(r + N) * CG + c];
                     x = p == 0 ? x + hi : x - hi;
@@ -2272,7 +2278,8 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 if (p == 0) ev[t] = v[t];
-                else T[(j + t * M) * CG + c] = ev[t] + v[t] * twiddle<R, true>(tt, (j + t * M) << sh2n);
+                else if (j + t * M < a.nx)   // the crop: rows 0 .. nx - 1
+                    T[(j + t * M) * CG + c] = ev[t] + v[t] * twiddle<R, true>(tt, (j + t * M) << sh2n);
             }
         }
         __syncthreads();
@@ -2322,18 +2329,18 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a,
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int ig = lb % ngrp;
     const int b = lb / ngrp;
-    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + (size_t)b * 2 * nx * a.ldh;
+    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + (size_t)b * a.lx * a.ldh;
     const int lgc = __builtin_ctz(a.cgc), cmask = a.cgc - 1;
-    const R scale = R(1) / (R(4) * R(nx) * R(ny));
+    const R scale = R(1) / ((R)a.lx * (R)a.ly);
     double part = 0.0;
     row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>()>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
         [&](int c, int k) -> cplx<R> {
             // group-major load of rows i, i + 1 at frequency kk (Hermitian: k > ny reads L - k)
-            const int kk = k <= ny ? k : L - k;
+            const int kk = k <= L / 2 ? k : L - k;
             const size_t o = (((size_t)(kk >> lgc) * nx + ig * 2 * C + 2 * c) << lgc) + (kk & cmask);
             cplx<R> xa = t1[o], xb = t1[o + a.cgc];
-            if (k > ny) {
+            if (k > L / 2) {
                 xa = conj(xa);
                 xb = conj(xb);
             }
@@ -2364,13 +2371,13 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a,
 
 template <typename R>
 static hipError_t conv_columns(const ConvArgs &a, int psf, hipStream_t s) {
-    return dispatch_int<4, 12>(__builtin_ctz(a.nx), [&](auto Lc) -> hipError_t {
+    return dispatch_int<4, 12>(__builtin_ctz(a.lx) - 1, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         constexpr int CG = conv_layout_cg<R, LG>();
         constexpr int CB = conv_cgc<R, LG>();   // columns per block
         using K = ConvCols<R, LG, CB>;
         if (a.cgc != CG) return hipErrorInvalidValue;
-        const int G = (a.ny + CG) / CG;
+        const int G = (a.ly / 2 + CG) / CG;
         const int nb = ((a.n_band * G + 7) / 8) * 8 * (CG / CB);
         if (psf) PFB_LAUNCH_NT((conv_cols_kernel<R, LG, CB, CG, true>), nb, K::NT, K::lds, s, a);
         else PFB_LAUNCH_NT((conv_cols_kernel<R, LG, CB, CG, false>), nb, K::NT, K::lds, s, a);
@@ -2378,13 +2385,21 @@ static hipError_t conv_columns(const ConvArgs &a, int psf, hipStream_t s) {
     });
 }
 
+// row pairs per block of the row passes: at most cmax, and a power of two that
+// divides the nx / 2 pairs of the image
+static int conv_row_pairs(int cmax, int nx) {
+    int C = 1;
+    while (2 * C <= cmax && (nx / 2) % (2 * C) == 0) C *= 2;
+    return C;
+}
+
 template <typename R>
 static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, void *y, const void *aux_out,
                              double sigma, int in_mode, int out_mode, hipStream_t s) {
-    const int lg = __builtin_ctz(2 * a.ny);
+    const int lg = __builtin_ctz(a.ly);
     hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const int C = std::min(rows_per_block<R, LG>(), a.nx / 2);   // vectors = row pairs
+        const int C = conv_row_pairs(rows_per_block<R, LG>(), a.nx);   // vectors = row pairs
         const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_band * (a.nx / (2 * C));
         const R *xr = reinterpret_cast<const R *>(x);
@@ -2399,7 +2414,7 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
     if (e != hipSuccess) return e;
     return dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const int C = std::min(rows_per_block<R, LG>(), a.nx / 2);   // vectors = row pairs
+        const int C = conv_row_pairs(rows_per_block<R, LG>(), a.nx);   // vectors = row pairs
         const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_band * (a.nx / (2 * C));
         R *yr = reinterpret_cast<R *>(y);
@@ -2424,26 +2439,26 @@ hipError_t launch_psf_conv(bool dbl, const ConvArgs &a, const void *x, void *aux
 
 int conv_partials_per_band(bool dbl, const ConvArgs &a) {
     // S3 writes one partial per block of 2C rows; C depends on the row length
-    const int lg = __builtin_ctz(2 * a.ny);
+    const int lg = __builtin_ctz(a.ly);
     int C = 1;
     (void)dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         C = dbl ? rows_per_block<double, LG>() : rows_per_block<float, LG>();
         return hipSuccess;
     });
-    return a.nx / (2 * std::min(C, a.nx / 2));
+    return a.nx / (2 * conv_row_pairs(C, a.nx));
 }
 
 template <typename R>
 static hipError_t psfhat_t(const ConvArgs &a, const void *psf_img, hipStream_t s) {
-    const int lg = __builtin_ctz(2 * a.ny);
+    const int lg = __builtin_ctz(a.ly);
     hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const int C = std::min(rows_per_block<R, LG>(), a.nx);          // vectors = row pairs of 2nx rows
+        const int C = std::min(rows_per_block<R, LG>(), a.lx / 2);      // vectors = row pairs of lx rows
         const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-        const int nb = a.n_band * (a.nx / C);
+        const int nb = a.n_band * (a.lx / (2 * C));
         PFB_LAUNCH_NT((s1_kernel<R, LG, CONV_IN_X>), nb, row_threads<LG>(), lds, s, a, reinterpret_cast<const R *>(psf_img),
-                   (R *)nullptr, 2 * a.nx, C, 1);
+                   (R *)nullptr, a.lx, C, 1);
         return hipSuccess;
     });
     if (e != hipSuccess) return e;

@@ -58,8 +58,8 @@ def test_null_arguments_rejected_without_gpu(lib):
 
 
 def test_shape_validation_without_gpu(lib):
-    """Checks that run before any device access: odd / non-power-of-two sides,
-    bad bands, bad options."""
+    """Checks that run before any device access: odd or too small sides, bad bands,
+    bad options."""
     import numpy as np
     from paper_2101_08072_amd import _lib
     freq = np.array([1e9, 1.1e9])
@@ -68,11 +68,13 @@ def test_shape_validation_without_gpu(lib):
     prob.n_row, prob.n_chan, prob.n_band = 10, 2, 1
     prob.chan_band, prob.freq = cb.ctypes.data, freq.ctypes.data
     prob.uvw, prob.weight = 16, 16            # never dereferenced: validation fails first
-    prob.nx, prob.ny, prob.cellx, prob.celly = 24, 32, 1e-4, 1e-4
+    prob.nx, prob.ny, prob.cellx, prob.celly = 25, 32, 1e-4, 1e-4
     h = ctypes.c_void_p()
     opt = _lib.PfbOptions()
     assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
-    assert b"powers of two" in lib.pfb_last_error()
+    assert b"even" in lib.pfb_last_error()
+    prob.nx = 14
+    assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1
     prob.nx = 32
     opt.support = 3
     assert lib.pfb_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt), None) == -1

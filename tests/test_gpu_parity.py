@@ -326,7 +326,7 @@ def test_error_paths():
     x = torch.zeros((1, 16, 16), dtype=torch.float32, device="cuda")
     with pytest.raises(PfbError, match="PFB_ESTATE"):
         plan.psf_conv(x)
-    bad = synth.Problem(**{**prob.__dict__, "nx": 24})
+    bad = synth.Problem(**{**prob.__dict__, "nx": 23})      # odd side
     with pytest.raises(PfbError, match="PFB_EINVAL"):
         make_plan(bad, "fp32")
     with pytest.raises(PfbError, match="PFB_EINVAL"):
