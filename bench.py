@@ -93,13 +93,13 @@ def kernel_models(info, prob, M, W, csz, rsz):
         "interp_kernel": ("alu", spread_flops),     # FP64 mode
         "interp4_kernel": ("alu", spread_flops),    # FP32
         # row inverse DFT of every w-plane: read its occupied tiles (the rest of the
-        # plane is zero), write the cropped rows
-        "g1_rows_kernel": ("hbm", (info["occ_tiles"] * T * T + nwt * gx * ny) * csz),
-        # column step A (in place on the cropped rows)
-        "colA_kernel": ("hbm", nwt * gx * ny * 2 * csz),
-        # column step B + w-phase + accumulation over planes + correction
-        "g3_kernel": ("hbm", nwt * gx * ny * csz + 2 * P * rsz),
-        "d2_kernel": ("hbm", nwt * gx * ny * 2 * csz),
+        # plane is zero), write the cropped rows of tile rows that hold them
+        "g1_rows_kernel": ("hbm", (info["occ_tiles"] * T * T + info["occ_tile_rows"] * T * ny) * csz),
+        # column passes (plane loop inside): per column and plane two N-point FFTs
+        # (N = gx / 2, 5 N log2 N flops each) and about 24 N flops of twiddles, the
+        # even/odd combination and the w-phase product (its sincos not counted)
+        "wgrid_cols_kernel": ("alu", nwt * ny * (10.0 * (gx // 2) * math.log2(gx // 2) + 24.0 * (gx // 2))),
+        "wdegrid_cols_kernel": ("alu", nwt * ny * (10.0 * (gx // 2) * math.log2(gx // 2) + 24.0 * (gx // 2))),
         # forward row DFT: read the cropped rows of tile rows the interpolation
         # reaches, write the tiles it reads
         "d3_rows_kernel": ("hbm", (info["need_tile_rows"] * T * ny + info["need_tiles"] * T * T) * csz),

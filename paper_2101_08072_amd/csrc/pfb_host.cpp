@@ -52,23 +52,6 @@ int ilog2(int64_t v) {
     return l;
 }
 
-ColSplit make_split(int n) {
-    ColSplit c;
-    const int lg = ilog2(n);
-    if (lg <= 9) {
-        c.n1 = n;
-        c.n2 = 1;
-        c.log2n1 = lg;
-        c.log2n2 = 0;
-    } else {
-        c.log2n1 = (lg + 1) / 2;
-        c.log2n2 = lg / 2;
-        c.n1 = 1 << c.log2n1;
-        c.n2 = 1 << c.log2n2;
-    }
-    return c;
-}
-
 // ---- Fourier transform of the ES kernel --------------------------------------
 // Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
@@ -168,7 +151,6 @@ struct Layout {
 // One NUFFT configuration (main w-stacked operator or the flat PSF gridder).
 struct GridderHost {
     GeomDev g{};
-    ColSplit cs{};
     std::vector<BandDev> bands;
     std::vector<int64_t> offsets;        // n_band * ntiles * nj0max + 1
     std::vector<int64_t> hoffsets;       // same, over the home-entry list
@@ -181,7 +163,6 @@ struct GridderHost {
     // interpolation may read it (occ dilated by one tile, the halo reach)
     std::vector<uint8_t> occ, need;
     std::vector<uint8_t> occ_row, need_row;   // per (band, plane, tile row): any such tile
-    bool row_skip = false;   // column passes skip empty rows (worth it when many rows are empty)
     bool mfma = false;                   // FP32 w-stacked: matrix-core spread (window sort, phase table)
     int sort_rb = 1, sort_cb = 1;        // sort blocks of base rows x columns
     int64_t n_entries = 0;
@@ -234,7 +215,7 @@ struct pfb_plan {
     char *ws = nullptr;
     bool counted = false, ws_ready = false, psf_ready = false;
     size_t o_freq = 0, o_cb = 0, o_cheb = 0, o_tw = 0, o_flagged = 0, o_flagcur = 0;
-    size_t o_planes = 0, o_t1 = 0, o_t2 = 0, o_vals = 0, o_psfimg = 0;
+    size_t o_planes = 0, o_t1 = 0, o_vals = 0, o_psfimg = 0;
     size_t o_t1c = 0, o_psfhat = 0, o_vec = 0, o_partials = 0, o_scal = 0, o_absmax = 0;
     size_t planes_bytes = 0, t_bytes = 0, vec_bytes = 0;
     size_t o_sorttmp = 0;   // scratch for the plan-time sort (aliases the w-plane area when it fits)
@@ -349,14 +330,6 @@ void build_work(GridderHost &G, const std::vector<unsigned> &counts, const std::
                 }
         }
         std::stable_sort(gw.begin(), gw.end(), [](auto &a, auto &b) { return a.first > b.first; });
-        if (b == g.n_band - 1) {
-            // per-row flag tests cost the column passes about 8 %; they pay when at
-            // least half of the tile rows (over bands and planes) have no occupied
-            // tile (measured: break-even near 40 %, a 4 % shorter step at 70 %)
-            size_t empty = 0;
-            for (uint8_t f : G.occ_row) empty += f == 0;
-            G.row_skip = empty * 2 >= G.occ_row.size();
-        }
         std::stable_sort(iw.begin(), iw.end(), [](auto &a, auto &b) { return a.first > b.first; });
         for (auto &x : gw) G.gwork.push_back(x.second);
         for (auto &x : iw) G.iwork.push_back(x.second);
@@ -385,19 +358,17 @@ XformArgs xform_args(const pfb_plan *P, const GridderHost &G, int b0, int nbb) {
     a.bands = G.d_bands;
     a.band0 = b0;
     a.n_bb = nbb;
-    a.cs = G.cs;
     a.tw = P->p(P->o_tw);
     a.log2_lmax = P->log2_lmax;
     a.planes = P->p(P->o_planes);
     a.t1 = P->p(P->o_t1);
-    a.t2 = P->p(P->o_t2);
     a.corr2d = G.corr2d ? G.d_corr2d : nullptr;
     a.corr_x = G.d_corrx;
     a.corr_y = G.d_corry;
     a.occ = G.d_occ;
     a.need = G.d_need;
-    a.occ_row = G.row_skip ? G.d_occ_row : nullptr;
-    a.need_row = G.row_skip ? G.d_need_row : nullptr;
+    a.occ_row = G.d_occ_row;
+    a.need_row = G.d_need_row;
     return a;
 }
 
@@ -757,11 +728,15 @@ pfb_status count_and_layout(pfb_plan *P, char *tmp, hipStream_t stream) {
         }
     }
     P->planes_bytes = (size_t)P->band_batch * per_band_planes;
-    P->t_bytes = (size_t)P->band_batch *
-                 std::max((size_t)M.g.nwmax * M.g.gx * M.g.ny, (size_t)Q.g.gx * Q.g.ny) * csz;
+    {
+        // cropped row spectra, columns padded to whole groups of plane_group_cols
+        const size_t cg = (size_t)plane_group_cols(dbl);
+        auto padded = [cg](int n) { return ((size_t)n + cg - 1) / cg * cg; };
+        P->t_bytes = (size_t)P->band_batch *
+                     std::max((size_t)M.g.nwmax * M.g.gx * padded(M.g.ny), (size_t)Q.g.gx * padded(Q.g.ny)) * csz;
+    }
     P->o_planes = L.take(P->planes_bytes);
     P->o_t1 = L.take(P->t_bytes);
-    P->o_t2 = L.take(M.cs.n2 > 1 ? P->t_bytes : 256);
     {
         const size_t recsz = dbl ? sizeof(Rec<double>) : sizeof(Rec<float>);
         size_t need = 0;
@@ -927,7 +902,6 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     // geometry of the two gridders
     GridderHost &M = P->main;
     M.g = base_geom(*P, pr.nx, pr.ny, opt.flat != 0);
-    M.cs = make_split(M.g.gx);
     // n - 1 over the pixels lies in [s_min, s_max] (s_max = 0 when the image holds the
     // phase centre; a facet away from it has a narrower range and so fewer w-planes)
     P->s_min = opt.flat ? 0.0 : -lmax2 / (1.0 + std::sqrt(1.0 - lmax2));
@@ -962,7 +936,6 @@ pfb_status pfb_plan_create(pfb_plan **out, const pfb_problem *prob, const pfb_op
     if (M.mfma) mfma_window(opt.support, &M.sort_rb, &M.sort_cb);
     GridderHost &Q = P->psf;
     Q.g = base_geom(*P, 2 * pr.nx, 2 * pr.ny, true);
-    Q.cs = make_split(Q.g.gx);
     Q.bands.assign(pr.n_band, BandDev{0.0, 1.0, 0.0, 1, 1});
     Q.g.nj0max = 1;
     Q.g.nwmax = 1;

@@ -76,10 +76,4 @@ struct BucketArgs {
     unsigned long long *flag_cursor;
 };
 
-// Launch-side description of the FFT factorisation of a column transform.
-struct ColSplit {
-    int n1, n2;       // L = n1 * n2; n2 == 1 means a single pass of length n1
-    int log2n1, log2n2;
-};
-
 }  // namespace pfb

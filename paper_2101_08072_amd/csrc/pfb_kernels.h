@@ -110,10 +110,10 @@ struct XformArgs {
     GeomDev g;
     const BandDev *bands;
     int band0, n_bb;       // bands [band0, band0 + n_bb) of the batch
-    ColSplit cs;           // factorisation of gx
     const void *tw;
     int log2_lmax;
-    void *planes, *t1, *t2;
+    void *planes;          // [n_bb][nwmax][gx][gy] uv planes
+    void *t1;              // [n_bb][nwmax] cropped row spectra, group-major (plane_group_cols)
     const void *corr2d;    // [n_band][nx][ny] or null
     const void *corr_x, *corr_y;  // 1-D tables when corr2d is null
     const void *image_in;  // degrid input [n_band][nx][ny]
@@ -123,13 +123,15 @@ struct XformArgs {
     // plane only where occ is set (elsewhere it is zero), the degrid transform
     // writes it only where need is set
     const uint8_t *occ, *need;
-    // [n_band][nwmax][ntx]: some tile of that tile row is occ / need, or null.
-    // When set, cropped rows of tile rows without occupied tiles are not written
-    // by the inverse row pass and are read as zero by the first column pass, and
-    // rows of tile rows without needed tiles are not written by the last column
-    // pass of the degrid
+    // [n_band][nwmax][ntx]: some tile of that tile row is occ / need.  Cropped
+    // rows of tile rows without occupied tiles are not written by the inverse row
+    // pass and are read as zero by the grid's column pass; rows of tile rows
+    // without needed tiles are neither written by the degrid's column pass nor
+    // read by its row pass
     const uint8_t *occ_row, *need_row;
 };
+// complex values per group of the plane intermediate t1 (one 128-byte line)
+int plane_group_cols(bool dbl);
 hipError_t launch_grid_xform(bool dbl, const XformArgs &a, hipStream_t s);    // planes -> image
 hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s);  // image -> planes
 

@@ -2,7 +2,8 @@
 //   * bucketing of visibilities into (band, uv tile, w base plane) buckets
 //   * ES-kernel gridding with owner-computes uv tiles (no global atomics)
 //   * ES-kernel degridding with a sliding window of w-planes in LDS
-//   * the 2-D FFT passes (LDS radix-8 DIT, four-step for long columns) with
+//   * the 2-D FFT passes (LDS radix-8 rows; single-pass columns that split the
+//     zero-padded transforms into two halves and loop over the w-planes) with
 //     the w-phase, cropping, padding and grid correction fused into them
 //   * PSF convolution by zero-padded FFT and the CG / power-iteration kernels
 #include <type_traits>
@@ -1673,6 +1674,19 @@ __host__ __device__ constexpr int rows_per_block() {
     return c;
 }
 
+// Plane intermediate of the grid and degrid transforms (cropped row spectra),
+// group-major: column iy = g CG + c of uv row u of plane (bb, j) sits at
+// T[(((bb nwmax + j) G + g) gx + u) CG + c], G = ceil(ny / CG), CG complex values
+// per 128-byte line.  The row passes store and load one whole line per group and
+// row; the gx rows of a group are one contiguous block for the column passes.
+template <typename R> __host__ __device__ constexpr int plane_cg() { return 128 / (int)sizeof(cplx<R>); }
+template <typename R> __device__ __forceinline__ size_t plane_at(const XformArgs &a, size_t plane, int u, int iy) {
+    constexpr int CG = plane_cg<R>();
+    const int G = (a.g.ny + CG - 1) / CG;
+    return ((plane * G + (size_t)(iy / CG)) * a.g.gx + u) * CG + (iy & (CG - 1));
+}
+int plane_group_cols(bool dbl) { return dbl ? plane_cg<double>() : plane_cg<float>(); }
+
 // G1: inverse row DFT of every plane row, keeping the ny cropped outputs.
 template <typename R, int LOG2L>
 __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformArgs a, int C) {
@@ -1693,7 +1707,7 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformA
     if (j >= nw) return;
     const size_t plane = (size_t)bb * a.g.nwmax + j;
     const cplx<R> *src = reinterpret_cast<const cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
-    cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.t1) + (plane * gx + (size_t)ug * C) * ny;
+    cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.t1);
     // tiles of these rows that hold spread values (the rest of the plane is zero
     // and is not read); rows whose tiles are all empty transform to zero
     const int lgT = __builtin_ctz(a.g.T), nty = a.g.nty;   // tiles are powers of two
@@ -1704,13 +1718,9 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformA
         const int c = k / nty, tv = k - c * nty;
         any |= occ[((row0 + c) >> lgT) * nty + tv] != 0;
     }
-    if (!__syncthreads_or(any)) {
-        // rows without occupied tiles transform to zero; with row flags the column
-        // pass reads them as zero, else they are written
-        if (!a.occ_row)
-            for (int id = threadIdx.x; id < C * ny; id += row_threads<LOG2L>()) dst[id] = cplx<R>{R(0), R(0)};
-        return;
-    }
+    // rows without occupied tiles transform to zero: not written, the column pass
+    // reads them as zero
+    if (!__syncthreads_or(any)) return;
     // output k of the row DFT is cropped column iy = k + ny / 2 (mod L), kept if iy < ny
     row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>()>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
@@ -1719,220 +1729,14 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformA
         },
         [&](int c, int k, const cplx<R> &v) {
             const int iy = (k + ny / 2) & (L - 1);
-            if (iy < ny) dst[(size_t)c * ny + iy] = v;
+            if (iy < ny) dst[plane_at<R>(a, plane, row0 + c, iy)] = v;
         });
 }
 
-// Column group width for column passes (contiguous complex values per row).
-template <typename R> __host__ __device__ constexpr int col_group() { return sizeof(R) == 4 ? 16 : 8; }
-
-// G2 / D1 / D2 helpers: step A of the four-step column transform.
-// Step A: for fixed r2, length-n1 DFT over rows r1*n2 + r2, times w_n^(-+r2 k1),
-// result stored at rows k1*n2 + r2.  INV selects the sign.
-// MODE 0 (grid, G2): in place on t1.  MODE 1 (degrid, D1): input computed from
-// the image with grid correction and the w-plane phase, output to t1.
-template <typename R, int LOG2N1, bool INV, int MODE>
-__global__ __launch_bounds__(kThreads) void colA_kernel(XformArgs a) {
-    constexpr int N1 = 1 << LOG2N1;
-    constexpr int C = col_group<R>();
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
-    const int ld = Lds<R, LOG2N1>::ld;
-    const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny;
-    const int n2 = a.cs.n2;
-    const int ncg = (ny + C - 1) / C;
-    int blk = blockIdx.x;
-    const int cg = blk % ncg;
-    blk /= ncg;
-    const int r2 = blk % n2;
-    blk /= n2;
-    const int j = blk % a.g.nwmax;
-    const int bb = blk / a.g.nwmax;
-    const int b = a.band0 + bb;
-    const BandDev bd = a.bands[b];
-    const int nw = a.g.flat ? 1 : bd.nw;
-    if (j >= nw) return;
-    const size_t plane = (size_t)bb * a.g.nwmax + j;
-    cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1) + plane * gx * ny;
-    const int col0 = cg * C;
-    const R wj = (R)(bd.w0 + j * bd.dw), sc = (R)bd.sc;
-    const int lgT = __builtin_ctz(a.g.T);
-    // row flags (null: rows are dense, every row is read and written)
-    const uint8_t *occ_row = a.occ_row ? a.occ_row + ((size_t)b * a.g.nwmax + j) * a.g.ntx : nullptr;
-    const uint8_t *need_row = a.need_row ? a.need_row + ((size_t)b * a.g.nwmax + j) * a.g.ntx : nullptr;
-    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
-        const int c = id % C, r1 = id / C;
-        const int col = col0 + c;
-        const int r = r1 * n2 + r2;
-        cplx<R> v{R(0), R(0)};
-        if (col < ny) {
-            if (MODE == 0) {
-                if (!occ_row || occ_row[r >> lgT]) v = t1[(size_t)r * ny + col];
-            } else {
-                const int i = wrapi(r + nx / 2, gx);
-                if (i < nx) {
-                    const size_t pix = ((size_t)b * nx + i) * ny + col;
-                    const R x = reinterpret_cast<const R *>(a.image_in)[pix];
-                    const R cr = a.corr2d ? reinterpret_cast<const R *>(a.corr2d)[pix]
-                                          : reinterpret_cast<const R *>(a.corr_x)[i] * reinterpret_cast<const R *>(a.corr_y)[col];
-                    v = cplx<R>{x * cr, R(0)};
-                    if (!a.g.flat) {
-                        const R s = pixel_sm1<R>(i, col, a.g) - sc;
-                        v = v * conj(cis_cycles<R>(wj * s));
-                    }
-                }
-            }
-        }
-        buf[c * ld + Lds<R, LOG2N1>::pad(dit_pos<LOG2N1>(r1))] = v;
-    }
-    __syncthreads();
-    lds_fft<R, INV, LOG2N1>(buf, C, ld, tt, a.log2_lmax - LOG2N1);
-    const int shift_n = a.log2_lmax - (a.cs.log2n1 + a.cs.log2n2);
-    const int nmask = gx - 1;
-    for (int id = threadIdx.x; id < C * N1; id += kThreads) {
-        const int c = id % C, k1 = id / C;
-        const int col = col0 + c;
-        if (col >= ny) continue;
-        // single-pass degrid: rows the forward row pass skips are not written
-        if (MODE == 1 && n2 == 1 && need_row && !need_row[k1 >> lgT]) continue;
-        cplx<R> v = buf[c * ld + Lds<R, LOG2N1>::pad(k1)];
-        if (n2 > 1) v = v * twiddle<R, INV>(tt, ((r2 * k1) & nmask) << shift_n);
-        t1[(size_t)(k1 * n2 + r2) * ny + col] = v;
-    }
-}
-
-// G3: step B of the inverse column transform (or the whole column when n1 = 1)
-// with the w-plane loop: accumulates Re(F_j e^{+2 pi i w_j (n - 1 - sc)}) over
-// planes in LDS, then applies the grid correction and writes the image.
-template <typename R, int LOG2N2>
-__global__ __launch_bounds__(kThreads) void g3_kernel(XformArgs a) {
-    constexpr int N2 = 1 << LOG2N2;
-    constexpr int C = col_group<R>();
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
-    const int ld = Lds<R, LOG2N2>::ld;
-    constexpr int NS = N2 + 1;                         // odd row stride of acc / sv (banks)
-    R *acc = reinterpret_cast<R *>(buf + C * ld);     // [C][NS]
-    R *sv = acc + C * NS;                              // [C][NS] (n - 1 - sc)
-    const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny;
-    const int n1 = a.cs.n1;
-    const int ncg = (ny + C - 1) / C;
-    int blk = blockIdx.x;
-    const int cg = blk % ncg;
-    blk /= ncg;
-    const int k1 = blk % n1;
-    const int bb = blk / n1;
-    const int b = a.band0 + bb;
-    const BandDev bd = a.bands[b];
-    const int nw = a.g.flat ? 1 : bd.nw;
-    const int col0 = cg * C;
-    const R sc = (R)bd.sc;
-    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
-        const int c = id % C, k2 = id / C;
-        acc[c * NS + k2] = R(0);
-        const int i = wrapi(k1 + n1 * k2 + nx / 2, gx);
-        const int col = col0 + c;
-        sv[c * NS + k2] = (!a.g.flat && i < nx && col < ny)
-                              ? pixel_sm1<R>(i, col, a.g) - sc
-                              : R(0);
-    }
-    for (int j = 0; j < nw; ++j) {
-        const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1) + ((size_t)bb * a.g.nwmax + j) * gx * ny;
-        // single pass (n1 == 1): t1 holds the inverse row pass's output, whose
-        // rows of tile rows without occupied tiles are zero and not written
-        const uint8_t *occ_row =
-            n1 == 1 && a.occ_row ? a.occ_row + ((size_t)b * a.g.nwmax + j) * a.g.ntx : nullptr;
-        for (int id = threadIdx.x; id < C * N2; id += kThreads) {
-            const int c = id % C, r2 = id / C;
-            const int col = col0 + c;
-            const int row = k1 * N2 + r2;
-            buf[c * ld + Lds<R, LOG2N2>::pad(dit_pos<LOG2N2>(r2))] =
-                col < ny && (!occ_row || occ_row[row >> __builtin_ctz(a.g.T)]) ? t1[(size_t)row * ny + col]
-                                                                                : cplx<R>{R(0), R(0)};
-        }
-        __syncthreads();
-        lds_fft<R, true, LOG2N2>(buf, C, ld, tt, a.log2_lmax - LOG2N2);
-        const R wj = (R)(bd.w0 + j * bd.dw);
-        for (int id = threadIdx.x; id < C * N2; id += kThreads) {
-            const int c = id % C, k2 = id / C;
-            const cplx<R> v = buf[c * ld + Lds<R, LOG2N2>::pad(k2)];
-            if (a.g.flat) {
-                acc[c * NS + k2] += v.re;
-            } else {
-                const cplx<R> ph = cis_cycles<R>(wj * sv[c * NS + k2]);
-                acc[c * NS + k2] += v.re * ph.re - v.im * ph.im;
-            }
-        }
-        __syncthreads();
-    }
-    R *img = reinterpret_cast<R *>(a.image_out) + (size_t)b * nx * ny;
-    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
-        const int c = id % C, k2 = id / C;
-        const int col = col0 + c;
-        const int i = wrapi(k1 + n1 * k2 + nx / 2, gx);
-        if (i >= nx || col >= ny) continue;
-        const size_t pix = (size_t)i * ny + col;
-        const R cr = a.corr2d ? reinterpret_cast<const R *>(a.corr2d)[(size_t)b * nx * ny + pix]
-                              : reinterpret_cast<const R *>(a.corr_x)[i] * reinterpret_cast<const R *>(a.corr_y)[col];
-        R v = acc[c * NS + k2] * cr;
-        if (a.zero_edge && (i == 0 || col == 0)) v = R(0);
-        img[pix] = v;
-    }
-}
-
-// D2: step B of the forward column transform, t1 (rows k1*n2 + r2) -> t2 (row k1 + n1 k2).
-template <typename R, int LOG2N2>
-__global__ __launch_bounds__(kThreads) void d2_kernel(XformArgs a) {
-    constexpr int N2 = 1 << LOG2N2;
-    constexpr int C = col_group<R>();
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, kThreads>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
-    const int ld = Lds<R, LOG2N2>::ld;
-    const int gx = a.g.gx, ny = a.g.ny;
-    const int n1 = a.cs.n1;
-    const int ncg = (ny + C - 1) / C;
-    int blk = blockIdx.x;
-    const int cg = blk % ncg;
-    blk /= ncg;
-    const int k1 = blk % n1;
-    blk /= n1;
-    const int j = blk % a.g.nwmax;
-    const int bb = blk / a.g.nwmax;
-    const int nw = a.g.flat ? 1 : a.bands[a.band0 + bb].nw;
-    if (j >= nw) return;
-    const size_t plane = (size_t)bb * a.g.nwmax + j;
-    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1) + plane * gx * ny;
-    cplx<R> *t2 = reinterpret_cast<cplx<R> *>(a.t2) + plane * gx * ny;
-    const int col0 = cg * C;
-    const int lgT = __builtin_ctz(a.g.T);
-    // rows the forward row pass skips are not written (null: all rows)
-    const uint8_t *need_row =
-        a.need_row ? a.need_row + ((size_t)(a.band0 + bb) * a.g.nwmax + j) * a.g.ntx : nullptr;
-    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
-        const int c = id % C, r2 = id / C;
-        const int col = col0 + c;
-        buf[c * ld + Lds<R, LOG2N2>::pad(dit_pos<LOG2N2>(r2))] =
-            col < ny ? t1[(size_t)(k1 * N2 + r2) * ny + col] : cplx<R>{R(0), R(0)};
-    }
-    __syncthreads();
-    lds_fft<R, false, LOG2N2>(buf, C, ld, tt, a.log2_lmax - LOG2N2);
-    for (int id = threadIdx.x; id < C * N2; id += kThreads) {
-        const int c = id % C, k2 = id / C;
-        const int col = col0 + c;
-        const int row = k1 + n1 * k2;
-        if (col < ny && (!need_row || need_row[row >> lgT])) t2[(size_t)row * ny + col] = buf[c * ld + Lds<R, LOG2N2>::pad(k2)];
-    }
-}
-
-// D3: forward row DFT of the ny placed inputs of each row, full output to the plane.
+// D3: forward row DFT of the ny placed inputs of each row (the rows the degrid
+// column pass wrote: tile rows with needed tiles), full output to the plane.
 template <typename R, int LOG2L>
-__global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformArgs a, int C, const void *src_v) {
+__global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformArgs a, int C) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
@@ -1949,7 +1753,7 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformA
     const int nw = a.g.flat ? 1 : a.bands[a.band0 + bb].nw;
     if (j >= nw) return;
     const size_t plane = (size_t)bb * a.g.nwmax + j;
-    const cplx<R> *src = reinterpret_cast<const cplx<R> *>(src_v) + (plane * gx + (size_t)ug * C) * ny;
+    const cplx<R> *src = reinterpret_cast<const cplx<R> *>(a.t1);
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
     // only tiles the interpolation may read are written; rows with none are skipped
     const int lgT = __builtin_ctz(a.g.T), nty = a.g.nty;   // tiles are powers of two
@@ -1966,11 +1770,319 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformA
         buf, C, ld, tt, a.log2_lmax - LOG2L,
         [&](int c, int r) -> cplx<R> {
             const int iy = (r + ny / 2) & (L - 1);
-            return iy < ny ? src[(size_t)c * ny + iy] : cplx<R>{R(0), R(0)};
+            return iy < ny ? src[plane_at<R>(a, plane, row0 + c, iy)] : cplx<R>{R(0), R(0)};
         },
         [&](int c, int k, const cplx<R> &v) {
             if (need[((row0 + c) >> lgT) * nty + (k >> lgT)]) dst[(size_t)c * L + k] = v;
         });
+}
+
+// Column passes of the w-plane transforms: for every column of the cropped row
+// spectra, the gx-point DFT over u between the uv rows and the image rows
+// i = 0 .. nx - 1, in one pass per plane with the plane loop inside the block.
+// With N = gx / 2, w = exp(-2 pi i / gx) and the image centred on the grid
+// origin (DFT index n = i - nx / 2, hx = nx / 2), nx <= N lets the gx-point
+// transforms split into N-point ones over even and odd u:
+//   grid   F(i) = sum_u G[u] w^(-u n) = E[i] + w^-i O[i],
+//          E, O = inverse N-point DFTs of G'[u] = G[u] w^(u hx) over even / odd u;
+//   degrid X[2k' + p] = w^(-(2k' + p) hx) DFT_N(x[i] w^(p i))[k']   (p = 0, 1),
+// so one column needs N complex values of LDS at a time.  The grid pass reads
+// only the rows of tile rows with occupied tiles (the others are zero and were
+// not written) and accumulates Re(F_j(i) e^(2 pi i w_j (n_i - 1 - sc))) over the
+// planes in registers before the grid correction; the degrid pass keeps the
+// corrected image column in registers and writes, for every plane, only the
+// rows of tile rows the forward row pass reads.
+template <typename R, int LOG2N, int C> struct WCols {
+    static constexpr int N = 1 << LOG2N;
+    static constexpr int NT0 = C * N / 8;   // one radix-8 butterfly per thread and stage
+    static constexpr int NT = NT0 < 64 ? 64 : NT0;
+    static_assert(NT0 <= 1024, "at most 1024 threads per block");
+    static constexpr int R0 = FftPlan<LOG2N>::radix(0);
+    static constexpr int ITER = (C * (N / R0) + NT - 1) / NT;   // innermost-stage items per thread
+    // the transform buffer, the twiddle table and two per-thread arrays of 8 values
+    // that live across the plane loop (kept in LDS, not in registers)
+    static constexpr size_t lds = (size_t)C * Lds<R, LOG2N>::ld * sizeof(cplx<R>) + kTwEntries * sizeof(cplx<R>) +
+                                  2 * 8 * (size_t)NT * sizeof(R);
+};
+// columns per block: the most (up to a whole group) whose C x N block spans at
+// most 1024 threads and 64 KiB of LDS
+template <typename R, int LG> constexpr int wcols_c() {
+    constexpr int N = 1 << LG;
+    constexpr int a = 4096 / N, b = (int)(65536 / ((size_t)N * sizeof(cplx<R>)));
+    constexpr int c = a < b ? a : b;
+    return c < 1 ? 1 : (c > plane_cg<R>() ? plane_cg<R>() : c);
+}
+
+// Blocks go to the XCDs in turn (block i on XCD i mod 8); the CG / C blocks of one
+// column group get indices that share i mod 8 and follow each other, so they run
+// together on one XCD and read (or write) the group's 128-byte lines through its L2.
+struct WColsBlock {
+    int g, sub, bb;
+    bool ok;
+};
+template <int NSUB> __device__ __forceinline__ WColsBlock wcols_block(int n_bb, int G) {
+    const int xcd = blockIdx.x & 7, jb = blockIdx.x >> 3;
+    const int gi = (jb / NSUB) * 8 + xcd;
+    return WColsBlock{gi % G, jb % NSUB, gi / G, gi < n_bb * G};
+}
+
+template <typename R, int LOG2N, int C>
+__global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wgrid_cols_kernel(XformArgs a) {
+    using K = WCols<R, LOG2N, C>;
+    using LD = Lds<R, LOG2N>;
+    using P = FftPlan<LOG2N>;
+    constexpr int N = K::N, NT = K::NT, S = P::NSTAGE, M = N / 8, R0 = K::R0, IT = K::ITER;
+    constexpr int CG = plane_cg<R>(), ld = LD::ld;
+    static_assert(S >= 2 && P::radix(S - 1) == 8, "columns of at least 16 points");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, NT>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny, hx = nx / 2;
+    const int G = (ny + CG - 1) / CG;
+    const WColsBlock wb = wcols_block<CG / C>(a.n_bb, G);
+    if (!wb.ok) return;
+    const int b = a.band0 + wb.bb;
+    const BandDev bd = a.bands[b];
+    const int nw = a.g.flat ? 1 : bd.nw;
+    const int col0 = wb.g * CG + wb.sub * C;
+    const int shg = a.log2_lmax - (LOG2N + 1), shn = a.log2_lmax - LOG2N;
+    const int lgT = __builtin_ctz(a.g.T);
+    // first stage: thread (c, jr) owns the butterfly of rows u' = jr + t M (t < 8)
+    const int c = threadIdx.x % C, jr = threadIdx.x / C;
+    const bool own = jr < M && col0 + c < ny;
+    // innermost stage: item (it, t) is position gq R0 + t of column cc, natural index i;
+    // its n - 1 - sc and accumulator sit in LDS slot (it R0 + t) NT + thread
+    cplx<R> ev[IT][R0];
+    R *const svl = reinterpret_cast<R *>(buf + C * ld);
+    R *const accl = svl + 8 * NT;
+    const R sc = (R)bd.sc;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int id = threadIdx.x + it * NT;
+        const int cc = id / (N / R0), gq = id - cc * (N / R0);
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int i = dit_inv<LOG2N>(gq * R0 + t);
+            const int sl = (it * R0 + t) * NT + threadIdx.x;
+            accl[sl] = R(0);
+            svl[sl] = (!a.g.flat && id < C * (N / R0) && i < nx && col0 + cc < ny) ? pixel_sm1<R>(i, col0 + cc, a.g) - sc
+                                                                                    : R(0);
+        }
+    }
+    for (int j = 0; j < nw; ++j) {
+        const uint8_t *orow = a.occ_row + ((size_t)b * a.g.nwmax + j) * a.g.ntx;
+        int any = 0;
+        for (int k = threadIdx.x; k < a.g.ntx; k += NT) any |= orow[k];
+        if (!__syncthreads_or(any)) continue;   // (also orders the twiddle table and the last plane's LDS reads)
+        const cplx<R> *T = reinterpret_cast<const cplx<R> *>(a.t1) +
+                           (((size_t)wb.bb * a.g.nwmax + j) * G + wb.g) * (size_t)gx * CG + wb.sub * C;
+        const R wj = (R)(bd.w0 + j * bd.dw);
+#pragma unroll 1
+        for (int p = 0; p < 2; ++p) {
+            // inverse N-point DFT of the even (p = 0) or odd (p = 1) rows by decimation in
+            // frequency: the first stage straight from HBM, output i ends at the DIT position of i
+            if (own) {
+                cplx<R> v[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int u = 2 * (jr + t * M) + p;
+                    v[t] = orow[u >> lgT] ? T[(size_t)u * CG + c] * twiddle<R, false>(tt, ((u * hx) & (gx - 1)) << shg)
+                                          : cplx<R>{R(0), R(0)};
+                }
+                dft_small<R, true, 8>(v);
+                stage_twiddles<R, true, 8>(v, tt, jr << shn);
+                cplx<R> *vb = buf + c * ld + LD::pad(jr);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) vb[LD::pad(t * M)] = v[t];
+            } else if (jr < M) {
+                cplx<R> *vb = buf + c * ld + LD::pad(jr);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) vb[LD::pad(t * M)] = cplx<R>{R(0), R(0)};
+            }
+            __syncthreads();
+            {
+                int m = M;
+#pragma unroll
+                for (int st = S - 2; st >= 1; --st) {   // middle stages, radix 8
+                    m /= 8;
+                    dif_stage<R, true, 8, LOG2N, NT>(buf, C, ld, m, tt, shn);
+                    __syncthreads();
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int id = threadIdx.x + it * NT;
+                if (id >= C * (N / R0)) continue;
+                const int cc = id / (N / R0), gq = id - cc * (N / R0);
+                const cplx<R> *vb = buf + cc * ld + LD::pad(gq * R0);
+                cplx<R> v[R0];
+#pragma unroll
+                for (int t = 0; t < R0; ++t) v[t] = vb[LD::pad(t)];
+                dft_small<R, true, R0>(v);
+#pragma unroll
+                for (int t = 0; t < R0; ++t) {
+                    if (p == 0) {
+                        ev[it][t] = v[t];
+                    } else {
+                        const int i = dit_inv<LOG2N>(gq * R0 + t);
+                        const int sl = (it * R0 + t) * NT + threadIdx.x;
+                        const cplx<R> y = ev[it][t] + v[t] * twiddle<R, true>(tt, i << shg);
+                        if (a.g.flat) {
+                            accl[sl] += y.re;
+                        } else {
+                            const cplx<R> ph = cis_cycles<R>(wj * svl[sl]);
+                            accl[sl] += y.re * ph.re - y.im * ph.im;
+                        }
+                    }
+                }
+            }
+            if (p == 0) __syncthreads();   // the odd half overwrites the buffer
+        }
+    }
+    R *img = reinterpret_cast<R *>(a.image_out) + (size_t)b * nx * ny;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int id = threadIdx.x + it * NT;
+        const int cc = id / (N / R0), gq = id - cc * (N / R0);
+        const int col = col0 + cc;
+        if (id >= C * (N / R0) || col >= ny) continue;
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int i = dit_inv<LOG2N>(gq * R0 + t);
+            if (i >= nx) continue;
+            const size_t pix = (size_t)i * ny + col;
+            const R cr = a.corr2d ? reinterpret_cast<const R *>(a.corr2d)[(size_t)b * nx * ny + pix]
+                                  : reinterpret_cast<const R *>(a.corr_x)[i] * reinterpret_cast<const R *>(a.corr_y)[col];
+            R v = accl[(it * R0 + t) * NT + threadIdx.x] * cr;
+            if (a.zero_edge && (i == 0 || col == 0)) v = R(0);
+            img[pix] = v;
+        }
+    }
+}
+
+template <typename R, int LOG2N, int C>
+__global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wdegrid_cols_kernel(XformArgs a) {
+    using K = WCols<R, LOG2N, C>;
+    using LD = Lds<R, LOG2N>;
+    using P = FftPlan<LOG2N>;
+    constexpr int N = K::N, NT = K::NT, S = P::NSTAGE, M = N / 8, R0 = K::R0, IT = K::ITER;
+    constexpr int CG = plane_cg<R>(), ld = LD::ld;
+    static_assert(S >= 2 && P::radix(S - 1) == 8, "columns of at least 16 points");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf = twl + kTwEntries;
+    const TwTab<R> tt = tw_fill<R, NT>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny, hx = nx / 2;
+    const int G = (ny + CG - 1) / CG;
+    const WColsBlock wb = wcols_block<CG / C>(a.n_bb, G);
+    if (!wb.ok) return;
+    const int b = a.band0 + wb.bb;
+    const BandDev bd = a.bands[b];
+    const int nw = a.g.flat ? 1 : bd.nw;
+    const int col0 = wb.g * CG + wb.sub * C;
+    const int shg = a.log2_lmax - (LOG2N + 1), shn = a.log2_lmax - LOG2N;
+    const int lgT = __builtin_ctz(a.g.T);
+    // first stage: thread (c, jr) owns image rows i = jr + t M (t < 8) of column col
+    const int c = threadIdx.x % C, jr = threadIdx.x / C;
+    const int col = col0 + c;
+    const bool own = jr < M;
+    // the corrected image value and n - 1 - sc of row t of the thread: LDS slot t NT + thread
+    R *const xrl = reinterpret_cast<R *>(buf + C * ld);
+    R *const svl = xrl + 8 * NT;
+    const R sc = (R)bd.sc;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int i = jr + t * M;
+        R xv = R(0), s = R(0);
+        if (own && i < nx && col < ny) {
+            const size_t pix = (size_t)i * ny + col;
+            const R x = reinterpret_cast<const R *>(a.image_in)[(size_t)b * nx * ny + pix];
+            const R cr = a.corr2d ? reinterpret_cast<const R *>(a.corr2d)[(size_t)b * nx * ny + pix]
+                                  : reinterpret_cast<const R *>(a.corr_x)[i] * reinterpret_cast<const R *>(a.corr_y)[col];
+            xv = x * cr;
+            if (!a.g.flat) s = pixel_sm1<R>(i, col, a.g) - sc;
+        }
+        xrl[t * NT + threadIdx.x] = xv;
+        svl[t * NT + threadIdx.x] = s;
+    }
+    for (int j = 0; j < nw; ++j) {
+        const uint8_t *nrow = a.need_row + ((size_t)b * a.g.nwmax + j) * a.g.ntx;
+        int any = 0;
+        for (int k = threadIdx.x; k < a.g.ntx; k += NT) any |= nrow[k];
+        if (!__syncthreads_or(any)) continue;   // (also orders the twiddle table and the last plane's LDS reads)
+        cplx<R> *T = reinterpret_cast<cplx<R> *>(a.t1) +
+                     (((size_t)wb.bb * a.g.nwmax + j) * G + wb.g) * (size_t)gx * CG + wb.sub * C;
+        const R wj = (R)(bd.w0 + j * bd.dw);
+        cplx<R> pv[8];   // x e^(-2 pi i w_j (n - 1 - sc))
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const R xv = xrl[t * NT + threadIdx.x];
+            pv[t] = a.g.flat ? cplx<R>{xv, R(0)} : conj(cis_cycles<R>(wj * svl[t * NT + threadIdx.x])) * xv;
+        }
+#pragma unroll 1
+        for (int p = 0; p < 2; ++p) {
+            // forward N-point DFT of x w^(p i) by decimation in frequency: the first stage
+            // from registers, X[k'] ends at the DIT position of k'
+            if (own) {
+                cplx<R> v[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) v[t] = p == 0 ? pv[t] : pv[t] * twiddle<R, false>(tt, (jr + t * M) << shg);
+                dft_small<R, false, 8>(v);
+                stage_twiddles<R, false, 8>(v, tt, jr << shn);
+                cplx<R> *vb = buf + c * ld + LD::pad(jr);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) vb[LD::pad(t * M)] = v[t];
+            }
+            __syncthreads();
+            {
+                int m = M;
+#pragma unroll
+                for (int st = S - 2; st >= 1; --st) {   // middle stages, radix 8
+                    m /= 8;
+                    dif_stage<R, false, 8, LOG2N, NT>(buf, C, ld, m, tt, shn);
+                    __syncthreads();
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int id = threadIdx.x + it * NT;
+                if (id >= C * (N / R0)) continue;
+                const int cc = id / (N / R0), gq = id - cc * (N / R0);
+                if (col0 + cc >= ny) continue;
+                const cplx<R> *vb = buf + cc * ld + LD::pad(gq * R0);
+                cplx<R> v[R0];
+#pragma unroll
+                for (int t = 0; t < R0; ++t) v[t] = vb[LD::pad(t)];
+                dft_small<R, false, R0>(v);
+#pragma unroll
+                for (int t = 0; t < R0; ++t) {
+                    const int u = 2 * dit_inv<LOG2N>(gq * R0 + t) + p;
+                    if (nrow[u >> lgT]) T[(size_t)u * CG + cc] = v[t] * twiddle<R, true>(tt, ((u * hx) & (gx - 1)) << shg);
+                }
+            }
+            if (p == 0) __syncthreads();   // the odd half overwrites the buffer
+        }
+    }
+}
+
+template <typename R, bool GRID>
+static hipError_t wcols_launch(const XformArgs &a, hipStream_t s) {
+    return dispatch_int<4, 13>(__builtin_ctz(a.g.gx) - 1, [&](auto Lc) -> hipError_t {
+        constexpr int LG = decltype(Lc)::value;
+        if constexpr (sizeof(R) == 8 && LG > 12) {
+            return hipErrorInvalidValue;   // FP64 plane rows stop at 8192 points
+        } else {
+            constexpr int C = wcols_c<R, LG>();
+            constexpr int CG = plane_cg<R>();
+            using K = WCols<R, LG, C>;
+            const int G = (a.g.ny + CG - 1) / CG;
+            const int nb = ((a.n_bb * G + 7) / 8) * 8 * (CG / C);
+            if (GRID) PFB_LAUNCH_NT((wgrid_cols_kernel<R, LG, C>), nb, K::NT, K::lds, s, a);
+            else PFB_LAUNCH_NT((wdegrid_cols_kernel<R, LG, C>), nb, K::NT, K::lds, s, a);
+            return hipSuccess;
+        }
+    });
 }
 
 template <typename R>
@@ -1985,67 +2097,20 @@ static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
         return hipSuccess;
     });
     if (e != hipSuccess) return e;
-    constexpr int C = col_group<R>();
-    const int ncg = (a.g.ny + C - 1) / C;
-    if (a.cs.n2 > 1) {
-        e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
-            constexpr int LG = decltype(Lc)::value;
-            const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-            const int nb = a.n_bb * a.g.nwmax * a.cs.n2 * ncg;
-            PFB_LAUNCH((colA_kernel<R, LG, true, 0>), nb, lds, s, a);
-            return hipSuccess;
-        });
-        if (e != hipSuccess) return e;
-    }
-    const int lg3 = a.cs.n2 > 1 ? a.cs.log2n2 : a.cs.log2n1;
-    XformArgs b = a;
-    if (a.cs.n2 == 1) {  // single pass: G3 takes the whole column (n1 -> 1, n2 -> L)
-        b.cs.n1 = 1;
-        b.cs.n2 = a.cs.n1;
-        b.cs.log2n1 = 0;
-        b.cs.log2n2 = a.cs.log2n1;
-    }
-    return dispatch_int<3, 9>(lg3, [&](auto Lc) -> hipError_t {
-        constexpr int LG = decltype(Lc)::value;
-        constexpr int N2 = 1 << LG;
-        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>) + 2 * (size_t)C * (N2 + 1) * sizeof(R);
-        const int nb = b.n_bb * b.cs.n1 * ncg;
-        PFB_LAUNCH((g3_kernel<R, LG>), nb, lds, s, b);
-        return hipSuccess;
-    });
+    return wcols_launch<R, true>(a, s);
 }
 
 template <typename R>
 static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
-    constexpr int C = col_group<R>();
-    const int ncg = (a.g.ny + C - 1) / C;
-    hipError_t e = dispatch_int<3, 9>(a.cs.log2n1, [&](auto Lc) -> hipError_t {
-        constexpr int LG = decltype(Lc)::value;
-        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-        const int nb = a.n_bb * a.g.nwmax * a.cs.n2 * ncg;
-        PFB_LAUNCH((colA_kernel<R, LG, false, 1>), nb, lds, s, a);
-        return hipSuccess;
-    });
+    hipError_t e = wcols_launch<R, false>(a, s);
     if (e != hipSuccess) return e;
-    const void *rows_src = a.t1;
-    if (a.cs.n2 > 1) {
-        e = dispatch_int<3, 9>(a.cs.log2n2, [&](auto Lc) -> hipError_t {
-            constexpr int LG = decltype(Lc)::value;
-            const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-            const int nb = a.n_bb * a.g.nwmax * a.cs.n1 * ncg;
-            PFB_LAUNCH((d2_kernel<R, LG>), nb, lds, s, a);
-            return hipSuccess;
-        });
-        if (e != hipSuccess) return e;
-        rows_src = a.t2;
-    }
     const int lgy = __builtin_ctz(a.g.gy);
     return dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C2 = std::min(rows_per_block<R, LG>(), a.g.gx);
         const size_t lds = (size_t)C2 * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
         const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C2);
-        PFB_LAUNCH_NT((d3_rows_kernel<R, LG>), nb, row_threads<LG>(), lds, s, a, C2, rows_src);
+        PFB_LAUNCH_NT((d3_rows_kernel<R, LG>), nb, row_threads<LG>(), lds, s, a, C2);
         return hipSuccess;
     });
 }

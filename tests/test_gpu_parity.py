@@ -337,13 +337,14 @@ def test_error_paths():
 
 
 # --------------------------------------------------------------------------
-# four-step column transforms (grid side > 512) and four-step PSF convolution
+# rectangular image with long columns (operator grid 1024 x 512)
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("prec", PRECISIONS)
-def test_four_step_sizes_sampled(prec):
-    """512 x 256 image: operator grid 1024 x 512 and PSF-convolution columns of
-    1024 use the two-pass column transforms; outputs checked on samples."""
+def test_long_columns_sampled(prec):
+    """512 x 256 image: operator grid 1024 x 512 (1024-point columns as two
+    512-point halves, more rows than columns) and PSF-convolution columns of
+    1024; outputs checked on samples."""
     R, C = _dtypes(prec)
     prob = synth.tiny_problem(seed=95, nx=512, ny=256, n_row=1500, freqs=(1.0e9, 1.2e9),
                               cell_arcsec=8.0, w_frac=0.3, flag_frac=0.05)
@@ -353,7 +354,7 @@ def test_four_step_sizes_sampled(prec):
     x[0, rng.integers(0, 512, 30), rng.integers(0, 256, 30)] = rng.uniform(0.1, 1, 30)
     x[0, 200:260, 100:150] += rng.normal(size=(60, 50))
     plan = make_plan(prob, prec)
-    say(f"four-step {prec}: info {plan.info()}")
+    say(f"long columns {prec}: info {plan.info()}")
     pix = rng.integers(0, 512 * 256, 300)
     d = host(plan.grid(to_dev(vis, C))).ravel()[pix]
     assert rel(d, oracle.grid(prob, vis, pix=pix)) < TOL[prec]
