@@ -163,6 +163,10 @@ struct GridderHost {
     // interpolation may read it (occ dilated by one tile, the halo reach)
     std::vector<uint8_t> occ, need;
     std::vector<uint8_t> occ_row, need_row;   // per (band, plane, tile row): any such tile
+    // the (band nwmax + plane) ntx + tile row of every set occ_row / need_row flag,
+    // band-major, with per-band starts (n_band + 1)
+    std::vector<int32_t> occ_list, need_list;
+    std::vector<int> occ_list_start, need_list_start;
     bool mfma = false;                   // FP32 w-stacked: matrix-core spread (window sort, phase table)
     int sort_rb = 1, sort_cb = 1;        // sort blocks of base rows x columns
     int64_t n_entries = 0;
@@ -170,6 +174,7 @@ struct GridderHost {
     // workspace offsets
     size_t o_bands = 0, o_offsets = 0, o_cursor = 0, o_gwork = 0, o_iwork = 0, o_recs = 0, o_omega = 0;
     size_t o_corr2d = 0, o_corrx = 0, o_corry = 0, o_occ = 0, o_need = 0, o_occ_row = 0, o_need_row = 0;
+    size_t o_occ_list = 0, o_need_list = 0;
     bool corr2d = true;
     // device pointers (valid after set_workspace)
     BandDev *d_bands = nullptr;
@@ -186,6 +191,7 @@ struct GridderHost {
     size_t o_home_pos = 0;           // main gridder: per entry, home-list position of its visibility
     uint32_t *d_home_pos = nullptr;
     const uint8_t *d_occ = nullptr, *d_need = nullptr, *d_occ_row = nullptr, *d_need_row = nullptr;
+    const int32_t *d_occ_list = nullptr, *d_need_list = nullptr;
     int64_t keys() const { return (int64_t)g.n_band * g.ntx * g.nty * g.nj0max; }
 };
 
@@ -336,6 +342,20 @@ void build_work(GridderHost &G, const std::vector<unsigned> &counts, const std::
         G.gband_start[b + 1] = (int)G.gwork.size();
         G.iband_start[b + 1] = (int)G.iwork.size();
     }
+    G.occ_list.clear();
+    G.need_list.clear();
+    G.occ_list_start.assign(g.n_band + 1, 0);
+    G.need_list_start.assign(g.n_band + 1, 0);
+    for (int b = 0; b < g.n_band; ++b) {
+        for (int p = 0; p < g.nwmax; ++p)
+            for (int tu = 0; tu < g.ntx; ++tu) {
+                const size_t k = ((size_t)b * g.nwmax + p) * g.ntx + tu;
+                if (G.occ_row[k]) G.occ_list.push_back((int32_t)k);
+                if (G.need_row[k]) G.need_list.push_back((int32_t)k);
+            }
+        G.occ_list_start[b + 1] = (int)G.occ_list.size();
+        G.need_list_start[b + 1] = (int)G.need_list.size();
+    }
 }
 
 // Installs the plan's launch profiler for the duration of one operator call.
@@ -369,6 +389,10 @@ XformArgs xform_args(const pfb_plan *P, const GridderHost &G, int b0, int nbb) {
     a.need = G.d_need;
     a.occ_row = G.d_occ_row;
     a.need_row = G.d_need_row;
+    a.occ_list = G.d_occ_list + G.occ_list_start[b0];
+    a.n_occ_list = G.occ_list_start[b0 + nbb] - G.occ_list_start[b0];
+    a.need_list = G.d_need_list + G.need_list_start[b0];
+    a.n_need_list = G.need_list_start[b0 + nbb] - G.need_list_start[b0];
     return a;
 }
 
@@ -720,6 +744,8 @@ pfb_status count_and_layout(pfb_plan *P, char *tmp, hipStream_t stream) {
         G->o_need = L.take(std::max<size_t>(G->need.size(), 1));
         G->o_occ_row = L.take(std::max<size_t>(G->occ_row.size(), 1));
         G->o_need_row = L.take(std::max<size_t>(G->need_row.size(), 1));
+        G->o_occ_list = L.take(std::max<size_t>(G->occ_list.size(), 1) * sizeof(int32_t));
+        G->o_need_list = L.take(std::max<size_t>(G->need_list.size(), 1) * sizeof(int32_t));
         if (G->corr2d) {
             G->o_corr2d = L.take((size_t)nb * G->g.nx * G->g.ny * P->rsz);
         } else {
@@ -1068,6 +1094,14 @@ pfb_status pfb_plan_set_workspace(pfb_plan *P, void *dev, size_t bytes, hipStrea
         HIP_OK(hipMemcpyAsync(P->p(G->o_occ_row), G->occ_row.data(), G->occ_row.size(), hipMemcpyHostToDevice, s));
         HIP_OK(hipMemcpyAsync(P->p(G->o_need_row), G->need_row.data(), G->need_row.size(), hipMemcpyHostToDevice,
                               s));
+        G->d_occ_list = reinterpret_cast<const int32_t *>(P->p(G->o_occ_list));
+        G->d_need_list = reinterpret_cast<const int32_t *>(P->p(G->o_need_list));
+        if (!G->occ_list.empty())
+            HIP_OK(hipMemcpyAsync(P->p(G->o_occ_list), G->occ_list.data(), G->occ_list.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s));
+        if (!G->need_list.empty())
+            HIP_OK(hipMemcpyAsync(P->p(G->o_need_list), G->need_list.data(), G->need_list.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s));
         if (G->corr2d) {
             G->d_corr2d = P->p(G->o_corr2d);
         } else {

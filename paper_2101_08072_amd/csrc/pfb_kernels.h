@@ -129,6 +129,11 @@ struct XformArgs {
     // without needed tiles are neither written by the degrid's column pass nor
     // read by its row pass
     const uint8_t *occ_row, *need_row;
+    // tile rows of bands [band0, band0 + n_bb) with occupied (needed) tiles, each
+    // (band nwmax + plane) ntx + tile row: the inverse (forward) row pass runs on
+    // their rows only
+    const int32_t *occ_list, *need_list;
+    int n_occ_list, n_need_list;
 };
 // complex values per group of the plane intermediate t1 (one 128-byte line)
 int plane_group_cols(bool dbl);

@@ -1696,31 +1696,21 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformA
     cplx<R> *buf = twl + kTwEntries;
     const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
-    const int gx = a.g.gx, ny = a.g.ny;
-    const int ngrp = gx / C;
-    int blk = blockIdx.x;
-    const int ug = blk % ngrp;
-    blk /= ngrp;
-    const int j = blk % a.g.nwmax;
-    const int bb = blk / a.g.nwmax;
-    const int nw = a.g.flat ? 1 : a.bands[a.band0 + bb].nw;
-    if (j >= nw) return;
+    const int gx = a.g.gx;
+    // block: C consecutive rows of a listed tile row (one that holds occupied tiles)
+    const int per = a.g.T / C;
+    const int e = a.occ_list[blockIdx.x / per];   // (band nwmax + plane) ntx + tile row
+    const int pj = e / a.g.ntx;
+    const int j = pj % a.g.nwmax, bb = pj / a.g.nwmax - a.band0;
+    const int row0 = (e - pj * a.g.ntx) * a.g.T + (blockIdx.x % per) * C;
     const size_t plane = (size_t)bb * a.g.nwmax + j;
-    const cplx<R> *src = reinterpret_cast<const cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
+    const cplx<R> *src = reinterpret_cast<const cplx<R> *>(a.planes) + (plane * gx + (size_t)row0) * L;
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.t1);
     // tiles of these rows that hold spread values (the rest of the plane is zero
-    // and is not read); rows whose tiles are all empty transform to zero
+    // and is not read)
     const int lgT = __builtin_ctz(a.g.T), nty = a.g.nty;   // tiles are powers of two
-    const uint8_t *occ = a.occ + ((size_t)(a.band0 + bb) * a.g.nwmax + j) * a.g.ntx * nty;
-    const int row0 = ug * C;
-    bool any = false;
-    for (int k = threadIdx.x; k < C * nty; k += row_threads<LOG2L>()) {
-        const int c = k / nty, tv = k - c * nty;
-        any |= occ[((row0 + c) >> lgT) * nty + tv] != 0;
-    }
-    // rows without occupied tiles transform to zero: not written, the column pass
-    // reads them as zero
-    if (!__syncthreads_or(any)) return;
+    const uint8_t *occ = a.occ + (size_t)pj * a.g.ntx * nty;
+    const int ny = a.g.ny;
     // output k of the row DFT is cropped column iy = k + ny / 2 (mod L), kept if iy < ny
     row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>()>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
@@ -1744,27 +1734,18 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformA
     const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int gx = a.g.gx, ny = a.g.ny;
-    const int ngrp = gx / C;
-    int blk = blockIdx.x;
-    const int ug = blk % ngrp;
-    blk /= ngrp;
-    const int j = blk % a.g.nwmax;
-    const int bb = blk / a.g.nwmax;
-    const int nw = a.g.flat ? 1 : a.bands[a.band0 + bb].nw;
-    if (j >= nw) return;
+    // block: C consecutive rows of a listed tile row (one with tiles the interpolation reads)
+    const int per = a.g.T / C;
+    const int e = a.need_list[blockIdx.x / per];   // (band nwmax + plane) ntx + tile row
+    const int pj = e / a.g.ntx;
+    const int j = pj % a.g.nwmax, bb = pj / a.g.nwmax - a.band0;
+    const int row0 = (e - pj * a.g.ntx) * a.g.T + (blockIdx.x % per) * C;
     const size_t plane = (size_t)bb * a.g.nwmax + j;
     const cplx<R> *src = reinterpret_cast<const cplx<R> *>(a.t1);
-    cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.planes) + (plane * gx + (size_t)ug * C) * L;
-    // only tiles the interpolation may read are written; rows with none are skipped
+    cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.planes) + (plane * gx + (size_t)row0) * L;
+    // only tiles the interpolation may read are written
     const int lgT = __builtin_ctz(a.g.T), nty = a.g.nty;   // tiles are powers of two
-    const uint8_t *need = a.need + ((size_t)(a.band0 + bb) * a.g.nwmax + j) * a.g.ntx * nty;
-    const int row0 = ug * C;
-    bool any = false;
-    for (int k = threadIdx.x; k < C * nty; k += row_threads<LOG2L>()) {
-        const int c = k / nty, tv = k - c * nty;
-        any |= need[((row0 + c) >> lgT) * nty + tv] != 0;
-    }
-    if (!__syncthreads_or(any)) return;
+    const uint8_t *need = a.need + (size_t)pj * a.g.ntx * nty;
     // input r of the row DFT is cropped column iy = r + ny / 2 (mod L), zero if iy >= ny
     row_fft<R, false, LOG2L, row_threads<LOG2L>(), true, true>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
@@ -2090,10 +2071,10 @@ static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
     const int lgy = __builtin_ctz(a.g.gy);
     hipError_t e = dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const int C = std::min(rows_per_block<R, LG>(), a.g.gx);
+        const int C = std::min(rows_per_block<R, LG>(), a.g.T);
         const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-        const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C);
-        PFB_LAUNCH_NT((g1_rows_kernel<R, LG>), nb, row_threads<LG>(), lds, s, a, C);
+        const int64_t nb = (int64_t)a.n_occ_list * (a.g.T / C);
+        if (nb > 0) PFB_LAUNCH_NT((g1_rows_kernel<R, LG>), nb, row_threads<LG>(), lds, s, a, C);
         return hipSuccess;
     });
     if (e != hipSuccess) return e;
@@ -2107,10 +2088,10 @@ static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
     const int lgy = __builtin_ctz(a.g.gy);
     return dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
-        const int C2 = std::min(rows_per_block<R, LG>(), a.g.gx);
+        const int C2 = std::min(rows_per_block<R, LG>(), a.g.T);
         const size_t lds = (size_t)C2 * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
-        const int nb = a.n_bb * a.g.nwmax * (a.g.gx / C2);
-        PFB_LAUNCH_NT((d3_rows_kernel<R, LG>), nb, row_threads<LG>(), lds, s, a, C2);
+        const int64_t nb = (int64_t)a.n_need_list * (a.g.T / C2);
+        if (nb > 0) PFB_LAUNCH_NT((d3_rows_kernel<R, LG>), nb, row_threads<LG>(), lds, s, a, C2);
         return hipSuccess;
     });
 }
