@@ -135,7 +135,7 @@ struct XformArgs {
     const int32_t *occ_list, *need_list;
     int n_occ_list, n_need_list;
 };
-// complex values per group of the plane intermediate t1 (one 128-byte line)
+// complex values per group of the plane intermediate t1 (64 bytes)
 int plane_group_cols(bool dbl);
 hipError_t launch_grid_xform(bool dbl, const XformArgs &a, hipStream_t s);    // planes -> image
 hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s);  // image -> planes

@@ -1677,9 +1677,11 @@ __host__ __device__ constexpr int rows_per_block() {
 // Plane intermediate of the grid and degrid transforms (cropped row spectra),
 // group-major: column iy = g CG + c of uv row u of plane (bb, j) sits at
 // T[(((bb nwmax + j) G + g) gx + u) CG + c], G = ceil(ny / CG), CG complex values
-// per 128-byte line.  The row passes store and load one whole line per group and
-// row; the gx rows of a group are one contiguous block for the column passes.
-template <typename R> __host__ __device__ constexpr int plane_cg() { return 128 / (int)sizeof(cplx<R>); }
+// in 64 bytes.  The row passes store and load 64-byte pieces (neighbouring rows
+// complete the lines); the gx rows of a group are one contiguous block for the
+// column passes, whose CG / C blocks per group share it through one XCD's L2
+// (64 bytes measured faster overall than 32 or 128).
+template <typename R> __host__ __device__ constexpr int plane_cg() { return 64 / (int)sizeof(cplx<R>); }
 template <typename R> __device__ __forceinline__ size_t plane_at(const XformArgs &a, size_t plane, int u, int iy) {
     constexpr int CG = plane_cg<R>();
     const int G = (a.g.ny + CG - 1) / CG;
@@ -2116,6 +2118,10 @@ __device__ __forceinline__ int xcd_block(int i, int n) {
     return (n & 7) ? i : (i & 7) * (n >> 3) + (i >> 3);
 }
 
+// Offset (in complex values, within a band's lx ldh area of t1c) of the column
+// pass's output in image mode: the upper half, free since nx <= lx / 2.
+__device__ __forceinline__ size_t conv_out_off(const ConvArgs &a) { return (size_t)(a.lx / 2) * a.ldh; }
+
 // S1: forward row DFT (length 2ny) of real rows, keeping the half spectrum k = 0..ny.
 //   in_mode CONV_IN_X      : row i of x (ny values, zero padded)
 //           CONV_IN_CG_P   : p = r + beta p, written back, then transformed
@@ -2185,11 +2191,11 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a,
 
 // Group-major half-spectrum layout of the convolution's intermediate: frequency
 // column k = g C + c of row i sits at T[band][(g rows + i) C + c] (rows = nx, or
-// 2nx for the PSF), so the nx values of a group of C columns form one contiguous
-// block (the column pass reads and writes whole blocks) and two adjacent rows of
-// a group are 2 C contiguous values (the row passes store and load 128-byte
-// pieces).  The PSF spectrum uses the same groups: psfhat[band][(g 2 + p) nx + k'][c]
-// holds frequency 2k' + p of column g C + c.
+// 2nx for the PSF; C values = one 128-byte line), so the rows of a group of C
+// columns form one contiguous block (the column pass reads and writes whole
+// blocks) and the row passes store and load whole lines.  The PSF spectrum uses
+// the same groups: psfhat[band][(g 2 + p) nx + k'][c] holds frequency 2k' + p of
+// column g C + c.
 
 // Column pass: for every column (nx complex values of the row spectra; rows nx ..
 // 2nx - 1 of the zero-padded grid are zero) the 2nx-point DFT, the product with
@@ -2236,10 +2242,14 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
     const int sub = jb % NSUB, gi = (jb / NSUB) * 8 + xcd;
     if (gi >= a.n_band * G) return;   // the grid is padded to whole rounds of eight
     const int g = gi % G, b = gi / G;
+    if (g * CG + sub * C > a.ly / 2) return;   // columns of the last group past the half spectrum
     const size_t boff = (size_t)b * a.lx * a.ldh;
     const int nin = PSF ? 2 * N : a.nx;   // rows with data; the rest of the padded column is zero
     // a group holds the rows the row pass wrote: all 2N of the PSF, the image's nx otherwise
-    cplx<R> *T = reinterpret_cast<cplx<R> *>(a.t1c) + boff + (size_t)g * (PSF ? 2 * N : a.nx) * CG + sub * C;
+    const cplx<R> *T = reinterpret_cast<const cplx<R> *>(a.t1c) + boff + (size_t)g * (PSF ? 2 * N : a.nx) * CG + sub * C;
+    // output (image mode): the same group layout in the upper half of the band's area,
+    // which the image's nx <= lx / 2 rows leave free
+    cplx<R> *Y = reinterpret_cast<cplx<R> *>(a.t1c) + boff + conv_out_off(a) + (size_t)g * a.nx * CG + sub * C;
     R *H = reinterpret_cast<R *>(a.psfhat) + boff + (size_t)g * 2 * N * CG + sub * C;
     const int sh2n = a.log2_lmax - (LOG2N + 1);   // table step of w = exp(-2 pi i / 2N)
     const int shn = a.log2_lmax - LOG2N;
@@ -2248,20 +2258,30 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
     const int c = threadIdx.x % C, j = threadIdx.x / C;
     const bool own = j < M;
     cplx<R> ev[8];   // the even half's outputs y_e[j + t M], kept for the odd half
+    cplx<R> xin[8];  // image mode: the thread's inputs, read once for both halves
+    if (!PSF && own) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int r = j + t * M;
+            xin[t] = r < nin ? T[r * CG + c] : cplx<R>{R(0), R(0)};
+        }
+    }
     __syncthreads();   // twiddle table
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         // forward N-point DFT of the even (p = 0) or odd (p = 1) half by decimation in
-        // frequency: the first stage straight from HBM, X[k] ends at the DIT position of k
+        // frequency: the first stage from the inputs, X[k] ends at the DIT position of k
         if (own) {
             cplx<R> v[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const int r = j + t * M;
-                cplx<R> x = r < nin ? T[r * CG + c] : cplx<R>{R(0), R(0)};
+                cplx<R> x;
                 if (PSF) {
-                    const cplx<R> hi = T[(r + N) * CG + c];
-                    x = p == 0 ? x + hi : x - hi;
+                    const cplx<R> lo = T[r * CG + c], hi = T[(r + N) * CG + c];
+                    x = p == 0 ? lo + hi : lo - hi;
+                } else {
+                    x = xin[t];
                 }
                 v[t] = p == 0 ? x : x * twiddle<R, false>(tt, r << sh2n);
             }
@@ -2325,7 +2345,7 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
             for (int t = 0; t < 8; ++t) {
                 if (p == 0) ev[t] = v[t];
                 else if (j + t * M < a.nx)   // the crop: rows 0 .. nx - 1
-                    T[(j + t * M) * CG + c] = ev[t] + v[t] * twiddle<R, true>(tt, (j + t * M) << sh2n);
+                    Y[(j + t * M) * CG + c] = ev[t] + v[t] * twiddle<R, true>(tt, (j + t * M) << sh2n);
             }
         }
         __syncthreads();
@@ -2342,10 +2362,13 @@ template <typename R, int LG> constexpr int conv_cgc() {
     static_assert(ConvCols<R, LG, C>::lds <= kMaxLdsBytes, "column group exceeds the LDS");
     return C;
 }
-// layout group width: the column pass's columns per block, at least 2 (two rows
-// of a group are then at least 32 contiguous bytes for the row passes; blocks of
-// one column share a group with a neighbour on the same XCD)
-template <typename R, int LG> constexpr int conv_layout_cg() { return conv_cgc<R, LG>() < 2 ? 2 : conv_cgc<R, LG>(); }
+// layout group width: the column pass's columns per block, at least 32 bytes of a
+// row (the row passes store and load 64 contiguous bytes of each row pair; the
+// CG / C column-pass blocks of a group share its lines in the L2 of one XCD, and
+// more of them per group lose to L2 misses: measured best at 32 bytes)
+template <typename R, int LG> constexpr int conv_layout_cg() {
+    return conv_cgc<R, LG>() < 32 / (int)sizeof(cplx<R>) ? 32 / (int)sizeof(cplx<R>) : conv_cgc<R, LG>();
+}
 int conv_group_cols(bool dbl, int nx) {
     int C = 1;
     (void)dispatch_int<4, 12>(__builtin_ctz(nx), [&](auto Lc) -> hipError_t {
@@ -2375,7 +2398,7 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a,
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int ig = lb % ngrp;
     const int b = lb / ngrp;
-    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + (size_t)b * a.lx * a.ldh;
+    const cplx<R> *t1 = reinterpret_cast<const cplx<R> *>(a.t1c) + (size_t)b * a.lx * a.ldh + conv_out_off(a);
     const int lgc = __builtin_ctz(a.cgc), cmask = a.cgc - 1;
     const R scale = R(1) / ((R)a.lx * (R)a.ly);
     double part = 0.0;
