@@ -1831,6 +1831,12 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wgrid_cols_kernel(Xf
     const int col0 = wb.g * CG + wb.sub * C;
     const int shg = a.log2_lmax - (LOG2N + 1), shn = a.log2_lmax - LOG2N;
     const int lgT = __builtin_ctz(a.g.T);
+    // gx = 2 nx (power-of-two sides): G'[u] = G[u] (-i)^u, so the even half's
+    // transform is that of G[2u'] shifted by N / 2 and the odd half's also times -i:
+    // pixel i comes from natural index i ^ N / 2 and the odd half's factor is
+    // w^-(i - N / 2); no product on the loaded values
+    const bool qs = 4 * hx == gx;
+    const int hs = qs ? N / 2 : 0;
     // first stage: thread (c, jr) owns the butterfly of rows u' = jr + t M (t < 8)
     const int c = threadIdx.x % C, jr = threadIdx.x / C;
     const bool own = jr < M && col0 + c < ny;
@@ -1846,7 +1852,7 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wgrid_cols_kernel(Xf
         const int cc = id / (N / R0), gq = id - cc * (N / R0);
 #pragma unroll
         for (int t = 0; t < R0; ++t) {
-            const int i = dit_inv<LOG2N>(gq * R0 + t);
+            const int i = dit_inv<LOG2N>(gq * R0 + t) ^ hs;
             const int sl = (it * R0 + t) * NT + threadIdx.x;
             accl[sl] = R(0);
             svl[sl] = (!a.g.flat && id < C * (N / R0) && i < nx && col0 + cc < ny) ? pixel_sm1<R>(i, col0 + cc, a.g) - sc
@@ -1870,8 +1876,12 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wgrid_cols_kernel(Xf
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     const int u = 2 * (jr + t * M) + p;
-                    v[t] = orow[u >> lgT] ? T[(size_t)u * CG + c] * twiddle<R, false>(tt, ((u * hx) & (gx - 1)) << shg)
-                                          : cplx<R>{R(0), R(0)};
+                    cplx<R> x{R(0), R(0)};
+                    if (orow[u >> lgT]) {
+                        x = T[(size_t)u * CG + c];
+                        if (!qs) x = x * twiddle<R, false>(tt, ((u * hx) & (gx - 1)) << shg);
+                    }
+                    v[t] = x;
                 }
                 dft_small<R, true, 8>(v);
                 stage_twiddles<R, true, 8>(v, tt, jr << shn);
@@ -1908,9 +1918,10 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wgrid_cols_kernel(Xf
                     if (p == 0) {
                         ev[it][t] = v[t];
                     } else {
-                        const int i = dit_inv<LOG2N>(gq * R0 + t);
+                        const int i = dit_inv<LOG2N>(gq * R0 + t) ^ hs;
                         const int sl = (it * R0 + t) * NT + threadIdx.x;
-                        const cplx<R> y = ev[it][t] + v[t] * twiddle<R, true>(tt, i << shg);
+                        const int e = qs ? (i + gx - N / 2) & (gx - 1) : i;
+                        const cplx<R> y = ev[it][t] + v[t] * twiddle<R, true>(tt, e << shg);
                         if (a.g.flat) {
                             accl[sl] += y.re;
                         } else {
@@ -1932,7 +1943,7 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wgrid_cols_kernel(Xf
         if (id >= C * (N / R0) || col >= ny) continue;
 #pragma unroll
         for (int t = 0; t < R0; ++t) {
-            const int i = dit_inv<LOG2N>(gq * R0 + t);
+            const int i = dit_inv<LOG2N>(gq * R0 + t) ^ hs;
             if (i >= nx) continue;
             const size_t pix = (size_t)i * ny + col;
             const R cr = a.corr2d ? reinterpret_cast<const R *>(a.corr2d)[(size_t)b * nx * ny + pix]
@@ -1966,7 +1977,13 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wdegrid_cols_kernel(
     const int col0 = wb.g * CG + wb.sub * C;
     const int shg = a.log2_lmax - (LOG2N + 1), shn = a.log2_lmax - LOG2N;
     const int lgT = __builtin_ctz(a.g.T);
-    // first stage: thread (c, jr) owns image rows i = jr + t M (t < 8) of column col
+    // gx = 2 nx (power-of-two sides): w^(-u hx) = i^u = (-1)^k' i^p for u = 2k' + p,
+    // so position m of the transforms takes image row m ^ N / 2, the odd half's
+    // input factor becomes w^(i - N / 2), and the outputs need no product
+    const bool qs = 4 * hx == gx;
+    const int hs = qs ? N / 2 : 0;
+    // first stage: thread (c, jr) owns positions jr + t M (t < 8), image rows
+    // (jr + t M) ^ hs, of column col
     const int c = threadIdx.x % C, jr = threadIdx.x / C;
     const int col = col0 + c;
     const bool own = jr < M;
@@ -1976,7 +1993,7 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wdegrid_cols_kernel(
     const R sc = (R)bd.sc;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        const int i = jr + t * M;
+        const int i = (jr + t * M) ^ hs;
         R xv = R(0), s = R(0);
         if (own && i < nx && col < ny) {
             const size_t pix = (size_t)i * ny + col;
@@ -2010,7 +2027,11 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wdegrid_cols_kernel(
             if (own) {
                 cplx<R> v[8];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) v[t] = p == 0 ? pv[t] : pv[t] * twiddle<R, false>(tt, (jr + t * M) << shg);
+                for (int t = 0; t < 8; ++t) {
+                    const int i = (jr + t * M) ^ hs;
+                    const int e = qs ? (i + gx - N / 2) & (gx - 1) : i;
+                    v[t] = p == 0 ? pv[t] : pv[t] * twiddle<R, false>(tt, e << shg);
+                }
                 dft_small<R, false, 8>(v);
                 stage_twiddles<R, false, 8>(v, tt, jr << shn);
                 cplx<R> *vb = buf + c * ld + LD::pad(jr);
@@ -2041,7 +2062,8 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wdegrid_cols_kernel(
 #pragma unroll
                 for (int t = 0; t < R0; ++t) {
                     const int u = 2 * dit_inv<LOG2N>(gq * R0 + t) + p;
-                    if (nrow[u >> lgT]) T[(size_t)u * CG + cc] = v[t] * twiddle<R, true>(tt, ((u * hx) & (gx - 1)) << shg);
+                    if (nrow[u >> lgT])
+                        T[(size_t)u * CG + cc] = qs ? v[t] : v[t] * twiddle<R, true>(tt, ((u * hx) & (gx - 1)) << shg);
                 }
             }
             if (p == 0) __syncthreads();   // the odd half overwrites the buffer
