@@ -102,3 +102,30 @@ def test_paper_image_1728x1200(prec):
     for k in ("dirty", "degrid", "hessian", "psf", "psf_conv"):
         assert e[k] < tol, k
     assert e["cg"] < (1e-4 if prec == "fp32" else 1e-9)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_partial_last_column_group(prec):
+    """64 x 34: the cropped row spectra of the w-plane transforms are stored in
+    groups of 8 (FP32) or 4 (FP64) columns, and the convolution's half spectra in
+    groups of 4 (FP32) or 2 (FP64): with ny = 34 the last plane group holds 2 of
+    its columns, and gx = 2 nx takes the index-shift form of the centring factors
+    while gy = 128 > 2 ny does not.  Operators against the FP64 oracle, two bands."""
+    R, C = _dt(prec)
+    prob = synth.tiny_problem(seed=synth.SEED_BASE + 64, nx=64, ny=34, n_row=900, cell_arcsec=40.0,
+                              n_band=2, freqs=(1.0e9, 1.1e9, 1.2e9, 1.3e9), flag_frac=0.1, w_frac=0.5)
+    rng = np.random.default_rng(65)
+    vis = rng.normal(size=(prob.n_row, prob.n_chan)) + 1j * rng.normal(size=(prob.n_row, prob.n_chan))
+    x = rng.normal(size=(2, 64, 34))
+    plan = make_plan(prob, prec)
+    inf = plan.info()
+    assert (inf["grid_x"], inf["grid_y"]) == (128, 128)
+    e = {"dirty": rel(host(plan.grid(to_dev(vis, C))), oracle.grid(prob, vis)),
+         "degrid": rel(host(plan.degrid(to_dev(x, R))), oracle.degrid(prob, x)),
+         "hessian": rel(host(plan.hessian(to_dev(x, R))), oracle.hessian(prob, x))}
+    psf = oracle.psf(prob)
+    e["psf"] = rel(host(plan.make_psf()), psf)
+    e["psf_conv"] = rel(host(plan.psf_conv(to_dev(x, R))), oracle.psf_conv(psf, x))
+    say(f"64x34 {prec}: w-planes {inf['n_wplanes_max']}; " + ", ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    for k, v in e.items():
+        assert v < TOL[prec], k
