@@ -230,6 +230,32 @@ def test_multiband_all_operators(multi, prec, chunk):
     assert rel(host(plan.psf_conv(to_dev(multi["x"], R))), multi["conv"]) < TOL[prec]
 
 
+@pytest.fixture(scope="module")
+def three():
+    prob = synth.tiny_problem(seed=79, nx=48, ny=40, n_row=500, freqs=(1.0e9, 1.05e9, 1.2e9, 1.25e9, 1.4e9, 1.45e9),
+                              cell_arcsec=90.0, w_frac=1.0, n_band=3, flag_frac=0.15)
+    rng = np.random.default_rng(80)
+    x = rng.normal(size=(3, 48, 40))
+    vis = rng.normal(size=(prob.n_row, prob.n_chan)) + 1j * rng.normal(size=(prob.n_row, prob.n_chan))
+    say("oracle: three-band references")
+    return dict(prob=prob, x=x, vis=vis, dirty=oracle.grid(prob, vis), degrid=oracle.degrid(prob, x),
+                hess=oracle.hessian(prob, x))
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+@pytest.mark.parametrize("band_batch", [1, 2])
+def test_partial_band_batches(three, prec, band_batch):
+    """Three bands with one or two bands' w-planes resident at a time: the batches
+    start at bands 0, 1, 2 or 0, 2, so every per-band table (work lists, tile-row
+    lists, flags) is read from a band offset and the last batch is short."""
+    R, C = _dtypes(prec)
+    plan = make_plan(three["prob"], prec, band_batch=band_batch)
+    assert plan.info()["band_batch"] == band_batch
+    assert rel(host(plan.grid(to_dev(three["vis"], C))), three["dirty"]) < TOL[prec]
+    assert rel(host(plan.degrid(to_dev(three["x"], R))), three["degrid"]) < TOL[prec]
+    assert rel(host(plan.hessian(to_dev(three["x"], R))), three["hess"]) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", PRECISIONS)
 def test_flat_mode_hessian_equals_psf_convolution(multi, prec):
     """Without w and 1/n the Hessian is exactly the PSF convolution (eq. 4 becomes exact)."""
