@@ -1,6 +1,7 @@
 // Device-side building blocks shared by the gfx950 kernels: complex
-// arithmetic, the exponential-of-semicircle (ES) kernel, and an LDS-resident
-// mixed radix-2/4/8 decimation-in-time FFT used by every transform pass.
+// arithmetic, the exponential-of-semicircle (ES) kernel, and LDS-resident
+// mixed radix-2/4/8 FFT stages (decimation in time for the row passes, in
+// frequency for the split column passes) used by every transform pass.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
