@@ -90,6 +90,22 @@ Profiler::~Profiler() {
 
 __device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
 
+// exp(-2 pi i t / 16), t = 0 .. 7: w^(t N / 8) for w = exp(-2 pi i / 2N), the
+// factor between the eight inputs of an outermost radix-8 butterfly (t a constant
+// once the loop over t is unrolled)
+template <typename R> __device__ __forceinline__ cplx<R> root16(int t) {
+    const R c1 = R(0.92387953251128675613), s1 = R(0.38268343236508977173), h = R(0.70710678118654752440);
+    switch (t) {
+        case 0: return cplx<R>{R(1), R(0)};
+        case 1: return cplx<R>{c1, -s1};
+        case 2: return cplx<R>{h, -h};
+        case 3: return cplx<R>{s1, -c1};
+        case 4: return cplx<R>{R(0), R(-1)};
+        case 5: return cplx<R>{-s1, -c1};
+        case 6: return cplx<R>{-h, -h};
+        default: return cplx<R>{-c1, -s1};
+    }
+}
 __device__ __forceinline__ int wrapi(int a, int n) {
     a %= n;
     return a < 0 ? a + n : a;
@@ -1667,7 +1683,6 @@ template <int LOG2L> __host__ __device__ constexpr int row_threads() {
 // rows per workgroup: the largest power of two whose LDS tiles fit kRowLds
 template <typename R, int LOG2L>
 __host__ __device__ constexpr int rows_per_block() {
-    constexpr int L = 1 << LOG2L;
     constexpr int per = Lds<R, LOG2L>::ld * (int)sizeof(cplx<R>);
     int c = 1;
     while (2 * c * per <= kRowLds) c *= 2;
@@ -2023,14 +2038,17 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wdegrid_cols_kernel(
 #pragma unroll 1
         for (int p = 0; p < 2; ++p) {
             // forward N-point DFT of x w^(p i) by decimation in frequency: the first stage
-            // from registers, X[k'] ends at the DIT position of k'
+            // from registers, X[k'] ends at the DIT position of k'.  The odd half's factor
+            // at position jr + t M is w^jr exp(-2 pi i t / 16), negated for t >= 4 when the
+            // rows are shifted (w^N = -1)
             if (own) {
                 cplx<R> v[8];
+                const cplx<R> wj = twiddle<R, false>(tt, jr << shg);
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
-                    const int i = (jr + t * M) ^ hs;
-                    const int e = qs ? (i + gx - N / 2) & (gx - 1) : i;
-                    v[t] = p == 0 ? pv[t] : pv[t] * twiddle<R, false>(tt, e << shg);
+                    cplx<R> f = wj * root16<R>(t);
+                    if (qs && t >= 4) f = cplx<R>{-f.re, -f.im};
+                    v[t] = p == 0 ? pv[t] : pv[t] * f;
                 }
                 dft_small<R, false, 8>(v);
                 stage_twiddles<R, false, 8>(v, tt, jr << shn);
@@ -2289,6 +2307,7 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
         }
     }
     __syncthreads();   // twiddle table
+    const cplx<R> wj = twiddle<R, false>(tt, j << sh2n);
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         // forward N-point DFT of the even (p = 0) or odd (p = 1) half by decimation in
@@ -2305,7 +2324,7 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
                 } else {
                     x = xin[t];
                 }
-                v[t] = p == 0 ? x : x * twiddle<R, false>(tt, r << sh2n);
+                v[t] = p == 0 ? x : x * (wj * root16<R>(t));   // w^r = w^j exp(-2 pi i t / 16)
             }
             dft_small<R, false, 8>(v);
             stage_twiddles<R, false, 8>(v, tt, (j * (N / (8 * M))) << shn);
@@ -2367,7 +2386,7 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
             for (int t = 0; t < 8; ++t) {
                 if (p == 0) ev[t] = v[t];
                 else if (j + t * M < a.nx)   // the crop: rows 0 .. nx - 1
-                    Y[(j + t * M) * CG + c] = ev[t] + v[t] * twiddle<R, true>(tt, (j + t * M) << sh2n);
+                    Y[(j + t * M) * CG + c] = ev[t] + v[t] * conj(wj * root16<R>(t));
             }
         }
         __syncthreads();
