@@ -138,22 +138,75 @@ template <typename R, bool INV, int RAD> __device__ __forceinline__ void dft_sma
 // hi[k] = w^(k 2^sh) copied from the FP64-accurate forward table in HBM (one
 // complex product, about 1.5 ulp; an LDS read instead of a scattered global one).
 constexpr int kTwEntries = 256;   // lo + hi entries for Lmax <= 2^14
+
+// The radix-8 stages below the outermost one of an L-point transform
+// can take their twiddles from direct tables: for the span m of such a stage
+// (the spans are R0 8^s, R0 the radix of the span-1 stage), the values
+// w_{8m}^{t j} = exp(-2 pi i t j / (8 m)) for t = 1 .. 7, j < m, at
+// off(m) + (t - 1) m + j, copied from the same HBM table and read once each (no
+// products, no index arithmetic beyond the butterfly's j).  Whole tables of the smallest spans are kept, as
+// many as the kernel's LDS budget allows; mtop is the first span without one.
+template <int LOG2L> struct StageTab {
+    static constexpr int L = 1 << LOG2L;
+    static constexpr int R0 = (LOG2L % 3) ? (1 << (LOG2L % 3)) : 8;
+    // entries of the tables of the spans below m
+    static __host__ __device__ constexpr int off(int m) {
+        int e = 0;
+        for (int s = R0; s < m; s *= 8) e += 7 * s;
+        return e;
+    }
+    // entries kept within a budget of maxe
+    static __host__ __device__ constexpr int entries(int maxe) {
+        int e = 0;
+        for (int s = R0; s < L / 8 && e + 7 * s <= maxe; s *= 8) e += 7 * s;
+        return e;
+    }
+    static __host__ __device__ constexpr int mtop(int se) {
+        int s = R0;
+        for (int e = 0; s < L / 8 && e + 7 * s <= se; s *= 8) e += 7 * s;
+        return s;
+    }
+};
 template <typename R> struct TwTab {
     const cplx<R> *lo, *hi;
     int sh, mask;
+    const cplx<R> *st;   // direct tables of the spans below mtop
+    int mtop;
     __device__ __forceinline__ cplx<R> get(int e) const { return lo[e & mask] * hi[e >> sh]; }
 };
-// fill the table at lds (kTwEntries elements) from the table of length 2^log2_lmax;
-// the caller synchronises the block before the first use
-template <typename R, int NT>
+// fill the two-level table at lds (kTwEntries elements) from the table of length
+// 2^log2_lmax, and after it the SE entries of the direct tables of a 2^LOG2L-point
+// transform (SE = StageTab<LOG2L>::entries(budget)); the caller synchronises the
+// block before the first use
+template <typename R, int NT, int LOG2L, int SE>
 __device__ __forceinline__ TwTab<R> tw_fill(cplx<R> *lds, const cplx<R> *tw, int log2_lmax) {
+    using ST = StageTab<LOG2L>;
     const int sh = (log2_lmax + 1) / 2, nlo = 1 << sh, nhi = 1 << (log2_lmax - sh);
     for (int k = threadIdx.x; k < nlo + nhi; k += NT) lds[k] = k < nlo ? tw[k] : tw[(k - nlo) << sh];
-    return TwTab<R>{lds, lds + nlo, sh, nlo - 1};
+    cplx<R> *st = lds + kTwEntries;
+    for (int k = threadIdx.x; k < SE; k += NT) {
+        int m = ST::R0, o = 0;
+        while (k >= o + 7 * m) {
+            o += 7 * m;
+            m *= 8;
+        }
+        const int t = (k - o) / m + 1, j = k - o - (t - 1) * m;
+        st[k] = tw[(t * j * (ST::L / (8 * m))) << (log2_lmax - LOG2L)];
+    }
+    return TwTab<R>{lds, lds + nlo, sh, nlo - 1, st, ST::mtop(SE)};
 }
 template <typename R, bool INV> __device__ __forceinline__ cplx<R> twiddle(const TwTab<R> &tt, int e) {
     cplx<R> w = tt.get(e);
     return INV ? conj(w) : w;
+}
+
+// v[t] *= w^(t j) for t = 1 .. 7 from a direct table (p = st + off(m) + j)
+template <typename R, bool INV> __device__ __forceinline__ void stage_twiddles_tab(cplx<R> *v, const cplx<R> *p, int m) {
+#pragma unroll
+    for (int t = 1; t < 8; ++t) {
+        const cplx<R> w = p[(t - 1) * m];
+        v[t] = v[t] * (INV ? conj(w) : w);
+    }
 }
 
 // v[t] *= w^(t e) for t = 1 .. RAD - 1
@@ -197,7 +250,8 @@ __device__ __forceinline__ void dit_stage(cplx<R> *buf, int C, int ld, int m, co
         cplx<R> v[RAD];
 #pragma unroll
         for (int t = 0; t < RAD; ++t) v[t] = vb[Lds<R, LOG2L>::pad(t * m)];
-        if (m > 1) stage_twiddles<R, INV, RAD>(v, tw, j * estep);
+        if (RAD == 8 && m > 1 && m < tw.mtop) stage_twiddles_tab<R, INV>(v, tw.st + StageTab<LOG2L>::off(m) + j, m);
+        else if (m > 1) stage_twiddles<R, INV, RAD>(v, tw, j * estep);
         dft_small<R, INV, RAD>(v);
 #pragma unroll
         for (int t = 0; t < RAD; ++t) vb[Lds<R, LOG2L>::pad(t * m)] = v[t];
@@ -242,7 +296,8 @@ __device__ __forceinline__ void dif_stage(cplx<R> *buf, int C, int ld, int m, co
 #pragma unroll
         for (int t = 0; t < RAD; ++t) v[t] = vb[Lds<R, LOG2L>::pad(t * m)];
         dft_small<R, INV, RAD>(v);
-        if (m > 1) stage_twiddles<R, INV, RAD>(v, tw, j * estep);
+        if (RAD == 8 && m > 1 && m < tw.mtop) stage_twiddles_tab<R, INV>(v, tw.st + StageTab<LOG2L>::off(m) + j, m);
+        else if (m > 1) stage_twiddles<R, INV, RAD>(v, tw, j * estep);
 #pragma unroll
         for (int t = 0; t < RAD; ++t) vb[Lds<R, LOG2L>::pad(t * m)] = v[t];
     }

@@ -1688,6 +1688,20 @@ __host__ __device__ constexpr int rows_per_block() {
     while (2 * c * per <= kRowLds) c *= 2;
     return c;
 }
+// entries of the direct stage twiddle tables of a 2^LOG2L-point transform that a
+// block can keep beside `other` bytes of LDS while two blocks still fit a CU
+template <typename R, int LOG2L> __host__ __device__ constexpr int tw_stage_entries(size_t other) {
+    constexpr size_t half = kMaxLdsBytes / 2, tab = kTwEntries * sizeof(cplx<R>);
+    return other + tab >= half ? 0 : StageTab<LOG2L>::entries((int)((half - other - tab) / sizeof(cplx<R>)));
+}
+// the row passes: budget for their most rows per block
+template <typename R, int LOG2L> __host__ __device__ constexpr int row_tw_se() {
+    return tw_stage_entries<R, LOG2L>((size_t)rows_per_block<R, LOG2L>() * Lds<R, LOG2L>::ld * sizeof(cplx<R>));
+}
+// LDS bytes of a row-pass block of C vectors
+template <typename R, int LOG2L> constexpr size_t row_lds(int C) {
+    return (size_t)C * (Lds<R, LOG2L>::ld * sizeof(cplx<R>)) + (kTwEntries + row_tw_se<R, LOG2L>()) * sizeof(cplx<R>);
+}
 
 // Plane intermediate of the grid and degrid transforms (cropped row spectra),
 // group-major: column iy = g CG + c of uv row u of plane (bb, j) sits at
@@ -1710,8 +1724,9 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformA
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    cplx<R> *buf = twl + kTwEntries + row_tw_se<R, LOG2L>();
+    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>(), LOG2L, row_tw_se<R, LOG2L>()>(
+        twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int gx = a.g.gx;
     // block: C consecutive rows of a listed tile row (one that holds occupied tiles)
@@ -1747,8 +1762,9 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformA
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    cplx<R> *buf = twl + kTwEntries + row_tw_se<R, LOG2L>();
+    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>(), LOG2L, row_tw_se<R, LOG2L>()>(
+        twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int gx = a.g.gx, ny = a.g.ny;
     // block: C consecutive rows of a listed tile row (one with tiles the interpolation reads)
@@ -1797,10 +1813,11 @@ template <typename R, int LOG2N, int C> struct WCols {
     static_assert(NT0 <= 1024, "at most 1024 threads per block");
     static constexpr int R0 = FftPlan<LOG2N>::radix(0);
     static constexpr int ITER = (C * (N / R0) + NT - 1) / NT;   // innermost-stage items per thread
-    // the transform buffer, the twiddle table and two per-thread arrays of 8 values
+    // the transform buffer, the twiddle tables and two per-thread arrays of 8 values
     // that live across the plane loop (kept in LDS, not in registers)
-    static constexpr size_t lds = (size_t)C * Lds<R, LOG2N>::ld * sizeof(cplx<R>) + kTwEntries * sizeof(cplx<R>) +
-                                  2 * 8 * (size_t)NT * sizeof(R);
+    static constexpr size_t other = (size_t)C * Lds<R, LOG2N>::ld * sizeof(cplx<R>) + 2 * 8 * (size_t)NT * sizeof(R);
+    static constexpr int SE = tw_stage_entries<R, LOG2N>(other);
+    static constexpr size_t lds = other + (kTwEntries + SE) * sizeof(cplx<R>);
 };
 // columns per block: the most (up to a whole group) whose C x N block spans at
 // most 1024 threads and 64 KiB of LDS
@@ -1834,8 +1851,8 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wgrid_cols_kernel(Xf
     static_assert(S >= 2 && P::radix(S - 1) == 8, "columns of at least 16 points");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, NT>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    cplx<R> *buf = twl + kTwEntries + K::SE;
+    const TwTab<R> tt = tw_fill<R, NT, LOG2N, K::SE>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny, hx = nx / 2;
     const int G = (ny + CG - 1) / CG;
     const WColsBlock wb = wcols_block<CG / C>(a.n_bb, G);
@@ -1980,8 +1997,8 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wdegrid_cols_kernel(
     static_assert(S >= 2 && P::radix(S - 1) == 8, "columns of at least 16 points");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, NT>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    cplx<R> *buf = twl + kTwEntries + K::SE;
+    const TwTab<R> tt = tw_fill<R, NT, LOG2N, K::SE>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int gx = a.g.gx, nx = a.g.nx, ny = a.g.ny, hx = nx / 2;
     const int G = (ny + CG - 1) / CG;
     const WColsBlock wb = wcols_block<CG / C>(a.n_bb, G);
@@ -2114,7 +2131,7 @@ static hipError_t grid_xform_t(const XformArgs &a, hipStream_t s) {
     hipError_t e = dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = std::min(rows_per_block<R, LG>(), a.g.T);
-        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
+        const size_t lds = row_lds<R, LG>(C);
         const int64_t nb = (int64_t)a.n_occ_list * (a.g.T / C);
         if (nb > 0) PFB_LAUNCH_NT((g1_rows_kernel<R, LG>), nb, row_threads<LG>(), lds, s, a, C);
         return hipSuccess;
@@ -2131,7 +2148,7 @@ static hipError_t degrid_xform_t(const XformArgs &a, hipStream_t s) {
     return dispatch_int<5, 14>(lgy, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C2 = std::min(rows_per_block<R, LG>(), a.g.T);
-        const size_t lds = (size_t)C2 * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
+        const size_t lds = row_lds<R, LG>(C2);
         const int64_t nb = (int64_t)a.n_need_list * (a.g.T / C2);
         if (nb > 0) PFB_LAUNCH_NT((d3_rows_kernel<R, LG>), nb, row_threads<LG>(), lds, s, a, C2);
         return hipSuccess;
@@ -2176,8 +2193,9 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a,
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    cplx<R> *buf = twl + kTwEntries + row_tw_se<R, LOG2L>();
+    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>(), LOG2L, row_tw_se<R, LOG2L>()>(
+        twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
     const int ngrp = nrows / (2 * C);
@@ -2253,7 +2271,8 @@ template <typename R, int LOG2N, int C> struct ConvCols {
     static constexpr int NT0 = C * N / 8;   // one radix-8 butterfly per thread and stage
     static constexpr int NT = NT0 < 64 ? 64 : NT0;
     static_assert(NT0 <= 1024, "at most 1024 threads per block");
-    static constexpr size_t lds = (size_t)C * Lds<R, LOG2N>::ld * sizeof(cplx<R>) + kTwEntries * sizeof(cplx<R>);
+    static constexpr int SE = tw_stage_entries<R, LOG2N>((size_t)C * Lds<R, LOG2N>::ld * sizeof(cplx<R>));
+    static constexpr size_t lds = (size_t)C * Lds<R, LOG2N>::ld * sizeof(cplx<R>) + (kTwEntries + SE) * sizeof(cplx<R>);
 };
 
 // A block transforms C of the CG columns of a group (CG / C blocks per group).
@@ -2275,8 +2294,8 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
     constexpr int ld = LD::ld;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, NT>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    cplx<R> *buf = twl + kTwEntries + K::SE;
+    const TwTab<R> tt = tw_fill<R, NT, LOG2N, K::SE>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     const int G = (a.ly / 2 + CG) / CG;   // groups of the ly / 2 + 1 columns
     const int xcd = blockIdx.x & 7, jb = blockIdx.x >> 3;
     const int sub = jb % NSUB, gi = (jb / NSUB) * 8 + xcd;
@@ -2430,8 +2449,9 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a,
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *buf = twl + kTwEntries;
-    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>()>(twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
+    cplx<R> *buf = twl + kTwEntries + row_tw_se<R, LOG2L>();
+    const TwTab<R> tt = tw_fill<R, row_threads<LOG2L>(), LOG2L, row_tw_se<R, LOG2L>()>(
+        twl, reinterpret_cast<const cplx<R> *>(a.tw), a.log2_lmax);
     __shared__ double red[row_threads<LOG2L>() / 64];
     const int ld = Lds<R, LOG2L>::ld;
     const int nx = a.nx, ny = a.ny;
@@ -2510,7 +2530,7 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
     hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = conv_row_pairs(rows_per_block<R, LG>(), a.nx);   // vectors = row pairs
-        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
+        const size_t lds = row_lds<R, LG>(C);
         const int nb = a.n_band * (a.nx / (2 * C));
         const R *xr = reinterpret_cast<const R *>(x);
         R *ap = reinterpret_cast<R *>(aux_in);
@@ -2525,7 +2545,7 @@ static hipError_t psf_conv_t(const ConvArgs &a, const void *x, void *aux_in, voi
     return dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = conv_row_pairs(rows_per_block<R, LG>(), a.nx);   // vectors = row pairs
-        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
+        const size_t lds = row_lds<R, LG>(C);
         const int nb = a.n_band * (a.nx / (2 * C));
         R *yr = reinterpret_cast<R *>(y);
         const R *ax = reinterpret_cast<const R *>(aux_out);
@@ -2565,7 +2585,7 @@ static hipError_t psfhat_t(const ConvArgs &a, const void *psf_img, hipStream_t s
     hipError_t e = dispatch_int<5, 14>(lg, [&](auto Lc) -> hipError_t {
         constexpr int LG = decltype(Lc)::value;
         const int C = std::min(rows_per_block<R, LG>(), a.lx / 2);      // vectors = row pairs of lx rows
-        const size_t lds = (size_t)C * (Lds<R, LG>::ld * sizeof(cplx<R>)) + kTwEntries * sizeof(cplx<R>);
+        const size_t lds = row_lds<R, LG>(C);
         const int nb = a.n_band * (a.lx / (2 * C));
         PFB_LAUNCH_NT((s1_kernel<R, LG, CONV_IN_X>), nb, row_threads<LG>(), lds, s, a, reinterpret_cast<const R *>(psf_img),
                    (R *)nullptr, a.lx, C, 1);
