@@ -347,44 +347,70 @@ template <int D> __device__ __forceinline__ int rev8(int q) {
     return r;
 }
 
+// Input and output of the row transforms go in two steps each, so that all the
+// global loads of a thread's batch are issued before any of them is waited for
+// (a load whose value is used at once, or a store between loads, would expose
+// each load's latency in turn):
+//   fetch_in(c, r)          loads of input r of vector c (no arithmetic, no stores)
+//   make_in(c, r, raw)      the input value from them (arithmetic, side effects)
+//   fetch_out(c, k)         loads that output k of vector c needs
+//   put_out(c, k, v, raw)   its stores
+struct NoRaw {};
+struct InPlain {   // make_in for inputs loaded as they are
+    template <class T> __device__ __forceinline__ T operator()(int, int, const T &raw) const { return raw; }
+};
+struct OutNoFetch {
+    __device__ __forceinline__ NoRaw operator()(int, int) const { return NoRaw{}; }
+};
+// items per thread whose loads are in flight together in the unfused input and
+// output loops: eight, or four in 1024-thread blocks (two of them per CU leave 64
+// registers per lane)
+template <class Raw, int NT> constexpr int io_batch() { return NT >= 1024 ? 4 : 8; }
+
 // FFT of C vectors of length 2^LOG2L (2^5 .. 2^14) whose first stage reads its
-// inputs through load(c, n) (natural order n) and, with STORE_REGS, whose last
-// stage hands its outputs to store(c, k, value) (natural order k) instead of
-// writing them to LDS; without STORE_REGS the result is in LDS at
+// inputs through fetch_in / make_in (natural order n) and, with STORE_REGS, whose
+// last stage hands its outputs to fetch_out / put_out (natural order k) instead
+// of writing them to LDS; without STORE_REGS the result is in LDS at
 // Lds::pad(k) after a final barrier.  The first stage (radix R0, span 1) takes
 // inputs t Q + q (Q = L / R0, t < R0): its outputs belong at DIT positions
 // rev8(q) R0 + t, which replaces the digit-reversed scatter and one LDS pass.
-template <typename R, bool INV, int LOG2L, int NT, bool STORE_REGS, class Load, class Store>
-__device__ __forceinline__ void lds_fft_io(cplx<R> *buf, int C, int ld, const TwTab<R> &tw, int tw_shift, Load load,
-                                           Store store) {
+template <typename R, bool INV, int LOG2L, int NT, bool STORE_REGS, class FIn, class MIn, class FOut, class POut>
+__device__ __forceinline__ void lds_fft_io(cplx<R> *buf, int C, int ld, const TwTab<R> &tw, int tw_shift,
+                                           FIn fetch_in, MIn make_in, FOut fetch_out, POut put_out) {
     using P = FftPlan<LOG2L>;
     constexpr int L = 1 << LOG2L;
     constexpr int S = P::NSTAGE;
     constexpr int R0 = P::radix(0);
     constexpr int Q = L / R0;
     static_assert(S >= 2, "at least two stages");
-    // G = 8 / R0 butterflies per thread and iteration keep eight loads in flight
+    using Raw = decltype(fetch_in(0, 0));
+    // G = 8 / R0 butterflies per thread and iteration keep eight loads in flight;
+    // when the thread count divides the work no bounds test separates the loads
     constexpr int G = 8 / R0;
+    constexpr bool EXACT = Q % (G * NT) == 0;
     for (int id0 = threadIdx.x; id0 < C * Q; id0 += G * NT) {
-        cplx<R> v[G][R0];
+        Raw raw[G][R0];
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int id = id0 + u * NT;
-            if (id < C * Q) {
+            if (EXACT || id < C * Q) {
                 const int c = id / Q, q = id - c * Q;
 #pragma unroll
-                for (int t = 0; t < R0; ++t) v[u][t] = load(c, t * Q + q);
+                for (int t = 0; t < R0; ++t) raw[u][t] = fetch_in(c, t * Q + q);
             }
         }
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int id = id0 + u * NT;
-            if (id < C * Q) {
+            if (EXACT || id < C * Q) {
                 const int c = id / Q, q = id - c * Q;
-                dft_small<R, INV, R0>(v[u]);
+                cplx<R> v[R0];
+#pragma unroll
+                for (int t = 0; t < R0; ++t) v[t] = make_in(c, t * Q + q, raw[u][t]);
+                dft_small<R, INV, R0>(v);
                 cplx<R> *vb = buf + c * ld + Lds<R, LOG2L>::pad(rev8<S - 1>(q) * R0);
 #pragma unroll
-                for (int t = 0; t < R0; ++t) vb[Lds<R, LOG2L>::pad(t)] = v[u][t];
+                for (int t = 0; t < R0; ++t) vb[Lds<R, LOG2L>::pad(t)] = v[t];
             }
         }
     }
@@ -400,8 +426,12 @@ __device__ __forceinline__ void lds_fft_io(cplx<R> *buf, int C, int ld, const Tw
     if constexpr (STORE_REGS) {
         // last stage: span m = L / 8; butterfly j holds outputs j + t m
         constexpr int M = L / 8;
+        using ORaw = decltype(fetch_out(0, 0));
         for (int id = threadIdx.x; id < C * M; id += NT) {
             const int c = id / M, j = id - c * M;
+            ORaw oraw[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) oraw[t] = fetch_out(c, j + t * M);
             const cplx<R> *vb = buf + c * ld + Lds<R, LOG2L>::pad(j);
             cplx<R> v[8];
 #pragma unroll
@@ -409,33 +439,70 @@ __device__ __forceinline__ void lds_fft_io(cplx<R> *buf, int C, int ld, const Tw
             stage_twiddles<R, INV, 8>(v, tw, j << tw_shift);
             dft_small<R, INV, 8>(v);
 #pragma unroll
-            for (int t = 0; t < 8; ++t) store(c, j + t * M, v[t]);
+            for (int t = 0; t < 8; ++t) put_out(c, j + t * M, v[t], oraw[t]);
         }
     }
 }
 
 // lds_fft_io when FUSE, else the same interface over the plain sequence: every
-// input scattered to its DIT position, lds_fft, and (STORE_REGS) store of every
-// output read back from LDS.  The fused first stage measured slower where it
-// starts with radix 2 or 4 (fewer loads in flight, for most kernels).
-template <typename R, bool INV, int LOG2L, int NT, bool STORE_REGS, bool FUSE, class Load, class Store>
-__device__ __forceinline__ void row_fft(cplx<R> *buf, int C, int ld, const TwTab<R> &tw, int tw_shift, Load load,
-                                        Store store) {
+// input scattered to its DIT position, lds_fft, and (STORE_REGS) every output
+// read back from LDS.  The fused first stage measured slower where it starts with
+// radix 2 or 4.
+template <typename R, bool INV, int LOG2L, int NT, bool STORE_REGS, bool FUSE, class FIn, class MIn, class FOut, class POut>
+__device__ __forceinline__ void row_fft(cplx<R> *buf, int C, int ld, const TwTab<R> &tw, int tw_shift, FIn fetch_in,
+                                        MIn make_in, FOut fetch_out, POut put_out) {
     if constexpr (FUSE) {
-        lds_fft_io<R, INV, LOG2L, NT, STORE_REGS>(buf, C, ld, tw, tw_shift, load, store);
+        lds_fft_io<R, INV, LOG2L, NT, STORE_REGS>(buf, C, ld, tw, tw_shift, fetch_in, make_in, fetch_out, put_out);
     } else {
         constexpr int L = 1 << LOG2L;
-        for (int id = threadIdx.x; id < C * L; id += NT) {
-            const int c = id / L, r = id - c * L;
-            buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = load(c, r);
+        using Raw = decltype(fetch_in(0, 0));
+        constexpr int U = io_batch<Raw, NT>();
+        constexpr bool EXACT = L % (U * NT) == 0;
+        for (int id0 = threadIdx.x; id0 < C * L; id0 += U * NT) {
+            Raw raw[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int id = id0 + u * NT;
+                if (EXACT || id < C * L) {
+                    const int c = id / L, r = id - c * L;
+                    raw[u] = fetch_in(c, r);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int id = id0 + u * NT;
+                if (EXACT || id < C * L) {
+                    const int c = id / L, r = id - c * L;
+                    buf[c * ld + Lds<R, LOG2L>::pad(dit_pos<LOG2L>(r))] = make_in(c, r, raw[u]);
+                }
+            }
         }
         __syncthreads();
         lds_fft<R, INV, LOG2L, NT>(buf, C, ld, tw, tw_shift);
-        if constexpr (STORE_REGS)
-            for (int id = threadIdx.x; id < C * L; id += NT) {
-                const int c = id / L, k = id - c * L;
-                store(c, k, buf[c * ld + Lds<R, LOG2L>::pad(k)]);
+        if constexpr (STORE_REGS) {
+            using ORaw = decltype(fetch_out(0, 0));
+            constexpr int UO = io_batch<ORaw, NT>();
+            constexpr bool EXO = L % (UO * NT) == 0;
+            for (int id0 = threadIdx.x; id0 < C * L; id0 += UO * NT) {
+                ORaw oraw[UO];
+#pragma unroll
+                for (int u = 0; u < UO; ++u) {
+                    const int id = id0 + u * NT;
+                    if (EXO || id < C * L) {
+                        const int c = id / L, k = id - c * L;
+                        oraw[u] = fetch_out(c, k);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UO; ++u) {
+                    const int id = id0 + u * NT;
+                    if (EXO || id < C * L) {
+                        const int c = id / L, k = id - c * L;
+                        put_out(c, k, buf[c * ld + Lds<R, LOG2L>::pad(k)], oraw[u]);
+                    }
+                }
             }
+        }
     }
 }
 // the fused form for lengths whose plan starts with radix 8

@@ -1680,6 +1680,8 @@ constexpr int kRowLds = 32768;   // target LDS bytes per row-transform workgroup
 template <int LOG2L> __host__ __device__ constexpr int row_threads() {
     return (1 << LOG2L) / 8 > 1024 ? 1024 : ((1 << LOG2L) / 8 < kThreads ? kThreads : (1 << LOG2L) / 8);
 }
+// waves per SIMD that two row-pass blocks per CU need (the register budget)
+template <int LOG2L> __host__ __device__ constexpr int row_min_waves() { return row_threads<LOG2L>() / 128; }
 // rows per workgroup: the largest power of two whose LDS tiles fit kRowLds
 template <typename R, int LOG2L>
 __host__ __device__ constexpr int rows_per_block() {
@@ -1694,13 +1696,18 @@ template <typename R, int LOG2L> __host__ __device__ constexpr int tw_stage_entr
     constexpr size_t half = kMaxLdsBytes / 2, tab = kTwEntries * sizeof(cplx<R>);
     return other + tab >= half ? 0 : StageTab<LOG2L>::entries((int)((half - other - tab) / sizeof(cplx<R>)));
 }
+// bytes after a row-pass block's vectors for one tile row's occupancy flags (at
+// most L / 8 tiles: tiles have at least 8 cells)
+template <int LOG2L> __host__ __device__ constexpr size_t row_aux_bytes() { return ((1 << LOG2L) / 8 + 15) / 16 * 16; }
 // the row passes: budget for their most rows per block
 template <typename R, int LOG2L> __host__ __device__ constexpr int row_tw_se() {
-    return tw_stage_entries<R, LOG2L>((size_t)rows_per_block<R, LOG2L>() * Lds<R, LOG2L>::ld * sizeof(cplx<R>));
+    return tw_stage_entries<R, LOG2L>((size_t)rows_per_block<R, LOG2L>() * Lds<R, LOG2L>::ld * sizeof(cplx<R>) +
+                                      row_aux_bytes<LOG2L>());
 }
 // LDS bytes of a row-pass block of C vectors
 template <typename R, int LOG2L> constexpr size_t row_lds(int C) {
-    return (size_t)C * (Lds<R, LOG2L>::ld * sizeof(cplx<R>)) + (kTwEntries + row_tw_se<R, LOG2L>()) * sizeof(cplx<R>);
+    return (size_t)C * (Lds<R, LOG2L>::ld * sizeof(cplx<R>)) + (kTwEntries + row_tw_se<R, LOG2L>()) * sizeof(cplx<R>) +
+           row_aux_bytes<LOG2L>();
 }
 
 // Plane intermediate of the grid and degrid transforms (cropped row spectra),
@@ -1720,7 +1727,7 @@ int plane_group_cols(bool dbl) { return dbl ? plane_cg<double>() : plane_cg<floa
 
 // G1: inverse row DFT of every plane row, keeping the ny cropped outputs.
 template <typename R, int LOG2L>
-__global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformArgs a, int C) {
+__global__ __launch_bounds__(row_threads<LOG2L>(), row_min_waves<LOG2L>()) void g1_rows_kernel(XformArgs a, int C) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
@@ -1741,15 +1748,23 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformA
     // tiles of these rows that hold spread values (the rest of the plane is zero
     // and is not read)
     const int lgT = __builtin_ctz(a.g.T), nty = a.g.nty;   // tiles are powers of two
-    const uint8_t *occ = a.occ + (size_t)pj * a.g.ntx * nty;
+    // the C rows lie in one tile row: its flags go to LDS first, so that the row
+    // loads do not wait on flag loads
+    const uint8_t *occ = a.occ + ((size_t)pj * a.g.ntx + (row0 >> lgT)) * nty;
+    uint8_t *occ_l = reinterpret_cast<uint8_t *>(buf + C * ld);
+    for (int k = threadIdx.x; k < nty; k += row_threads<LOG2L>()) occ_l[k] = occ[k];
+    __syncthreads();
     const int ny = a.g.ny;
     // output k of the row DFT is cropped column iy = k + ny / 2 (mod L), kept if iy < ny
     row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>()>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
         [&](int c, int r) -> cplx<R> {
-            return occ[((row0 + c) >> lgT) * nty + (r >> lgT)] ? src[(size_t)c * L + r] : cplx<R>{R(0), R(0)};
+            cplx<R> v{R(0), R(0)};
+            if (occ_l[r >> lgT]) v = src[(size_t)c * L + r];
+            return v;
         },
-        [&](int c, int k, const cplx<R> &v) {
+        InPlain{}, OutNoFetch{},
+        [&](int c, int k, const cplx<R> &v, NoRaw) {
             const int iy = (k + ny / 2) & (L - 1);
             if (iy < ny) dst[plane_at<R>(a, plane, row0 + c, iy)] = v;
         });
@@ -1758,7 +1773,7 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void g1_rows_kernel(XformA
 // D3: forward row DFT of the ny placed inputs of each row (the rows the degrid
 // column pass wrote: tile rows with needed tiles), full output to the plane.
 template <typename R, int LOG2L>
-__global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformArgs a, int C) {
+__global__ __launch_bounds__(row_threads<LOG2L>(), row_min_waves<LOG2L>()) void d3_rows_kernel(XformArgs a, int C) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
@@ -1778,16 +1793,23 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void d3_rows_kernel(XformA
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.planes) + (plane * gx + (size_t)row0) * L;
     // only tiles the interpolation may read are written
     const int lgT = __builtin_ctz(a.g.T), nty = a.g.nty;   // tiles are powers of two
-    const uint8_t *need = a.need + (size_t)pj * a.g.ntx * nty;
+    // the C rows lie in one tile row; its flags in LDS (read after the transform's
+    // barriers) keep flag loads out of the store loop
+    const uint8_t *need = a.need + ((size_t)pj * a.g.ntx + (row0 >> lgT)) * nty;
+    uint8_t *need_l = reinterpret_cast<uint8_t *>(buf + C * ld);
+    for (int k = threadIdx.x; k < nty; k += row_threads<LOG2L>()) need_l[k] = need[k];
     // input r of the row DFT is cropped column iy = r + ny / 2 (mod L), zero if iy >= ny
     row_fft<R, false, LOG2L, row_threads<LOG2L>(), true, true>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
         [&](int c, int r) -> cplx<R> {
             const int iy = (r + ny / 2) & (L - 1);
-            return iy < ny ? src[plane_at<R>(a, plane, row0 + c, iy)] : cplx<R>{R(0), R(0)};
+            cplx<R> v{R(0), R(0)};
+            if (iy < ny) v = src[plane_at<R>(a, plane, row0 + c, iy)];
+            return v;
         },
-        [&](int c, int k, const cplx<R> &v) {
-            if (need[((row0 + c) >> lgT) * nty + (k >> lgT)]) dst[(size_t)c * L + k] = v;
+        InPlain{}, OutNoFetch{},
+        [&](int c, int k, const cplx<R> &v, NoRaw) {
+            if (need_l[k >> lgT]) dst[(size_t)c * L + k] = v;
         });
 }
 
@@ -2189,7 +2211,7 @@ __device__ __forceinline__ size_t conv_out_off(const ConvArgs &a) { return (size
 // out as X_a[k] = (Z[k] + conj Z[L - k]) / 2, X_b[k] = (Z[k] - conj Z[L - k]) / 2i.
 // C vectors (2C rows) per block.
 template <typename R, int LOG2L, int IN>
-__global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a, const R *x, R *auxp, int nrows, int C, int psf) {
+__global__ __launch_bounds__(row_threads<LOG2L>(), row_min_waves<LOG2L>()) void s1_kernel(ConvArgs a, const R *x, R *auxp, int nrows, int C, int psf) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
@@ -2205,34 +2227,63 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s1_kernel(ConvArgs a,
     R bscale = R(1);
     if (IN == CONV_IN_CG_P) bscale = (R)a.scal[b * 8 + S_BETA];
     if (IN == CONV_IN_SCALED) bscale = (R)a.scal[b * 8 + S_SCALE];
-    auto load = [&](int i, int r) -> R {
-        R v = R(0);
-        if (psf) {
-            // grid index i holds offset di = i (first half) or i - lx (second half) of the
-            // PSF; offsets outside [-nx, nx) x [-ny, ny) are zero
-            const int di = i < a.lx / 2 ? i : i - a.lx, dj = r < a.ly / 2 ? r : r - a.ly;
-            if (di >= -nx && di < nx && dj >= -ny && dj < ny)
-                v = x[((size_t)b * 2 * nx + di + nx) * 2 * ny + dj + ny];
-        } else if (r < ny) {
-            const size_t pix = ((size_t)b * nx + i) * ny + r;
-            if (IN == CONV_IN_X) {
-                v = x[pix];
-            } else if (IN == CONV_IN_SCALED) {
-                v = x[pix] * bscale;
-            } else {
-                v = x[pix] + bscale * auxp[pix];
-                auxp[pix] = v;
-            }
-        }
-        return v;
+    // inputs r of rows i = ig 2C + 2c and i + 1 (one complex vector): loads first,
+    // then the value (and the CG direction update p = x + beta p, stored back);
+    // the PSF (psf = 1, CONV_IN_X only) is read with its offsets rolled to the origin
+    struct RawP {
+        R x0, x1, p0, p1;
     };
     row_fft<R, false, LOG2L, row_threads<LOG2L>(), false, fuse_first8<LOG2L>()>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
-        [&](int c, int r) -> cplx<R> {
+        [&](int c, int r) {
             const int i = ig * 2 * C + 2 * c;
-            return cplx<R>{load(i, r), load(i + 1, r)};
+            if constexpr (IN == CONV_IN_CG_P) {
+                RawP raw{R(0), R(0), R(0), R(0)};
+                if (r < ny) {
+                    const size_t pix = ((size_t)b * nx + i) * ny + r;
+                    raw = RawP{x[pix], x[pix + ny], auxp[pix], auxp[pix + ny]};
+                }
+                return raw;
+            } else {
+                cplx<R> raw{R(0), R(0)};
+                if (psf) {
+                    // grid index i holds offset di = i (first half) or i - lx (second half) of
+                    // the PSF; offsets outside [-nx, nx) x [-ny, ny) are zero
+                    const int dj = r < a.ly / 2 ? r : r - a.ly;
+                    if (dj >= -ny && dj < ny) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int di = i + h < a.lx / 2 ? i + h : i + h - a.lx;
+                            if (di >= -nx && di < nx) {
+                                const R v = x[((size_t)b * 2 * nx + di + nx) * 2 * ny + dj + ny];
+                                if (h) raw.im = v;
+                                else raw.re = v;
+                            }
+                        }
+                    }
+                } else if (r < ny) {
+                    const size_t pix = ((size_t)b * nx + i) * ny + r;
+                    raw = cplx<R>{x[pix], x[pix + ny]};
+                }
+                return raw;
+            }
         },
-        [](int, int, const cplx<R> &) {});
+        [&](int c, int r, const auto &raw) -> cplx<R> {
+            if constexpr (IN == CONV_IN_CG_P) {
+                const cplx<R> v{raw.x0 + bscale * raw.p0, raw.x1 + bscale * raw.p1};
+                if (r < ny) {
+                    const size_t pix = ((size_t)b * nx + ig * 2 * C + 2 * c) * ny + r;
+                    auxp[pix] = v.re;
+                    auxp[pix + ny] = v.im;
+                }
+                return v;
+            } else if constexpr (IN == CONV_IN_SCALED) {
+                return raw * bscale;
+            } else {
+                return raw;
+            }
+        },
+        OutNoFetch{}, [](int, int, const cplx<R> &, NoRaw) {});
     // group-major store: frequency k = g CG + cc of row i at (g nrows + i) CG + cc
     cplx<R> *t1 = reinterpret_cast<cplx<R> *>(a.t1c) + (size_t)b * a.lx * a.ldh;
     const int lgc = __builtin_ctz(a.cgc), cmask = a.cgc - 1;
@@ -2445,7 +2496,7 @@ int conv_group_cols(bool dbl, int nx) {
 // X_b; Z = X_a + i X_b transforms to row a in the real part and row b in the
 // imaginary part.  C vectors (2C rows) per block.
 template <typename R, int LOG2L, int OUT>
-__global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a, R *y, const R *aux, R sigma, int C) {
+__global__ __launch_bounds__(row_threads<LOG2L>(), row_min_waves<LOG2L>()) void s3_kernel(ConvArgs a, R *y, const R *aux, R sigma, int C) {
     constexpr int L = 1 << LOG2L;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *const twl = reinterpret_cast<cplx<R> *>(smem_raw);
@@ -2463,33 +2514,44 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), 2) void s3_kernel(ConvArgs a,
     const int lgc = __builtin_ctz(a.cgc), cmask = a.cgc - 1;
     const R scale = R(1) / ((R)a.lx * (R)a.ly);
     double part = 0.0;
+    struct RawS {
+        cplx<R> xa, xb;
+    };
+    constexpr bool READ_AUX = OUT == CONV_OUT_SUB || OUT == CONV_OUT_CG || OUT == CONV_OUT_DOT;
     row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>()>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
-        [&](int c, int k) -> cplx<R> {
+        [&](int c, int k) {
             // group-major load of rows i, i + 1 at frequency kk (Hermitian: k > ny reads L - k)
             const int kk = k <= L / 2 ? k : L - k;
             const size_t o = (((size_t)(kk >> lgc) * nx + ig * 2 * C + 2 * c) << lgc) + (kk & cmask);
-            cplx<R> xa = t1[o], xb = t1[o + a.cgc];
-            if (k > L / 2) {
-                xa = conj(xa);
-                xb = conj(xb);
-            }
+            return RawS{t1[o], t1[o + a.cgc]};
+        },
+        [&](int, int k, const RawS &raw) -> cplx<R> {
+            const cplx<R> xa = k > L / 2 ? conj(raw.xa) : raw.xa, xb = k > L / 2 ? conj(raw.xb) : raw.xb;
             return cplx<R>{xa.re - xb.im, xa.im + xb.re};
         },
-        [&](int c, int j, const cplx<R> &z) {
+        [&](int c, int j) -> cplx<R> {   // the auxiliary image at the two output pixels
+            cplx<R> p{R(0), R(0)};
+            if (READ_AUX && j < ny) {
+                const size_t pix = ((size_t)b * nx + ig * 2 * C + 2 * c) * ny + j;
+                p = cplx<R>{aux[pix], aux[pix + ny]};
+            }
+            return p;
+        },
+        [&](int c, int j, const cplx<R> &z, const cplx<R> &p) {
             if (j >= ny) return;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {   // rows 2c (real part) and 2c + 1 (imaginary part)
                 const size_t pix = ((size_t)b * nx + ig * 2 * C + 2 * c + h) * ny + j;
+                const R pv = h ? p.im : p.re;
                 R v = (h ? z.im : z.re) * scale;
-                if (OUT == CONV_OUT_SUB) v -= aux[pix];
+                if (OUT == CONV_OUT_SUB) v -= pv;
                 if (OUT == CONV_OUT_CG) {
-                    const R pv = aux[pix];
                     v += sigma * pv;
                     part += (double)pv * (double)v;
                 }
                 if (OUT == CONV_OUT_NORM) part += (double)v * (double)v;
-                if (OUT == CONV_OUT_DOT) part += (double)aux[pix] * (double)v;
+                if (OUT == CONV_OUT_DOT) part += (double)pv * (double)v;
                 y[pix] = v;
             }
         });
