@@ -1837,7 +1837,9 @@ template <typename R, int LOG2N, int C> struct WCols {
     static constexpr int ITER = (C * (N / R0) + NT - 1) / NT;   // innermost-stage items per thread
     // the transform buffer, the twiddle tables and two per-thread arrays of 8 values
     // that live across the plane loop (kept in LDS, not in registers)
-    static constexpr size_t other = (size_t)C * Lds<R, LOG2N>::ld * sizeof(cplx<R>) + 2 * 8 * (size_t)NT * sizeof(R);
+    // plus two buffers of a plane's tile-row flags (at most gx / 8 = N / 4 tile rows)
+    static constexpr size_t other =
+        (size_t)C * Lds<R, LOG2N>::ld * sizeof(cplx<R>) + 2 * 8 * (size_t)NT * sizeof(R) + 2 * (size_t)(N / 4);
     static constexpr int SE = tw_stage_entries<R, LOG2N>(other);
     static constexpr size_t lds = other + (kTwEntries + SE) * sizeof(cplx<R>);
 };
@@ -1913,10 +1915,16 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wgrid_cols_kernel(Xf
                                                                                     : R(0);
         }
     }
+    uint8_t *const flb = reinterpret_cast<uint8_t *>(accl + 8 * NT);   // two buffers of ntx flags
     for (int j = 0; j < nw; ++j) {
+        // the plane's tile-row flags go to LDS, so that the row loads do not wait on flag loads
         const uint8_t *orow = a.occ_row + ((size_t)b * a.g.nwmax + j) * a.g.ntx;
+        uint8_t *const fl = flb + (j & 1) * (N / 4);
         int any = 0;
-        for (int k = threadIdx.x; k < a.g.ntx; k += NT) any |= orow[k];
+        for (int k = threadIdx.x; k < a.g.ntx; k += NT) {
+            fl[k] = orow[k];
+            any |= orow[k];
+        }
         if (!__syncthreads_or(any)) continue;   // (also orders the twiddle table and the last plane's LDS reads)
         const cplx<R> *T = reinterpret_cast<const cplx<R> *>(a.t1) +
                            (((size_t)wb.bb * a.g.nwmax + j) * G + wb.g) * (size_t)gx * CG + wb.sub * C;
@@ -1928,14 +1936,17 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wgrid_cols_kernel(Xf
             if (own) {
                 cplx<R> v[8];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
+                for (int t = 0; t < 8; ++t) {   // all loads first
                     const int u = 2 * (jr + t * M) + p;
-                    cplx<R> x{R(0), R(0)};
-                    if (orow[u >> lgT]) {
-                        x = T[(size_t)u * CG + c];
-                        if (!qs) x = x * twiddle<R, false>(tt, ((u * hx) & (gx - 1)) << shg);
+                    v[t] = cplx<R>{R(0), R(0)};
+                    if (fl[u >> lgT]) v[t] = T[(size_t)u * CG + c];
+                }
+                if (!qs) {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int u = 2 * (jr + t * M) + p;
+                        v[t] = v[t] * twiddle<R, false>(tt, ((u * hx) & (gx - 1)) << shg);
                     }
-                    v[t] = x;
                 }
                 dft_small<R, true, 8>(v);
                 stage_twiddles<R, true, 8>(v, tt, jr << shn);
@@ -1989,22 +2000,30 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wgrid_cols_kernel(Xf
         }
     }
     R *img = reinterpret_cast<R *>(a.image_out) + (size_t)b * nx * ny;
+    const R *corr2d = reinterpret_cast<const R *>(a.corr2d);
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int id = threadIdx.x + it * NT;
         const int cc = id / (N / R0), gq = id - cc * (N / R0);
         const int col = col0 + cc;
         if (id >= C * (N / R0) || col >= ny) continue;
+        // the correction factors' loads first (corr2d, or corr_x[i] times corr_y[col])
+        R cf[R0];
+        const R cy = corr2d ? R(1) : reinterpret_cast<const R *>(a.corr_y)[col];
+#pragma unroll
+        for (int t = 0; t < R0; ++t) {
+            const int i = dit_inv<LOG2N>(gq * R0 + t) ^ hs;
+            cf[t] = R(0);
+            if (i < nx)
+                cf[t] = corr2d ? corr2d[(size_t)b * nx * ny + (size_t)i * ny + col] : reinterpret_cast<const R *>(a.corr_x)[i];
+        }
 #pragma unroll
         for (int t = 0; t < R0; ++t) {
             const int i = dit_inv<LOG2N>(gq * R0 + t) ^ hs;
             if (i >= nx) continue;
-            const size_t pix = (size_t)i * ny + col;
-            const R cr = a.corr2d ? reinterpret_cast<const R *>(a.corr2d)[(size_t)b * nx * ny + pix]
-                                  : reinterpret_cast<const R *>(a.corr_x)[i] * reinterpret_cast<const R *>(a.corr_y)[col];
-            R v = accl[(it * R0 + t) * NT + threadIdx.x] * cr;
+            R v = accl[(it * R0 + t) * NT + threadIdx.x] * (cf[t] * cy);
             if (a.zero_edge && (i == 0 || col == 0)) v = R(0);
-            img[pix] = v;
+            img[(size_t)i * ny + col] = v;
         }
     }
 }
@@ -2045,25 +2064,42 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wdegrid_cols_kernel(
     R *const xrl = reinterpret_cast<R *>(buf + C * ld);
     R *const svl = xrl + 8 * NT;
     const R sc = (R)bd.sc;
+    {
+        // loads first: image values and correction factors (corr2d, or corr_x[i] times corr_y[col])
+        const R *corr2d = reinterpret_cast<const R *>(a.corr2d);
+        const bool colok = own && col < ny;
+        const R cy = (corr2d || !colok) ? R(1) : reinterpret_cast<const R *>(a.corr_y)[col];
+        R xs[8], cf[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const int i = (jr + t * M) ^ hs;
-        R xv = R(0), s = R(0);
-        if (own && i < nx && col < ny) {
-            const size_t pix = (size_t)i * ny + col;
-            const R x = reinterpret_cast<const R *>(a.image_in)[(size_t)b * nx * ny + pix];
-            const R cr = a.corr2d ? reinterpret_cast<const R *>(a.corr2d)[(size_t)b * nx * ny + pix]
-                                  : reinterpret_cast<const R *>(a.corr_x)[i] * reinterpret_cast<const R *>(a.corr_y)[col];
-            xv = x * cr;
-            if (!a.g.flat) s = pixel_sm1<R>(i, col, a.g) - sc;
+        for (int t = 0; t < 8; ++t) {
+            const int i = (jr + t * M) ^ hs;
+            xs[t] = cf[t] = R(0);
+            if (colok && i < nx) {
+                const size_t pix = (size_t)b * nx * ny + (size_t)i * ny + col;
+                xs[t] = reinterpret_cast<const R *>(a.image_in)[pix];
+                cf[t] = corr2d ? corr2d[pix] : reinterpret_cast<const R *>(a.corr_x)[i];
+            }
         }
-        xrl[t * NT + threadIdx.x] = xv;
-        svl[t * NT + threadIdx.x] = s;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int i = (jr + t * M) ^ hs;
+            R s = R(0);
+            if (colok && i < nx && !a.g.flat) s = pixel_sm1<R>(i, col, a.g) - sc;
+            xrl[t * NT + threadIdx.x] = xs[t] * (cf[t] * cy);
+            svl[t * NT + threadIdx.x] = s;
+        }
     }
+    uint8_t *const flb = reinterpret_cast<uint8_t *>(svl + 8 * NT);   // two buffers of ntx flags
     for (int j = 0; j < nw; ++j) {
+        // the plane's tile-row flags go to LDS (two buffers: the last plane's stores may
+        // still read the other), so that the stores do not wait on flag loads
         const uint8_t *nrow = a.need_row + ((size_t)b * a.g.nwmax + j) * a.g.ntx;
+        uint8_t *const fl = flb + (j & 1) * (N / 4);
         int any = 0;
-        for (int k = threadIdx.x; k < a.g.ntx; k += NT) any |= nrow[k];
+        for (int k = threadIdx.x; k < a.g.ntx; k += NT) {
+            fl[k] = nrow[k];
+            any |= nrow[k];
+        }
         if (!__syncthreads_or(any)) continue;   // (also orders the twiddle table and the last plane's LDS reads)
         cplx<R> *T = reinterpret_cast<cplx<R> *>(a.t1) +
                      (((size_t)wb.bb * a.g.nwmax + j) * G + wb.g) * (size_t)gx * CG + wb.sub * C;
@@ -2119,7 +2155,7 @@ __global__ __launch_bounds__((WCols<R, LOG2N, C>::NT)) void wdegrid_cols_kernel(
 #pragma unroll
                 for (int t = 0; t < R0; ++t) {
                     const int u = 2 * dit_inv<LOG2N>(gq * R0 + t) + p;
-                    if (nrow[u >> lgT])
+                    if (fl[u >> lgT])
                         T[(size_t)u * CG + cc] = qs ? v[t] : v[t] * twiddle<R, true>(tt, ((u * hx) & (gx - 1)) << shg);
                 }
             }
