@@ -1477,13 +1477,32 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
     const int gx = a.g.gx, gy = a.g.gy;
     const int ox = tu * T - H, oy = tv * T - H;
 
-    auto load_plane = [&](int p, int slot) {
-        const cplx<R> *P = pbase + (size_t)p * plane_sz;
-        cplx<R> *dst = ring + slot * SS;
-        for (int k = threadIdx.x; k < E * E; k += NT) {
-            const int aa = k / E, cc = k - aa * E;
-            const int gi = wrapi(ox + aa, gx), gj = wrapi(oy + cc, gy);
-            dst[aa * S + cc] = P[(size_t)gi * gy + gj];
+    // value k of the E x E footprint of plane p (row k / E, column k mod E, wrapped)
+    auto fetch = [&](int p, int k) {
+        const int aa = k / E, cc = k - aa * E;
+        return pbase[(size_t)p * plane_sz + (size_t)wrapi(ox + aa, gx) * gy + wrapi(oy + cc, gy)];
+    };
+    auto put = [&](int p, int k, const cplx<R> &v) {
+        const int aa = k / E;
+        ring[(p % WW) * SS + aa * S + k - aa * E] = v;
+    };
+    // the footprints of planes pa .. pb - 1 into their ring slots, eight loads per
+    // thread in flight before their LDS writes
+    auto load_planes = [&](int pa, int pb) {
+        const int per = E * E, total = (pb - pa) * per;
+        constexpr int U = 8;
+        for (int k0 = threadIdx.x; k0 < total; k0 += U * NT) {
+            cplx<R> v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + u * NT, pl = k / per;
+                if (k < total) v[u] = fetch(pa + pl, k - pl * per);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + u * NT, pl = k / per;
+                if (k < total) put(pa + pl, k - pl * per, v[u]);
+            }
         }
     };
     if (threadIdx.x < kInterp4Pad) ring[WW * SS + threadIdx.x] = cplx<R>{R(0), R(0)};
@@ -1492,9 +1511,12 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
             const int r = k / kInterp4ColPad, c = k - r * kInterp4ColPad;
             ring[r * S + E + c] = cplx<R>{R(0), R(0)};
         }
-    for (int k = 0; k < WW; ++k)
-        if (wk.q0 + k < (FLAT ? 1 : bd.nw)) load_plane(wk.q0 + k, (wk.q0 + k) % WW);
+    load_planes(wk.q0, min(wk.q0 + WW, FLAT ? 1 : bd.nw));
     __syncthreads();
+    // the plane that replaces plane q in the ring is loaded into registers before
+    // q's entries are processed (footprints of up to kPre NT values)
+    constexpr int kPre = 2;
+    const bool pre_ok = E * E <= kPre * NT;
 
     const int lq = threadIdx.x & 3;
     const int grp = threadIdx.x >> 2;
@@ -1508,6 +1530,15 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
     R vmre = R(0), vmim = R(0);
     bool vbad = false;
     for (int q = wk.q0; q <= wk.q1; ++q) {
+        const bool refill = !FLAT && q < wk.q1 && q + W < bd.nw;
+        cplx<R> pre[kPre];
+        if (refill && pre_ok) {
+#pragma unroll
+            for (int u = 0; u < kPre; ++u) {
+                const int k = threadIdx.x + u * NT;
+                if (k < E * E) pre[u] = fetch(q + W, k);
+            }
+        }
         const int64_t lo = max((int64_t)wk.e0, a.hoffsets[keybase + q]);
         const int64_t hi = min((int64_t)wk.e1, a.hoffsets[keybase + q + 1]);
         const int64_t n = max(hi - lo, (int64_t)0);
@@ -1515,17 +1546,30 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
         int64_t h = lo + grp;
         int64_t e_n = 0, e_nn = 0;
         Rec<R> rec_n{R(0), R(0), R(0), 0u};
+        // the stored phase of the next entry (degridding with stored phases), loaded with its record
+        constexpr bool PH = OMODE != 1 && !FLAT;
+        const cplx<R> *phs = reinterpret_cast<const cplx<R> *>(a.phase);
+        cplx<R> ph_n{R(1), R(0)};
+        R om_n = R(0);   // the weight of the next entry (OMODE 1)
+        // the loads of the next two entries run ahead of this one's arithmetic; their
+        // indices are clamped to the last entry instead of tested, so that no branch
+        // joins a load's value before it is used (that would wait for every load in flight)
         if (h < e_end) {
             e_n = a.hidx[h];
             rec_n = recs[e_n];
+            if (PH && a.use_phase) ph_n = phs[e_n];
+            if (OMODE == 1) om_n = omega[e_n];
+            e_nn = a.hidx[min(h + NGRP, e_end - 1)];
         }
-        if (h + NGRP < e_end) e_nn = a.hidx[h + NGRP];
         for (; h < e_end; h += NGRP) {
-            const int64_t e = e_n;
             const Rec<R> rec = rec_n;
+            const cplx<R> ph = ph_n;
+            const R om = om_n;
             e_n = e_nn;
-            if (h + NGRP < e_end) rec_n = recs[e_n];
-            e_nn = h + 2 * NGRP < e_end ? (int64_t)a.hidx[h + 2 * NGRP] : 0;
+            rec_n = recs[e_n];
+            if (PH && a.use_phase) ph_n = phs[e_n];
+            if (OMODE == 1) om_n = omega[e_n];
+            e_nn = a.hidx[min(h + 2 * NGRP, e_end - 1)];
             const int i0 = (int)dev_floor(rec.fu - hw) + 1;
             const int j0 = (int)dev_floor(rec.fv - hw) + 1;
             const R pv0 = es_kernel_fast(R(j0 + lq) - rec.fv, beta2, inv_hw);
@@ -1569,13 +1613,11 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
                 const uint32_t vid = rec.idx & ~kHomeBit;
                 if (OMODE != 1) {
                     cplx<R> out = acc;
-                    if (!FLAT)
-                        out = out * conj(a.use_phase ? reinterpret_cast<const cplx<R> *>(a.phase)[e]
-                                                     : cis_cycles<R>((w0 + rec.fw * dw) * sc));
+                    if (!FLAT) out = out * conj(a.use_phase ? ph : cis_cycles<R>((w0 + rec.fw * dw) * sc));
                     cplx<R> *ov = reinterpret_cast<cplx<R> *>(a.out) + vid;
                     *ov = OMODE == 2 ? *ov + out : out;
                 } else {
-                    const cplx<R> o = acc * omega[e];
+                    const cplx<R> o = acc * om;
                     reinterpret_cast<cplx<R> *>(a.out)[h] = o;   // home-list order
                     vmre = max(vmre, fabsf(o.re));
                     vmim = max(vmim, fabsf(o.im));
@@ -1584,8 +1626,16 @@ __global__ __launch_bounds__(kTileThreads) void interp4_kernel(InterpLaunch a) {
             }
         }
         __syncthreads();
-        if (!FLAT && q < wk.q1 && q + W < bd.nw) {
-            load_plane(q + W, q % W);
+        if (refill) {
+            if (pre_ok) {
+#pragma unroll
+                for (int u = 0; u < kPre; ++u) {
+                    const int k = threadIdx.x + u * NT;
+                    if (k < E * E) put(q + W, k, pre[u]);
+                }
+            } else {
+                load_planes(q + W, q + W + 1);
+            }
         }
         __syncthreads();
     }
