@@ -938,25 +938,38 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
         bq = kDone;
         be = bend = 0;
     };
-    auto load_rec = [&](int64_t ei, int64_t bend) {
-        Rec<R_> rr{R_(0), R_(0), R_(0), 0u};
-        if (ei < bend) rr = recs[ei];
-        return rr;
+    // Loads of lanes past a batch's end read its last entry instead (or entry 0 when
+    // the stream is done; the work item has entries): no branch joins a loaded value
+    // before its use, which would wait for every load in flight.  Those lanes' slots
+    // never reach the matrix products.
+    auto clampi = [](int64_t ei, int64_t bend) { return ei < bend ? ei : (bend > 0 ? bend - 1 : (int64_t)0); };
+    auto load_rec = [&](int64_t ei, int64_t bend) { return recs[clampi(ei, bend)]; };
+    // the value's loads (VMODE 2: through the entry's home position, loaded with its record)
+    struct RawVal {
+        cplx<R_> z, ph;
+        R_ om;
     };
-    auto load_val = [&](int64_t ei, int64_t bend, const Rec<R_> &rr) {
-        cplx<R_> v{R_(0), R_(0)};
-        if (ei < bend) {
-            if (VMODE == 0) {
-                v = vis[rr.idx & ~kHomeBit] * phase[ei] * (omega[ei] * fscale);
-            } else if (VMODE == 1) {
-                v = cplx<R_>{omega[ei] * fscale, R_(0)};
-            } else {
-                v = vis[a.home_pos[ei]] * fscale;
-            }
+    auto load_val = [&](int64_t ei, int64_t bend, const Rec<R_> &rr, uint32_t hp) {
+        const int64_t ec = clampi(ei, bend);
+        RawVal raw{{R_(0), R_(0)}, {R_(1), R_(0)}, R_(1)};
+        if (VMODE == 0) {
+            raw.z = vis[rr.idx & ~kHomeBit];
+            raw.ph = phase[ec];
+            raw.om = omega[ec];
+        } else if (VMODE == 1) {
+            raw.om = omega[ec];
+        } else {
+            raw.z = vis[hp];
         }
-        return v;
+        return raw;
     };
-    // batch a: records and values loaded; batch b: records loaded
+    auto make_val = [&](const RawVal &raw) {
+        if (VMODE == 0) return raw.z * raw.ph * (raw.om * fscale);
+        if (VMODE == 1) return cplx<R_>{raw.om * fscale, R_(0)};
+        return raw.z * fscale;
+    };
+    auto load_hp = [&](int64_t ei, int64_t bend) { return VMODE == 2 ? a.home_pos[clampi(ei, bend)] : 0u; };
+    // batch a: records and values loaded; batch b: records (and home positions) loaded
     int qa = qstart - 1, qb;
     int64_t ea = 0, enda = 0, eb, endb;
     next_batch(qa, ea, enda);
@@ -965,8 +978,9 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
     endb = enda;
     next_batch(qb, eb, endb);
     Rec<R_> rec_c = load_rec(ea + lane, enda);
-    cplx<R_> val_c = load_val(ea + lane, enda, rec_c);
+    RawVal val_c = load_val(ea + lane, enda, rec_c, load_hp(ea + lane, enda));
     Rec<R_> rec_n = load_rec(eb + lane, endb);
+    uint32_t hp_n = load_hp(eb + lane, endb);
     unsigned live = 0;    // bit k: base plane q - k has entries in this bucket (planes q - W + 1 .. q)
 
     for (int q = qstart; q < wk.p1; ++q) {
@@ -1033,8 +1047,10 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                 int qc = qb;
                 int64_t ec = eb, endc = endb;
                 next_batch(qc, ec, endc);
-                const cplx<R_> val_n = load_val(eb + lane, endb, rec_n);
+                const RawVal val_n = load_val(eb + lane, endb, rec_n, hp_n);
                 const Rec<R_> rec_nn = load_rec(ec + lane, endc);
+                const uint32_t hp_nn = load_hp(ec + lane, endc);
+                const cplx<R_> zc = make_val(val_c);
                 const int nbatch = (int)min((int64_t)64, enda - ea);
                 // owner lane: window of its entry and the offsets of the window origin
                 int okey;
@@ -1052,7 +1068,7 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                 // one before its matrix products, so the crossbar latency overlaps them
                 const int own0 = sg * 4;                // byte address of the owner lane
                 R_ du = bperm_f(own0, odu), dv = bperm_f(own0, odv), dq = bperm_f(own0, odq);
-                R_ zr = bperm_f(own0, val_c.re), zi = bperm_f(own0, val_c.im);
+                R_ zr = bperm_f(own0, zc.re), zi = bperm_f(own0, zc.im);
                 int key = __builtin_amdgcn_ds_bpermute(own0, okey);
 #pragma unroll 1
                 for (int g4 = 0; g4 < nbatch; g4 += 4) {
@@ -1086,8 +1102,8 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                         du = bperm_f(own, odu);
                         dv = bperm_f(own, odv);
                         dq = bperm_f(own, odq);
-                        zr = bperm_f(own, val_c.re);
-                        zi = bperm_f(own, val_c.im);
+                        zr = bperm_f(own, zc.re);
+                        zi = bperm_f(own, zc.im);
                         key = __builtin_amdgcn_ds_bpermute(own, okey);
                     }
                     __builtin_amdgcn_s_setprio(0);
@@ -1131,6 +1147,7 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(SpreadLaunch 
                 rec_c = rec_n;
                 val_c = val_n;
                 rec_n = rec_nn;
+                hp_n = hp_nn;
                 qa = qb;
                 ea = eb;
                 enda = endb;
