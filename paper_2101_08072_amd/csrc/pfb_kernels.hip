@@ -1188,27 +1188,59 @@ __global__ __launch_bounds__(kThreads) void absmax_blocks_kernel(int vmode, cons
     __shared__ float red[kThreads / 64];
     // per entry |w z| <= w hypot(|Re z|, |Im z|), the hypot formed without squaring
     // in FP32 (max * sqrt(1 + (min / max)^2)); a NaN or infinite weight, value or
-    // product makes the bound infinite.  Every load is issued whatever the weight
-    // and flag, so that loads of later iterations overlap.
+    // product makes the bound infinite.  U entries per thread at a time: all their
+    // loads (indices clamped, not tested; the flag and value reads fixed per
+    // instantiation) before any use, so that they are in flight together.
     float m = 0.f;
     bool bad = false;
-#pragma unroll 4
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
-        const float w = weight[e];
-        const bool on = w > 0.f && !(flag && flag[e]);
-        float v = w;
-        if (vmode != 1) {
-            const cplx<float> z = vis[e];
-            const float ar = fabsf(z.re), ai = fabsf(z.im);
-            const float hi = fmaxf(ar, ai), lo = fminf(ar, ai);
-            const float t = hi > 0.f ? lo / hi : 0.f;
-            v = hi * sqrtf(1.f + t * t) * (vmode == 0 ? w : 1.f);
-            if (on) bad = bad || not_finite(z.re) || not_finite(z.im);
+    auto run = [&](auto HASF, auto VM) {
+        constexpr bool HF = decltype(HASF)::value;
+        constexpr int VMODE = decltype(VM)::value;
+        constexpr int U = 4;
+        const int64_t stride = (int64_t)gridDim.x * kThreads;
+        for (int64_t e0 = (int64_t)blockIdx.x * kThreads + threadIdx.x; e0 < n; e0 += U * stride) {
+            float w[U];
+            uint8_t f[U];
+            cplx<float> z[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t e = min(e0 + u * stride, n - 1);
+                w[u] = weight[e];
+                f[u] = HF ? flag[e] : 0;
+                if (VMODE != 1) z[u] = vis[e];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                // (past the end: off, not a branch, which would let the compiler sink the loads)
+                const bool on = e0 + u * stride < n && w[u] > 0.f && !f[u];
+                float v = w[u];
+                if (VMODE != 1) {
+                    const float ar = fabsf(z[u].re), ai = fabsf(z[u].im);
+                    const float hi = fmaxf(ar, ai), lo = fminf(ar, ai);
+                    const float t = hi > 0.f ? lo / hi : 0.f;
+                    v = hi * sqrtf(1.f + t * t) * (VMODE == 0 ? w[u] : 1.f);
+                    if (on) bad = bad || not_finite(z[u].re) || not_finite(z[u].im);
+                }
+                if (on) {
+                    m = fmaxf(m, v);
+                    bad = bad || not_finite(v);
+                }
+            }
         }
-        if (on) {
-            m = fmaxf(m, v);
-            bad = bad || not_finite(v);
-        }
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    using V0 = std::integral_constant<int, 0>;
+    using V1 = std::integral_constant<int, 1>;
+    using V2 = std::integral_constant<int, 2>;
+    if (flag) {
+        if (vmode == 0) run(T_{}, V0{});
+        else if (vmode == 1) run(T_{}, V1{});
+        else run(T_{}, V2{});
+    } else {
+        if (vmode == 0) run(F_{}, V0{});
+        else if (vmode == 1) run(F_{}, V1{});
+        else run(F_{}, V2{});
     }
     if (bad) m = INFINITY;
     for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
