@@ -2574,6 +2574,13 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
             const int id = threadIdx.x + it * NT;
             if (!HEXACT && id >= C * (N / R0)) continue;
             const int cc = id / (N / R0), gq = id - cc * (N / R0);
+            // (without the early loads: this item's spectrum values are loaded first, then
+            // the LDS reads and the DFT cover part of their latency)
+            R hl[R0];
+            if (!PSF && !PREH) {
+#pragma unroll
+                for (int t = 0; t < R0; ++t) hl[t] = H[(p * N + dit_inv<LOG2N>(gq * R0 + t)) * CG + cc];
+            }
             cplx<R> *vb = buf + cc * ld + LD::pad(gq * R0);
             cplx<R> v[R0];
 #pragma unroll
@@ -2583,7 +2590,7 @@ __global__ __launch_bounds__((ConvCols<R, LOG2N, C>::NT)) void conv_cols_kernel(
             for (int t = 0; t < R0; ++t) {
                 const int k = dit_inv<LOG2N>(gq * R0 + t);
                 if (PSF) H[(p * N + k) * CG + cc] = v[t].re;
-                else v[t] = v[t] * (PREH ? hv[it * R0 + t] : H[(p * N + k) * CG + cc]);
+                else v[t] = v[t] * (PREH ? hv[it * R0 + t] : hl[t]);
             }
             if (!PSF) {
                 dft_small<R, true, R0>(v);
