@@ -364,7 +364,7 @@ struct OutNoFetch {
 };
 // items per thread whose loads are in flight together in the unfused input and
 // output loops: eight, or four in 1024-thread blocks (two of them per CU leave 64
-// registers per lane)
+// registers per lane); a caller may ask for another input batch (UIN)
 template <class Raw, int NT> constexpr int io_batch() { return NT >= 1024 ? 4 : 8; }
 
 // FFT of C vectors of length 2^LOG2L (2^5 .. 2^14) whose first stage reads its
@@ -448,7 +448,8 @@ __device__ __forceinline__ void lds_fft_io(cplx<R> *buf, int C, int ld, const Tw
 // input scattered to its DIT position, lds_fft, and (STORE_REGS) every output
 // read back from LDS.  The fused first stage measured slower where it starts with
 // radix 2 or 4.
-template <typename R, bool INV, int LOG2L, int NT, bool STORE_REGS, bool FUSE, class FIn, class MIn, class FOut, class POut>
+template <typename R, bool INV, int LOG2L, int NT, bool STORE_REGS, bool FUSE, int UIN = 0, class FIn, class MIn,
+          class FOut, class POut>
 __device__ __forceinline__ void row_fft(cplx<R> *buf, int C, int ld, const TwTab<R> &tw, int tw_shift, FIn fetch_in,
                                         MIn make_in, FOut fetch_out, POut put_out) {
     if constexpr (FUSE) {
@@ -456,7 +457,7 @@ __device__ __forceinline__ void row_fft(cplx<R> *buf, int C, int ld, const TwTab
     } else {
         constexpr int L = 1 << LOG2L;
         using Raw = decltype(fetch_in(0, 0));
-        constexpr int U = io_batch<Raw, NT>();
+        constexpr int U = UIN ? UIN : io_batch<Raw, NT>();
         constexpr bool EXACT = L % (U * NT) == 0;
         for (int id0 = threadIdx.x; id0 < C * L; id0 += U * NT) {
             Raw raw[U];

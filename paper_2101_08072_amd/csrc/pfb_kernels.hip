@@ -1855,7 +1855,7 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), row_min_waves<LOG2L>()) void 
     __syncthreads();
     const int ny = a.g.ny;
     // output k of the row DFT is cropped column iy = k + ny / 2 (mod L), kept if iy < ny
-    row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>()>(
+    row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>(), 8>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
         [&](int c, int r) -> cplx<R> {
             cplx<R> v{R(0), R(0)};
