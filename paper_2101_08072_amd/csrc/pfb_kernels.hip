@@ -2683,7 +2683,8 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), row_min_waves<LOG2L>()) void 
         cplx<R> xa, xb;
     };
     constexpr bool READ_AUX = OUT == CONV_OUT_SUB || OUT == CONV_OUT_CG || OUT == CONV_OUT_DOT;
-    row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>()>(
+    // eight inputs per thread in flight where that fits the register budget (up to 8192 points)
+    row_fft<R, true, LOG2L, row_threads<LOG2L>(), true, fuse_first8<LOG2L>(), (LOG2L <= 13 ? 8 : 0)>(
         buf, C, ld, tt, a.log2_lmax - LOG2L,
         [&](int c, int k) {
             // group-major load of rows i, i + 1 at frequency kk (Hermitian: k > ny reads L - k)
