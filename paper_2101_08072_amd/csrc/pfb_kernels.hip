@@ -1824,6 +1824,15 @@ template <typename R> __device__ __forceinline__ size_t plane_at(const XformArgs
 }
 int plane_group_cols(bool dbl) { return dbl ? plane_cg<double>() : plane_cg<float>(); }
 
+// Blocks go to the eight XCDs in turn (block i on XCD i mod 8).  For a grid that
+// is a multiple of 8 this returns the logical block of block i such that each XCD
+// runs one contiguous range of logical blocks: neighbouring rows of the row
+// passes then share an XCD and their partial cache lines of the group-major
+// layout meet in its L2.
+__device__ __forceinline__ int xcd_block(int i, int n) {
+    return (n & 7) ? i : (i & 7) * (n >> 3) + (i >> 3);
+}
+
 // G1: inverse row DFT of every plane row, keeping the ny cropped outputs.
 template <typename R, int LOG2L>
 __global__ __launch_bounds__(row_threads<LOG2L>(), row_min_waves<LOG2L>()) void g1_rows_kernel(XformArgs a, int C) {
@@ -1837,10 +1846,11 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), row_min_waves<LOG2L>()) void 
     const int gx = a.g.gx;
     // block: C consecutive rows of a listed tile row (one that holds occupied tiles)
     const int per = a.g.T / C;
-    const int e = a.occ_list[blockIdx.x / per];   // (band nwmax + plane) ntx + tile row
+    const int lb = xcd_block(blockIdx.x, gridDim.x);   // rows of a tile row on one XCD
+    const int e = a.occ_list[lb / per];   // (band nwmax + plane) ntx + tile row
     const int pj = e / a.g.ntx;
     const int j = pj % a.g.nwmax, bb = pj / a.g.nwmax - a.band0;
-    const int row0 = (e - pj * a.g.ntx) * a.g.T + (blockIdx.x % per) * C;
+    const int row0 = (e - pj * a.g.ntx) * a.g.T + (lb % per) * C;
     const size_t plane = (size_t)bb * a.g.nwmax + j;
     const cplx<R> *src = reinterpret_cast<const cplx<R> *>(a.planes) + (plane * gx + (size_t)row0) * L;
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.t1);
@@ -1883,10 +1893,11 @@ __global__ __launch_bounds__(row_threads<LOG2L>(), row_min_waves<LOG2L>()) void 
     const int gx = a.g.gx, ny = a.g.ny;
     // block: C consecutive rows of a listed tile row (one with tiles the interpolation reads)
     const int per = a.g.T / C;
-    const int e = a.need_list[blockIdx.x / per];   // (band nwmax + plane) ntx + tile row
+    const int lb = xcd_block(blockIdx.x, gridDim.x);   // rows of a tile row on one XCD
+    const int e = a.need_list[lb / per];   // (band nwmax + plane) ntx + tile row
     const int pj = e / a.g.ntx;
     const int j = pj % a.g.nwmax, bb = pj / a.g.nwmax - a.band0;
-    const int row0 = (e - pj * a.g.ntx) * a.g.T + (blockIdx.x % per) * C;
+    const int row0 = (e - pj * a.g.ntx) * a.g.T + (lb % per) * C;
     const size_t plane = (size_t)bb * a.g.nwmax + j;
     const cplx<R> *src = reinterpret_cast<const cplx<R> *>(a.t1);
     cplx<R> *dst = reinterpret_cast<cplx<R> *>(a.planes) + (plane * gx + (size_t)row0) * L;
@@ -2323,14 +2334,6 @@ hipError_t launch_degrid_xform(bool dbl, const XformArgs &a, hipStream_t s) {
 // PSF convolution on the 2nx x 2ny zero-padded grid
 // ---------------------------------------------------------------------------
 
-// Blocks go to the eight XCDs in turn (block i on XCD i mod 8).  For a grid that
-// is a multiple of 8 this returns the logical block of block i such that each XCD
-// runs one contiguous range of logical blocks: neighbouring rows of the row
-// passes then share an XCD and their partial cache lines of the group-major
-// layout meet in its L2.
-__device__ __forceinline__ int xcd_block(int i, int n) {
-    return (n & 7) ? i : (i & 7) * (n >> 3) + (i >> 3);
-}
 
 // Offset (in complex values, within a band's lx ldh area of t1c) of the column
 // pass's output in image mode: the upper half, free since nx <= lx / 2.
