@@ -1747,8 +1747,18 @@ hipError_t launch_interp(bool dbl, const InterpLaunch &a, hipStream_t s) {
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void zero_flagged_kernel(const uint32_t *idx, int64_t n, cplx<R> *vis) {
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads)
-        vis[idx[e]] = cplx<R>{R(0), R(0)};
+    // four indices per thread loaded before their stores; past the end the index is
+    // clamped to the last flagged entry, which is then zeroed once more (no branch
+    // for the compiler to sink a load into)
+    constexpr int U = 4;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e0 = (int64_t)blockIdx.x * kThreads + threadIdx.x; e0 < n; e0 += U * stride) {
+        uint32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = idx[min(e0 + u * stride, n - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) vis[v[u]] = cplx<R>{R(0), R(0)};
+    }
 }
 hipError_t launch_zero_flagged(bool dbl, const uint32_t *flagged, int64_t n, void *vis, hipStream_t s) {
     if (n <= 0) return hipSuccess;
