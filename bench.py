@@ -110,8 +110,11 @@ def kernel_models(info, prob, M, W, csz, rsz):
 
 
 def kernel_source_sha():
-    src = os.path.join(ROOT, "paper_2101_08072_amd", "csrc", "pfb_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    # the kernels and the device headers they are built from
+    h = hashlib.sha256()
+    for name in ("pfb_kernels.hip", "pfb_device.h", "pfb_kernels.h"):
+        h.update(open(os.path.join(ROOT, "paper_2101_08072_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def copy_calibration(mib):
